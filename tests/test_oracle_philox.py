@@ -1,0 +1,56 @@
+"""Pins of the counter-based generator behind the random search (section 3.1
+draws uniform offsets; Philox4x32-10 of Salmon et al., SC 2011, makes them a
+pure function of pixel, level, step and field).  No published answer vectors
+are in this repository, so the pins are statistical and structural; the GPU
+library carries its own implementation and the parity tests compare the two."""
+import numpy as np
+
+from oracle import ffo
+
+
+def test_deterministic_and_key_sensitive():
+    a = ffo.philox([1, 2, 3, 4], [5, 6])
+    b = ffo.philox([1, 2, 3, 4], [5, 6])
+    c = ffo.philox([1, 2, 3, 4], [5, 7])
+    assert np.array_equal(a, b)
+    assert not np.array_equal(a, c)
+
+
+def _draws(n, key=(12345, 678)):
+    return np.array([ffo.philox([i, 3, 1, 2], key) for i in range(n)], np.uint64)
+
+
+def test_distinct_outputs_for_distinct_counters():
+    u = _draws(20000)
+    packed = (u[:, 0] << np.uint64(32)) | u[:, 1]
+    assert len(np.unique(packed)) == len(packed)
+
+
+def test_avalanche():
+    rng = np.random.default_rng(0)
+    flips = []
+    for _ in range(400):
+        ctr = rng.integers(0, 2 ** 32, 4, dtype=np.uint64)
+        bit = int(rng.integers(0, 128))
+        ctr2 = ctr.copy()
+        ctr2[bit // 32] ^= np.uint64(1 << (bit % 32))
+        a = ffo.philox(ctr, [9, 9]).astype(np.uint64)
+        b = ffo.philox(ctr2, [9, 9]).astype(np.uint64)
+        flips.append(sum(bin(int(x ^ y)).count("1") for x, y in zip(a, b)))
+    m = np.mean(flips)
+    assert 60 < m < 68, m
+
+
+def test_offset_mapping_uniform_chi_square():
+    # offsets d = (u * span) >> 32 - rad, span = 2 rad + 1 (n R Q = 4 at n=1)
+    u = _draws(45000)
+    rad = 4
+    span = 2 * rad + 1
+    d = ((u[:, :2] * np.uint64(span)) >> np.uint64(32)).astype(np.int64) - rad
+    assert d.min() == -rad and d.max() == rad
+    for col in range(2):
+        cnt = np.bincount(d[:, col] + rad, minlength=span)
+        exp = len(d) / span
+        chi2 = ((cnt - exp) ** 2 / exp).sum()
+        # 8 degrees of freedom: P(chi2 > 26.1) = 0.001
+        assert chi2 < 26.1, chi2
