@@ -1,0 +1,180 @@
+/*
+ * ff.h -- C ABI of the MI355X (gfx950) Flow Fields correspondence-field search.
+ *
+ * Method: C. Bailer, B. Taetz, D. Stricker, "Flow Fields: Dense Correspondence
+ * Fields for Highly Accurate Large Displacement Optical Flow Estimation",
+ * ICCV 2015.  Section 3 defines the problem: for every pixel p1 of I1 find the
+ * flow F(p1) = M(p1) - p1 that minimises a patch data term against I2.
+ *
+ * Conventions shared by every call
+ *  - Pointers are DEVICE pointers unless a comment says "host".
+ *  - Every call that takes a stream only enqueues work on it: it never
+ *    allocates, never synchronises and never copies to the host, so it may be
+ *    captured in a HIP graph -- except the first call on a device, which
+ *    uploads the library's constant tables (call ff_init() first when the
+ *    first use is inside a capture).
+ *  - Arguments are validated on the host before anything is enqueued; on an
+ *    error nothing is enqueued and a negative ff_status is returned.
+ *  - Flows are packed int16x2 words: low half dx, high half dy, both in 1/Q
+ *    pixel ("subpel" Q in {1,2,4,8}); FF_EMPTY marks a pixel with no flow.
+ *    Costs are int32 Hamming sums; FF_COST_INF marks "no cost".
+ *  - The library keeps no per-call device state.  Buffers belong to the
+ *    caller; sizes come from the *_bytes / *_init queries below.
+ */
+#ifndef FF_H_
+#define FF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FF_EMPTY ((int32_t)0x80008000u)
+#define FF_COST_INF ((int32_t)0x7fffffff)
+#define FF_MAX_RADII 4
+
+typedef enum {
+  FF_OK = 0,
+  FF_ERR_ARG = -1,        /* null pointer, bad size, bad parameter */
+  FF_ERR_SIZE = -2,       /* image too large for the packed formats */
+  FF_ERR_WORKSPACE = -3,  /* workspace or descriptor buffer too small */
+  FF_ERR_UNSUPPORTED = -4,
+  FF_ERR_HIP = -5,        /* a HIP launch or query failed */
+  FF_ERR_DEVICE = -6      /* a device-side watchdog fired (see ff_read_status) */
+} ff_status;
+
+/* One image: width x height pixels, channels 3 (RGB, uint8) or 1 (gray),
+ * row_stride in bytes (>= width * channels). */
+typedef struct {
+  int32_t width, height, channels, row_stride;
+} ff_image;
+
+/*
+ * Descriptor layout of one image (host struct, filled by ff_desc_init).
+ * The device blob it describes holds, at the byte offsets given:
+ *  - lab:    channels planes of H*W uint8: 8-bit CIELab (section 3.3 computes
+ *            the census data term in CIELab); gray images pass through;
+ *  - smooth: (k+1) levels x channels planes of H*W int16, Q4 fixed point:
+ *            level j is I^n with n = 2^j (section 3.2: area downsampling by
+ *            n, then Lanczos upsampling to full resolution; level 0 = 16 x lab);
+ *  - census: (k+1) levels x subpel^2 phases of H*W uint32: the 3x3 census
+ *            (section 3.3) of I^n with neighbour stride n (the subsampled
+ *            patch of Eq. 3), on I^n shifted by the subpixel phase (a/Q, b/Q)
+ *            with bilinear weights (section 3.1); byte c = channel c;
+ *            plane index = level * Q*Q + b*Q + a;
+ *  - wht:    n_radii blocks of H*W vectors of wht_stride int32: the first 9
+ *            Walsh-Hadamard projections per channel of the patch of radius
+ *            rho (section 3.1; odd extents split into rho and rho+1).
+ */
+typedef struct {
+  int32_t width, height, channels, k, subpel, n_radii;
+  int32_t radii[FF_MAX_RADII];
+  int32_t wht_dims;    /* 9 * channels */
+  int32_t wht_stride;  /* int32 words per WHT vector (32 for RGB, 16 gray) */
+  size_t off_lab, off_smooth, off_census, off_wht;
+  size_t plane_bytes;  /* H*W*4, the census plane pitch */
+  size_t bytes;        /* total device bytes of the blob */
+} ff_desc;
+
+/* Search parameters (section 4 gives the paper's values in brackets). */
+typedef struct {
+  int32_t k;          /* hierarchy levels: coarsest grid step 2^k [3]; <= desc k */
+  int32_t R;          /* random-search radius in px at full resolution [1]; R_n = R n */
+  int32_t leaf;       /* kd-tree leaf size l [8], 1..64 */
+  int32_t n_prop;     /* propagation sweeps per level [4] */
+  int32_t n_rs;       /* random searches per level, after sweeps 1..n_rs [3] */
+  int32_t use_kdtree; /* 1: kd-tree seeds (Eq. 1 / Eq. 4); 0: proposal only */
+  int32_t max_steps;  /* < 0: whole search; else stop after this many steps
+                         (1 seed step, 7 at the coarsest level, 8 per finer
+                         level) and write the current grid -- for inspection */
+  uint32_t field_id;  /* 0..3, part of the random-search counter */
+  uint32_t pair_id;   /* part of the random-search counter */
+  uint32_t reserved;
+  uint64_t seed;      /* Philox key */
+} ff_match_params;
+
+/* Fill the paper's defaults (k=3, R=1, l=8, 4 sweeps, 3 searches). Host. */
+void ff_default_params(ff_match_params* p);
+
+/* Load the constant tables on the current device (idempotent, synchronous).
+ * Returns FF_ERR_HIP if the device cannot be used. */
+ff_status ff_init(void);
+
+/* Host-only: compute the descriptor layout for an image.  radii (host) lists
+ * the patch radii whose WHT vectors are kept (e.g. {8, 6}), 1..15 each.
+ * k in 0..4, subpel in {1,2,4,8}, width*height <= 2^22, width, height <= 8191. */
+ff_status ff_desc_init(ff_desc* d, const ff_image* img, int32_t k, int32_t subpel, const int32_t* radii,
+                       int32_t n_radii);
+
+/* Compute an image's descriptors (Lab8, I^n, census planes, WHT vectors) into
+ * blob (d->bytes device bytes).  pixels: device image as described by img
+ * (the same image that d was initialised with).  Section 3.1-3.3. */
+ff_status ff_compute_descriptors(const ff_desc* d, const ff_image* img, const uint8_t* pixels, void* blob,
+                                 size_t blob_bytes, hipStream_t stream);
+
+/* Workspace bytes for one ff_match_field call (kd-tree, level grids,
+ * propagation progress counters, status word). */
+size_t ff_match_workspace_bytes(const ff_desc* src, const ff_desc* dst, int32_t radius, const ff_match_params* p);
+
+/*
+ * One Flow Field src -> dst with patch radius `radius` (sections 3.1, 3.2):
+ * kd-tree over dst's WHT(radius) vectors, seeds on the 2^k grid re-ranked by
+ * the data term on P^{2^k}_r (Eq. 4), then per level n = 2^k..1 the
+ * alternating propagation sweeps (Eq. 2, four directions) and random
+ * searches (offsets up to R n, subpixel), coarse flows seeding the next
+ * level.  Both descriptors need the same channels, k >= p->k and subpel, and
+ * must hold WHT vectors for `radius` (unless p->use_kdtree == 0).
+ *  proposal: nullable; ceil(H/2^k) x ceil(W/2^k) packed flows (1/Q px), one
+ *            extra seed candidate per coarse grid point, evaluated after the
+ *            kd-tree leaf; FF_EMPTY entries are skipped.
+ *  flow, cost: src H*W outputs (row-major).  With max_steps >= 0 only grid
+ *            points of the level reached hold values; all others are
+ *            FF_EMPTY / FF_COST_INF.
+ */
+ff_status ff_match_field(const ff_desc* src, const void* src_blob, const ff_desc* dst, const void* dst_blob,
+                         int32_t radius, const ff_match_params* p, const int32_t* proposal, int32_t* flow,
+                         int32_t* cost, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * Eq. 5 (section 3.4): two-way forward/backward consistency check.  Keep p iff
+ * the nearest pixel m = round-half-up(p + F(p)) lies in the second image and
+ * for every backward field j, B_j(m) is not empty and
+ * |F(p) + B_j(m)|^2 < eps_q^2 (eps_q = epsilon * Q, in 1/Q px).
+ *  flow_bwd: host array of n_bwd (1..4) device pointers to w2*h2 fields.
+ *  keep: w1*h1 bytes (1 kept, 0 removed); flow_filtered: w1*h1 flows, FF_EMPTY
+ *  where removed.
+ */
+ff_status ff_consistency_filter(const int32_t* flow_fwd, int32_t w1, int32_t h1, const int32_t* const* flow_bwd,
+                                int32_t n_bwd, int32_t w2, int32_t h2, int32_t subpel, int32_t eps_q, uint8_t* keep,
+                                int32_t* flow_filtered, hipStream_t stream);
+
+/*
+ * Inspection: build the kd-tree of section 3.1 alone (the one ff_match_field
+ * builds first): over every pixel of the image's WHT(radius) vectors, split
+ * while a node holds more than `leaf` points, on the dimension of largest
+ * max-min spread (lowest on ties), at the median of (key, pixel index); left
+ * child = first floor(cnt/2).  Outputs in heap order (children 2i+1, 2i+2):
+ * node_dim (-1 = leaf) and node_split, ff_tree_nodes() entries each; perm: the
+ * H*W pixel indices, leaves left to right, ascending inside each leaf.
+ * workspace: ff_match_workspace_bytes() of a field with this dst suffices.
+ */
+int32_t ff_tree_nodes(int32_t n_points, int32_t leaf);
+ff_status ff_build_kdtree(const ff_desc* d, const void* blob, int32_t radius, int32_t leaf, int32_t* node_dim,
+                          int32_t* node_split, int32_t* perm, void* workspace, size_t workspace_bytes,
+                          hipStream_t stream);
+
+/* After the stream has finished: read the device status word a match call
+ * left in its workspace (FF_OK, or FF_ERR_DEVICE if a watchdog fired). */
+ff_status ff_read_status(const void* workspace, int32_t* status_host);
+
+const char* ff_status_string(ff_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FF_H_ */

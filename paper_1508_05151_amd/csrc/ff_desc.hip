@@ -1,0 +1,416 @@
+// Per-image descriptors for the Flow Fields data term and kd-tree keys:
+// 8-bit CIELab, the smoothed full-resolution images I^n, census planes per
+// level and subpixel phase, and WHT patch vectors (sections 3.1-3.3).
+//
+// All kernels are streaming (HBM-bound): one thread per output pixel,
+// row-major planes, coalesced along x.
+#include <math.h>
+
+#include <mutex>
+
+#include "ff_internal.h"
+
+namespace ff {
+
+// ---------------------------------------------------------------- tables
+// Section 3.3 computes the census in CIELab.  The conversion is integer:
+// sRGB decode (IEC 61966-2-1) as a Q16 table, the sRGB->XYZ matrix with each
+// row scaled to sum to exactly 2^14 (white -> (1,1,1), grays keep a = b = 0),
+// the CIE cube-root compression with its linear toe as a Q15 table over Q16
+// inputs.  L8 = round(2.55 L), a8/b8 = round(a/b) + 128, half up, clamped.
+__device__ int32_t g_gamma[256];
+__device__ int32_t g_mat[9];
+__device__ uint16_t g_fcurve[65537];
+// Section 3.2: Lanczos-3 upsampling weights, Q14, per scale n = 2,4,8,16
+// (index log2 n - 1), phase x mod n, tap -3..3 around floor(x/n).
+__constant__ int32_t c_lanczos[4][16][7];
+
+static void host_lab_tables(int32_t* gamma, int32_t* mat, uint16_t* fcurve) {
+  for (int c = 0; c < 256; ++c) {
+    const double v = (double)c / 255.0;
+    double lin;
+    if (v <= 0.04045)
+      lin = v / 12.92;
+    else
+      lin = pow((v + 0.055) / 1.055, 2.4);
+    gamma[c] = (int32_t)floor(lin * 65536.0 + 0.5);
+  }
+  static const double rgb2xyz[9] = {0.4124564, 0.3575761, 0.1804375, 0.2126729, 0.7151522,
+                                    0.0721750, 0.0193339, 0.1191920, 0.9503041};
+  for (int row = 0; row < 3; ++row) {
+    const double* m = rgb2xyz + 3 * row;
+    const double total = m[0] + m[1] + m[2];
+    int largest = 0, acc = 0;
+    for (int j = 0; j < 3; ++j) {
+      mat[3 * row + j] = (int32_t)floor(16384.0 * m[j] / total + 0.5);
+      acc += mat[3 * row + j];
+      if (m[j] > m[largest]) largest = j;
+    }
+    mat[3 * row + largest] += 16384 - acc;
+  }
+  const double toe = 216.0 / 24389.0;
+  for (int t = 0; t <= 65536; ++t) {
+    const double x = (double)t / 65536.0;
+    const double f = x > toe ? cbrt(x) : x * (841.0 / 108.0) + 4.0 / 29.0;
+    fcurve[t] = (uint16_t)(int32_t)floor(f * 32768.0 + 0.5);
+  }
+}
+
+static void host_lanczos(int32_t (*w)[16][7]) {
+  const double pi = 3.14159265358979323846;
+  for (int li = 0; li < 4; ++li) {
+    const int n = 2 << li;
+    for (int ph = 0; ph < 16; ++ph)
+      for (int k = 0; k < 7; ++k) w[li][ph][k] = 0;
+    for (int ph = 0; ph < n; ++ph) {
+      const double centre = (ph + 0.5) / n - 0.5;
+      int sum = 0;
+      for (int k = -3; k <= 3; ++k) {
+        const double x = centre - k;
+        double L = 0.0;
+        if (x == 0.0)
+          L = 1.0;
+        else if (fabs(x) < 3.0)
+          L = 3.0 * sin(pi * x) * sin(pi * x / 3.0) / (pi * pi * x * x);
+        w[li][ph][k + 3] = (int32_t)floor(16384.0 * L + 0.5);
+        sum += w[li][ph][k + 3];
+      }
+      w[li][ph][3] += 16384 - sum;
+    }
+  }
+}
+
+static std::mutex g_init_mu;
+static bool g_init_done[64];
+
+ff_status ensure_init() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return FF_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_init_mu);
+  if (g_init_done[dev]) return FF_OK;
+  static int32_t gamma[256], mat[9];
+  static uint16_t fcurve[65537];
+  static int32_t lz[4][16][7];
+  host_lab_tables(gamma, mat, fcurve);
+  host_lanczos(lz);
+  if (hipMemcpyToSymbol(HIP_SYMBOL(g_gamma), gamma, sizeof(gamma)) != hipSuccess) return FF_ERR_HIP;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(g_mat), mat, sizeof(mat)) != hipSuccess) return FF_ERR_HIP;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(g_fcurve), fcurve, sizeof(fcurve)) != hipSuccess) return FF_ERR_HIP;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_lanczos), lz, sizeof(lz)) != hipSuccess) return FF_ERR_HIP;
+  if (hipDeviceSynchronize() != hipSuccess) return FF_ERR_HIP;
+  g_init_done[dev] = true;
+  return FF_OK;
+}
+
+ff_status launch_status() { return hipGetLastError() == hipSuccess ? FF_OK : FF_ERR_HIP; }
+
+__global__ void k_fill_i32(int32_t* p, size_t n, int32_t v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+void fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t s) {
+  if (n == 0) return;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  k_fill_i32<<<(unsigned)blocks, 256, 0, s>>>(p, n, v);
+}
+
+// ---------------------------------------------------------------- Lab8
+__global__ void k_lab8(const uint8_t* __restrict__ img, int W, int H, int C, int stride, uint8_t* __restrict__ lab) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= W) return;
+  const size_t N = (size_t)W * H;
+  const uint8_t* px = img + (size_t)y * stride + (size_t)x * C;
+  const size_t o = (size_t)y * W + x;
+  if (C == 1) {
+    lab[o] = px[0];
+    return;
+  }
+  const int32_t lr = g_gamma[px[0]], lg = g_gamma[px[1]], lb = g_gamma[px[2]];
+  int32_t f[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int32_t acc = g_mat[3 * i] * lr + g_mat[3 * i + 1] * lg + g_mat[3 * i + 2] * lb;
+    f[i] = g_fcurve[(acc + 8192) >> 14];
+  }
+  // L = 116 fY - 16 scaled by 2.55: (2958 fY - 408 * 2^15) / (10 * 2^15), >= 0
+  const int32_t L = (2958 * f[1] - 408 * 32768 + 163840) / 327680;
+  const int32_t a = ((500 * (f[0] - f[1]) + 16384) >> 15) + 128;
+  const int32_t b = ((200 * (f[1] - f[2]) + 16384) >> 15) + 128;
+  lab[o] = (uint8_t)clampi(L, 0, 255);
+  lab[N + o] = (uint8_t)clampi(a, 0, 255);
+  lab[2 * N + o] = (uint8_t)clampi(b, 0, 255);
+}
+
+// ---------------------------------------------------------------- I^n
+__global__ void k_scale16(const uint8_t* __restrict__ lab, int16_t* __restrict__ out, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (int16_t)(16 * lab[i]);
+}
+
+// n x n block sums of the replicate-padded plane
+__global__ void k_blocksum(const uint8_t* __restrict__ J, int W, int H, int n, int Wc, int Hc, int32_t* __restrict__ A) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  const int c = blockIdx.z;
+  if (j >= Wc) return;
+  const uint8_t* P = J + (size_t)c * W * H;
+  int32_t s = 0;
+  for (int u = 0; u < n; ++u) {
+    const uint8_t* row = P + (size_t)min(i * n + u, H - 1) * W;
+    for (int v = 0; v < n; ++v) s += row[min(j * n + v, W - 1)];
+  }
+  A[((size_t)c * Hc + i) * Wc + j] = s;
+}
+
+// horizontal Lanczos pass: coarse rows -> full-resolution columns, rounded
+// back to block-sum units
+__global__ void k_lanczos_h(const int32_t* __restrict__ A, int W, int n, int li, int Wc, int Hc, int32_t* __restrict__ T) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  const int c = blockIdx.z;
+  if (x >= W) return;
+  const int32_t* row = A + ((size_t)c * Hc + i) * Wc;
+  const int ph = x % n, base = x / n;
+  int32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) s += c_lanczos[li][ph][k] * row[clampi(base + k - 3, 0, Wc - 1)];
+  T[((size_t)c * Hc + i) * W + x] = (s + 8192) >> 14;
+}
+
+// vertical pass: divide by 2^14 n^2 and keep 4 fractional bits
+__global__ void k_lanczos_v(const int32_t* __restrict__ T, int W, int H, int n, int li, int Hc, int shift,
+                            int16_t* __restrict__ S) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  const int c = blockIdx.z;
+  if (x >= W) return;
+  const int32_t* P = T + (size_t)c * Hc * W;
+  const int ph = y % n, base = y / n;
+  int32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) s += c_lanczos[li][ph][k] * P[(size_t)clampi(base + k - 3, 0, Hc - 1) * W + x];
+  S[((size_t)c * H + y) * W + x] = (int16_t)((s + (1 << (shift - 1))) >> shift);
+}
+
+// ---------------------------------------------------------------- census
+// One thread per pixel computes all Q*Q subpixel phases of its census word:
+// the 2x2 neighbourhoods of the centre and of the 8 neighbours at stride n
+// are loaded once per channel; each phase mixes them with exact integer
+// bilinear weights.
+template <int Q>
+__global__ void k_census(const int16_t* __restrict__ S, int W, int H, int C, int n, uint32_t* __restrict__ out,
+                         size_t plane_words) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= W) return;
+  uint32_t word[Q * Q];
+#pragma unroll
+  for (int i = 0; i < Q * Q; ++i) word[i] = 0;
+  const size_t N = (size_t)W * H;
+  for (int c = 0; c < C; ++c) {
+    const int16_t* P = S + c * N;
+    int32_t s00[9], s01[9], s10[9], s11[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int dx = t % 3 - 1, dy = t / 3 - 1;
+      const int X = clampi(x + n * dx, 0, W - 1), Y = clampi(y + n * dy, 0, H - 1);
+      const int X1 = min(X + 1, W - 1), Y1 = min(Y + 1, H - 1);
+      s00[t] = P[(size_t)Y * W + X];
+      s01[t] = P[(size_t)Y * W + X1];
+      s10[t] = P[(size_t)Y1 * W + X];
+      s11[t] = P[(size_t)Y1 * W + X1];
+    }
+#pragma unroll
+    for (int b = 0; b < Q; ++b)
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        const int w00 = (Q - a) * (Q - b), w01 = a * (Q - b), w10 = (Q - a) * b, w11 = a * b;
+        int32_t B[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) B[t] = w00 * s00[t] + w01 * s01[t] + w10 * s10[t] + w11 * s11[t];
+        // neighbours in raster order, skipping the centre (t = 4); bit i
+        // set when the neighbour is darker than the centre
+        uint32_t bits = 0;
+        int bit = 0;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+          if (t == 4) continue;
+          bits |= (uint32_t)(B[t] < B[4]) << bit;
+          ++bit;
+        }
+        word[b * Q + a] |= bits << (8 * c);
+      }
+  }
+  const size_t o = (size_t)y * W + x;
+#pragma unroll
+  for (int i = 0; i < Q * Q; ++i) out[i * plane_words + o] = word[i];
+}
+
+// ---------------------------------------------------------------- WHT
+// 1-D Walsh functions in sequency order on [-rho, rho]; odd extents split
+// rho | rho+1, the second split puts the smaller part first.
+__device__ __forceinline__ int walsh_sign(int s, int t, int rho) {
+  if (s == 0) return 1;
+  if (s == 1) return t < 0 ? 1 : -1;
+  if (t < 0) return (t + rho < rho / 2) ? 1 : -1;
+  return (t < (rho + 1) / 2) ? -1 : 1;
+}
+
+// horizontal 1-D transforms, three per channel
+__global__ void k_wht_h(const uint8_t* __restrict__ J, int W, int H, int rho, int32_t* __restrict__ h) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  const int c = blockIdx.z;
+  if (x >= W) return;
+  const size_t N = (size_t)W * H;
+  const uint8_t* row = J + c * N + (size_t)y * W;
+  int32_t s0 = 0, s1 = 0, s2 = 0;
+  for (int t = -rho; t <= rho; ++t) {
+    const int v = row[clampi(x + t, 0, W - 1)];
+    s0 += v;
+    s1 += walsh_sign(1, t, rho) * v;
+    s2 += walsh_sign(2, t, rho) * v;
+  }
+  const size_t o = (size_t)y * W + x;
+  h[(c * 3 + 0) * N + o] = s0;
+  h[(c * 3 + 1) * N + o] = s1;
+  h[(c * 3 + 2) * N + o] = s2;
+}
+
+// vertical combination into the 9 bases (u on dy, v on dx) in the order
+// (0,0) (0,1) (1,0) (1,1) (0,2) (2,0) (1,2) (2,1) (2,2)
+__global__ void k_wht_v(const int32_t* __restrict__ h, int W, int H, int C, int rho, int stride,
+                        int32_t* __restrict__ V) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= W) return;
+  const size_t N = (size_t)W * H;
+  const int bu[9] = {0, 0, 1, 1, 0, 2, 1, 2, 2};
+  const int bv[9] = {0, 1, 0, 1, 2, 0, 2, 1, 2};
+  int32_t* out = V + ((size_t)y * W + x) * stride;
+  for (int c = 0; c < C; ++c) {
+    int32_t acc[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) acc[j] = 0;
+    for (int t = -rho; t <= rho; ++t) {
+      const size_t o = (size_t)clampi(y + t, 0, H - 1) * W + x;
+      const int32_t hv[3] = {h[(c * 3 + 0) * N + o], h[(c * 3 + 1) * N + o], h[(c * 3 + 2) * N + o]};
+      const int su[3] = {1, walsh_sign(1, t, rho), walsh_sign(2, t, rho)};
+#pragma unroll
+      for (int j = 0; j < 9; ++j) acc[j] += su[bu[j]] * hv[bv[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < 9; ++j) out[c * 9 + j] = acc[j];
+  }
+  for (int j = 9 * C; j < stride; ++j) out[j] = 0;
+}
+
+}  // namespace ff
+
+using namespace ff;
+
+extern "C" {
+
+ff_status ff_init(void) { return ensure_init(); }
+
+ff_status ff_desc_init(ff_desc* d, const ff_image* img, int32_t k, int32_t subpel, const int32_t* radii,
+                       int32_t n_radii) {
+  if (!d || !img) return FF_ERR_ARG;
+  const int W = img->width, H = img->height, C = img->channels;
+  if (W < 1 || H < 1 || (C != 1 && C != 3) || img->row_stride < W * C) return FF_ERR_ARG;
+  if (k < 0 || k > 4) return FF_ERR_ARG;
+  if (subpel != 1 && subpel != 2 && subpel != 4 && subpel != 8) return FF_ERR_ARG;
+  if (n_radii < 0 || n_radii > FF_MAX_RADII || (n_radii > 0 && !radii)) return FF_ERR_ARG;
+  if (W > kMaxDim || H > kMaxDim || (int64_t)W * H > kMaxPoints) return FF_ERR_SIZE;
+  if ((int64_t)W * subpel > 32767 || (int64_t)H * subpel > 32767) return FF_ERR_SIZE;
+  *d = ff_desc{};
+  d->width = W;
+  d->height = H;
+  d->channels = C;
+  d->k = k;
+  d->subpel = subpel;
+  d->n_radii = n_radii;
+  for (int i = 0; i < n_radii; ++i) {
+    if (radii[i] < 1 || radii[i] > kMaxRadius) return FF_ERR_ARG;
+    for (int j = 0; j < i; ++j)
+      if (radii[j] == radii[i]) return FF_ERR_ARG;
+    d->radii[i] = radii[i];
+  }
+  d->wht_dims = 9 * C;
+  d->wht_stride = C == 3 ? 32 : 16;
+  const size_t N = (size_t)W * H;
+  size_t off = 0;
+  d->off_lab = off;
+  off = align_up(off + C * N, 256);
+  d->off_smooth = off;
+  off = align_up(off + (size_t)(k + 1) * C * N * 2, 256);
+  d->off_census = off;
+  d->plane_bytes = N * 4;
+  size_t census = (size_t)(k + 1) * subpel * subpel * N * 4;
+  // the census region doubles as scratch before the planes are written
+  const int Wc2 = (W + 1) / 2, Hc2 = (H + 1) / 2;
+  size_t scratch = (size_t)C * 3 * N * 4;
+  const size_t sm = (size_t)C * ((size_t)Hc2 * Wc2 + (size_t)Hc2 * W) * 4;
+  if (sm > scratch) scratch = sm;
+  if (scratch > census) census = scratch;
+  off = align_up(off + census, 256);
+  d->off_wht = off;
+  off = align_up(off + (size_t)n_radii * N * d->wht_stride * 4, 256);
+  d->bytes = off;
+  return FF_OK;
+}
+
+ff_status ff_compute_descriptors(const ff_desc* d, const ff_image* img, const uint8_t* pixels, void* blob,
+                                 size_t blob_bytes, hipStream_t stream) {
+  if (!d || !img || !pixels || !blob) return FF_ERR_ARG;
+  if (img->width != d->width || img->height != d->height || img->channels != d->channels ||
+      img->row_stride < img->width * img->channels)
+    return FF_ERR_ARG;
+  if (blob_bytes < d->bytes) return FF_ERR_WORKSPACE;
+  ff_status st = ensure_init();
+  if (st != FF_OK) return st;
+  const int W = d->width, H = d->height, C = d->channels;
+  const size_t N = (size_t)W * H;
+  char* base = static_cast<char*>(blob);
+  uint8_t* lab = reinterpret_cast<uint8_t*>(base + d->off_lab);
+  int16_t* smooth = reinterpret_cast<int16_t*>(base + d->off_smooth);
+  int32_t* scratch = reinterpret_cast<int32_t*>(base + d->off_census);
+  const dim3 tb(256);
+  const unsigned gx = (unsigned)((W + 255) / 256);
+
+  k_lab8<<<dim3(gx, H), tb, 0, stream>>>(pixels, W, H, C, img->row_stride, lab);
+  k_scale16<<<(unsigned)((C * N + 255) / 256), tb, 0, stream>>>(lab, smooth, C * N);
+  for (int lev = 1; lev <= d->k; ++lev) {
+    const int n = 1 << lev;
+    const int Wc = (W + n - 1) / n, Hc = (H + n - 1) / n;
+    int32_t* A = scratch;
+    int32_t* T = scratch + (size_t)C * Hc * Wc;
+    k_blocksum<<<dim3((unsigned)((Wc + 255) / 256), Hc, C), tb, 0, stream>>>(lab, W, H, n, Wc, Hc, A);
+    k_lanczos_h<<<dim3(gx, Hc, C), tb, 0, stream>>>(A, W, n, lev - 1, Wc, Hc, T);
+    const int shift = 14 + 2 * lev - 4;
+    k_lanczos_v<<<dim3(gx, H, C), tb, 0, stream>>>(T, W, H, n, lev - 1, Hc, shift, smooth + (size_t)lev * C * N);
+  }
+  for (int i = 0; i < d->n_radii; ++i) {
+    int32_t* V = reinterpret_cast<int32_t*>(base + d->off_wht + (size_t)i * N * d->wht_stride * 4);
+    k_wht_h<<<dim3(gx, H, C), tb, 0, stream>>>(lab, W, H, d->radii[i], scratch);
+    k_wht_v<<<dim3(gx, H), tb, 0, stream>>>(scratch, W, H, C, d->radii[i], d->wht_stride, V);
+  }
+  const size_t pw = N;
+  for (int lev = 0; lev <= d->k; ++lev) {
+    uint32_t* out = reinterpret_cast<uint32_t*>(base + d->off_census) + (size_t)lev * d->subpel * d->subpel * pw;
+    const int16_t* S = smooth + (size_t)lev * C * N;
+    const int n = 1 << lev;
+    switch (d->subpel) {
+      case 1: k_census<1><<<dim3(gx, H), tb, 0, stream>>>(S, W, H, C, n, out, pw); break;
+      case 2: k_census<2><<<dim3(gx, H), tb, 0, stream>>>(S, W, H, C, n, out, pw); break;
+      case 4: k_census<4><<<dim3(gx, H), tb, 0, stream>>>(S, W, H, C, n, out, pw); break;
+      default: k_census<8><<<dim3(gx, H), tb, 0, stream>>>(S, W, H, C, n, out, pw); break;
+    }
+  }
+  return launch_status();
+}
+
+}  // extern "C"

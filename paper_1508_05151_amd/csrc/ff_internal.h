@@ -1,0 +1,70 @@
+// Internal declarations shared by the translation units of libff (HIP for
+// gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "ff.h"
+
+namespace ff {
+
+constexpr int32_t kEmpty = FF_EMPTY;
+constexpr int32_t kInf = FF_COST_INF;
+constexpr int kMaxPoints = 1 << 22;   // pixel index fits 22 bits
+constexpr int kMaxDim = 8191;         // packed int16 flows at Q = 4 (|f| <= 32767)
+constexpr int kMaxRadius = 15;
+constexpr int kMaxLeaf = 64;
+
+// ---------------------------------------------------------------- helpers
+__host__ __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+__host__ __device__ inline int fx_of(int32_t f) { return (int)(int16_t)(uint16_t)((uint32_t)f & 0xFFFFu); }
+__host__ __device__ inline int fy_of(int32_t f) { return (int)(int16_t)(uint16_t)((uint32_t)f >> 16); }
+__host__ __device__ inline int32_t packf(int dx, int dy) {
+  return (int32_t)(((uint32_t)(uint16_t)(int16_t)dy << 16) | (uint32_t)(uint16_t)(int16_t)dx);
+}
+__host__ __device__ inline int ilog2i(int n) { int l = 0; while ((1 << l) < n) ++l; return l; }
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// ---------------------------------------------------------------- kd-tree
+// Levels whose nodes hold more than kTreeLds points are split by global
+// radix-select passes; below that, one workgroup finishes each subtree in LDS.
+constexpr int kTreeLds = 2048;
+constexpr int kSelBins = 2048;        // 11-bit digits, 4 passes over 44 bits
+constexpr int kSelPasses = 4;
+
+struct TreeLayout {
+  int N, depth, nodes;   // nodes = (2 << depth) - 1
+  int top;               // levels handled by the global passes
+  size_t off_dim, off_split, off_perm, off_perm2, off_minmax, off_hist, off_cnt;
+  size_t bytes;
+};
+TreeLayout tree_layout(int N, int leaf, size_t base);
+int tree_depth_of(int N, int leaf);
+
+// Builds the tree over V (N x stride int32, D dims) into the workspace
+// regions of `L` (and optionally copies nothing else).  Enqueues only.
+ff_status enqueue_tree_build(const int32_t* V, int N, int D, int stride, int leaf, const TreeLayout& L,
+                             char* ws, hipStream_t stream);
+
+// ---------------------------------------------------------------- descriptors
+inline const uint32_t* census_plane(const ff_desc* d, const void* blob, int lev, int a, int b) {
+  return reinterpret_cast<const uint32_t*>(static_cast<const char*>(blob) + d->off_census +
+                                           d->plane_bytes * ((size_t)lev * d->subpel * d->subpel + b * d->subpel + a));
+}
+inline const int32_t* wht_block(const ff_desc* d, const void* blob, int radius) {
+  for (int i = 0; i < d->n_radii; ++i)
+    if (d->radii[i] == radius)
+      return reinterpret_cast<const int32_t*>(static_cast<const char*>(blob) + d->off_wht +
+                                              (size_t)i * d->width * d->height * d->wht_stride * 4);
+  return nullptr;
+}
+
+ff_status ensure_init();
+ff_status launch_status();   // maps hipGetLastError to FF_ERR_HIP
+
+// fill a device int32 buffer with a value (graph-safe: a kernel, no memset)
+void fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t s);
+
+}  // namespace ff

@@ -1,0 +1,443 @@
+// kd-tree over the WHT vectors of every target pixel (section 3.1): split
+// while a node holds more than l points, on the dimension of maximal spread,
+// at the median of (key, pixel index).
+//
+// GPU design.  The tree is perfectly balanced by construction (left child =
+// first floor(cnt/2) points), so every node's range in the permutation array
+// is a function of its heap index alone.  Only the *membership* of each child
+// matters (leaves are finally sorted by pixel index), so the order inside a
+// node is free.
+//  * Top levels (nodes larger than kTreeLds points): level-synchronous passes
+//    over all nodes of a level at once --
+//      minmax    per-node per-dimension min/max (order-free atomics),
+//      hist x4   MSD radix select of the rank floor(cnt/2) element of the
+//                44-bit key ((key - min) << 22 | pixel), 11 bits per pass,
+//      partition strict-less-than-pivot to the left, others right.
+//  * Below: one workgroup per subtree of <= kTreeLds points finishes every
+//    remaining level in LDS with a bitonic sort of (segment, key, pixel).
+#include "ff_internal.h"
+
+namespace ff {
+
+constexpr int kChunk = 4096;     // elements per workgroup in the global passes
+constexpr int kTpb = 256;
+
+int tree_depth_of(int N, int leaf) {
+  int d = 0;
+  while (((int64_t)N + (1LL << d) - 1) / (1LL << d) > leaf) ++d;
+  return d;
+}
+
+TreeLayout tree_layout(int N, int leaf, size_t base) {
+  TreeLayout L{};
+  L.N = N;
+  L.depth = tree_depth_of(N, leaf);
+  L.nodes = (2 << L.depth) - 1;
+  int top = 0;
+  while (((int64_t)N + (1LL << top) - 1) / (1LL << top) > kTreeLds) ++top;
+  L.top = top;
+  const size_t topnodes = ((size_t)1 << top) - 1;
+  size_t off = align_up(base, 256);
+  L.off_dim = off;   off = align_up(off + (size_t)L.nodes * 4, 256);
+  L.off_split = off; off = align_up(off + (size_t)L.nodes * 4, 256);
+  L.off_perm = off;  off = align_up(off + (size_t)N * 4, 256);
+  L.off_perm2 = off; off = align_up(off + (size_t)N * 4, 256);
+  L.off_minmax = off; off = align_up(off + topnodes * 64 * 4, 256);
+  L.off_hist = off;  off = align_up(off + topnodes * kSelPasses * kSelBins * 4, 256);
+  L.off_cnt = off;   off = align_up(off + topnodes * 2 * 4, 256);
+  L.bytes = off - base;
+  return L;
+}
+
+// range [start, start+cnt) of node j at depth d (j's bits from the top are
+// the left/right decisions)
+__device__ __forceinline__ void node_range(int d, int j, int N, int& start, int& cnt) {
+  start = 0;
+  cnt = N;
+  for (int b = d - 1; b >= 0; --b) {
+    const int h = cnt >> 1;
+    if ((j >> b) & 1) { start += h; cnt -= h; }
+    else cnt = h;
+  }
+}
+
+__global__ void k_iota(int32_t* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = i;
+}
+
+__global__ void k_minmax_init(int32_t* mm, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) mm[i] = (i & 1) ? INT32_MIN : INT32_MAX;   // pairs (min, max)
+}
+
+// ---------------------------------------------------------------- top levels
+__global__ __launch_bounds__(kTpb) void k_tree_minmax(const int32_t* __restrict__ V, int stride, int D, int N, int d,
+                                                      const int32_t* __restrict__ perm, int32_t* __restrict__ mm) {
+  const int j = blockIdx.y;
+  int start, cnt;
+  node_range(d, j, N, start, cnt);
+  const int lo = blockIdx.x * kChunk;
+  if (lo >= cnt) return;
+  const int hi = min(cnt, lo + kChunk);
+  __shared__ int32_t smin[32], smax[32];
+  if (threadIdx.x < 32) { smin[threadIdx.x] = INT32_MAX; smax[threadIdx.x] = INT32_MIN; }
+  __syncthreads();
+  int32_t mn[27], mx[27];
+#pragma unroll
+  for (int k = 0; k < 27; ++k) { mn[k] = INT32_MAX; mx[k] = INT32_MIN; }
+  for (int e = lo + threadIdx.x; e < hi; e += kTpb) {
+    const int32_t* v = V + (size_t)perm[start + e] * stride;
+#pragma unroll
+    for (int k = 0; k < 27; ++k)
+      if (k < D) { const int32_t x = v[k]; mn[k] = min(mn[k], x); mx[k] = max(mx[k], x); }
+  }
+#pragma unroll
+  for (int k = 0; k < 27; ++k) {
+    if (k >= D) break;
+    int32_t a = mn[k], b = mx[k];
+    for (int o = 32; o > 0; o >>= 1) {
+      a = min(a, __shfl_xor(a, o));
+      b = max(b, __shfl_xor(b, o));
+    }
+    if ((threadIdx.x & 63) == 0) { atomicMin(&smin[k], a); atomicMax(&smax[k], b); }
+  }
+  __syncthreads();
+  const int node = (1 << d) - 1 + j;
+  if (threadIdx.x < D) {
+    atomicMin(&mm[((size_t)node * 32 + threadIdx.x) * 2], smin[threadIdx.x]);
+    atomicMax(&mm[((size_t)node * 32 + threadIdx.x) * 2 + 1], smax[threadIdx.x]);
+  }
+}
+
+// split dimension of a node from its min/max: largest spread, lowest on ties
+__device__ __forceinline__ void node_split_dim(const int32_t* mm, int node, int D, int& dim, int32_t& mn) {
+  int best = 0;
+  int64_t bs = -1;
+  for (int k = 0; k < D; ++k) {
+    const int64_t s = (int64_t)mm[((size_t)node * 32 + k) * 2 + 1] - mm[((size_t)node * 32 + k) * 2];
+    if (s > bs) { bs = s; best = k; }
+  }
+  dim = best;
+  mn = mm[((size_t)node * 32 + best) * 2];
+}
+
+// Radix-select state after `passes` completed passes: the known high digits
+// of the pivot key and its rank among the keys sharing them.  Whole-block
+// cooperative scan of each pass's histogram.
+__device__ void select_state(const int32_t* __restrict__ hist, int node, int passes, int rank0, uint64_t& prefix,
+                             int& rank) {
+  __shared__ int32_t part[kTpb];
+  __shared__ int32_t s_bin, s_before;
+  prefix = 0;
+  rank = rank0;
+  constexpr int per = kSelBins / kTpb;
+  for (int p = 0; p < passes; ++p) {
+    const int32_t* h = hist + ((size_t)node * kSelPasses + p) * kSelBins;
+    int32_t loc[per];
+    int32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < per; ++i) { loc[i] = h[threadIdx.x * per + i]; s += loc[i]; }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    // inclusive scan over the block (Hillis-Steele)
+    for (int o = 1; o < kTpb; o <<= 1) {
+      const int32_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+      __syncthreads();
+      part[threadIdx.x] += v;
+      __syncthreads();
+    }
+    const int32_t incl = part[threadIdx.x];
+    const int32_t excl = incl - s;
+    if (rank >= excl && rank < incl) {
+      int32_t c = excl;
+      for (int i = 0; i < per; ++i) {
+        if (rank < c + loc[i]) { s_bin = threadIdx.x * per + i; s_before = c; break; }
+        c += loc[i];
+      }
+    }
+    __syncthreads();
+    prefix = (prefix << 11) | (uint64_t)s_bin;
+    rank -= s_before;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kTpb) void k_tree_hist(const int32_t* __restrict__ V, int stride, int D, int N, int d,
+                                                    const int32_t* __restrict__ perm, const int32_t* __restrict__ mm,
+                                                    int32_t* __restrict__ hist, int32_t* __restrict__ node_dim,
+                                                    int pass) {
+  const int j = blockIdx.y;
+  int start, cnt;
+  node_range(d, j, N, start, cnt);
+  const int lo = blockIdx.x * kChunk;
+  if (lo >= cnt) return;
+  const int hi = min(cnt, lo + kChunk);
+  const int node = (1 << d) - 1 + j;
+  int dim;
+  int32_t mn;
+  node_split_dim(mm, node, D, dim, mn);
+  if (pass == 0 && blockIdx.x == 0 && threadIdx.x == 0) node_dim[node] = dim;
+  uint64_t prefix;
+  int rank;
+  select_state(hist, node, pass, cnt >> 1, prefix, rank);
+  __shared__ int32_t lh[kSelBins];
+  for (int i = threadIdx.x; i < kSelBins; i += kTpb) lh[i] = 0;
+  __syncthreads();
+  const int shift = 33 - 11 * pass;
+  for (int e = lo + threadIdx.x; e < hi; e += kTpb) {
+    const int id = perm[start + e];
+    const uint64_t ck = ((uint64_t)(uint32_t)(V[(size_t)id * stride + dim] - mn) << 22) | (uint64_t)id;
+    if ((ck >> (shift + 11)) == prefix) atomicAdd(&lh[(ck >> shift) & (kSelBins - 1)], 1);
+  }
+  __syncthreads();
+  int32_t* g = hist + ((size_t)node * kSelPasses + pass) * kSelBins;
+  for (int i = threadIdx.x; i < kSelBins; i += kTpb)
+    if (lh[i]) atomicAdd(&g[i], lh[i]);
+}
+
+__global__ __launch_bounds__(kTpb) void k_tree_partition(const int32_t* __restrict__ V, int stride, int D, int N, int d,
+                                                         const int32_t* __restrict__ perm, int32_t* __restrict__ out,
+                                                         const int32_t* __restrict__ mm, const int32_t* __restrict__ hist,
+                                                         int32_t* __restrict__ counters, int32_t* __restrict__ node_split) {
+  const int j = blockIdx.y;
+  int start, cnt;
+  node_range(d, j, N, start, cnt);
+  const int lo = blockIdx.x * kChunk;
+  if (lo >= cnt) return;
+  const int hi = min(cnt, lo + kChunk);
+  const int node = (1 << d) - 1 + j;
+  int dim;
+  int32_t mn;
+  node_split_dim(mm, node, D, dim, mn);
+  uint64_t pivot;
+  int rank;
+  select_state(hist, node, kSelPasses, cnt >> 1, pivot, rank);
+  if (blockIdx.x == 0 && threadIdx.x == 0) node_split[node] = (int32_t)(pivot >> 22) + mn;
+  constexpr int EPT = kChunk / kTpb;
+  int ids[EPT];
+  uint32_t leftmask = 0;
+  int nl = 0, nv = 0;
+  const int e0 = lo + threadIdx.x * EPT;
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = e0 + i;
+    if (e < hi) {
+      const int id = perm[start + e];
+      ids[i] = id;
+      const uint64_t ck = ((uint64_t)(uint32_t)(V[(size_t)id * stride + dim] - mn) << 22) | (uint64_t)id;
+      if (ck < pivot) { leftmask |= 1u << i; ++nl; }
+      ++nv;
+    }
+  }
+  __shared__ int32_t sl[kTpb], sr[kTpb];
+  __shared__ int32_t baseL, baseR;
+  sl[threadIdx.x] = nl;
+  sr[threadIdx.x] = nv - nl;
+  __syncthreads();
+  for (int o = 1; o < kTpb; o <<= 1) {
+    const int32_t a = threadIdx.x >= o ? sl[threadIdx.x - o] : 0;
+    const int32_t b = threadIdx.x >= o ? sr[threadIdx.x - o] : 0;
+    __syncthreads();
+    sl[threadIdx.x] += a;
+    sr[threadIdx.x] += b;
+    __syncthreads();
+  }
+  if (threadIdx.x == kTpb - 1) {
+    baseL = atomicAdd(&counters[node * 2], sl[kTpb - 1]);
+    baseR = atomicAdd(&counters[node * 2 + 1], sr[kTpb - 1]);
+  }
+  __syncthreads();
+  int pl = start + baseL + sl[threadIdx.x] - nl;
+  int pr = start + (cnt >> 1) + baseR + sr[threadIdx.x] - (nv - nl);
+  // every write stays inside this node's range even if the counts were off
+  const int lend = start + (cnt >> 1), rend = start + cnt;
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    if (e0 + i < hi) {
+      if ((leftmask >> i) & 1) {
+        if (pl < lend) out[pl] = ids[i];
+        ++pl;
+      } else {
+        if (pr < rend) out[pr] = ids[i];
+        ++pr;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- subtrees in LDS
+constexpr int kSubTpb = 512;
+
+__device__ __forceinline__ void heap_range(int node, int N, int& start, int& cnt) {
+  const int d = 31 - __clz(node + 1);
+  node_range(d, node + 1 - (1 << d), N, start, cnt);
+}
+
+__device__ void bitonic_sort(uint64_t* key, int P) {
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < P; i += kSubTpb) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t a = key[i], b = key[ixj];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) { key[i] = b; key[ixj] = a; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ __launch_bounds__(kSubTpb) void k_tree_subtree(const int32_t* __restrict__ V, int stride, int D, int N,
+                                                          int top, int leaf, const int32_t* __restrict__ perm_in,
+                                                          int32_t* __restrict__ perm_out, int32_t* __restrict__ node_dim,
+                                                          int32_t* __restrict__ node_split) {
+  __shared__ uint64_t key[kTreeLds];
+  __shared__ int32_t enode[kTreeLds];       // heap node of the segment holding position e
+  __shared__ uint16_t eseg[kTreeLds];       // local start of that segment
+  __shared__ int32_t s_start[kTreeLds / 2], s_cnt[kTreeLds / 2];
+  __shared__ int32_t s_min[kTreeLds / 2], s_max[kTreeLds / 2];
+  __shared__ int32_t s_best[kTreeLds / 2], s_dim[kTreeLds / 2], s_bmin[kTreeLds / 2];
+  __shared__ int s_any;
+  const int root = (1 << top) - 1 + blockIdx.x;
+  int rstart, rcnt;
+  heap_range(root, N, rstart, rcnt);
+  int P = 1;
+  while (P < rcnt) P <<= 1;
+  for (int e = threadIdx.x; e < P; e += kSubTpb) {
+    if (e < rcnt) {
+      key[e] = (uint64_t)perm_in[rstart + e];
+      enode[e] = root;
+      eseg[e] = 0;
+    } else {
+      key[e] = ~0ull;
+    }
+  }
+  __syncthreads();
+  const uint64_t idmask = (1ull << 22) - 1;
+  for (int t = 0;; ++t) {
+    const int nslots = 1 << t;
+    const int base = (root + 1) * nslots - 1;    // first heap index at this relative depth
+    if (threadIdx.x == 0) s_any = 0;
+    __syncthreads();
+    for (int s = threadIdx.x; s < nslots; s += kSubTpb) {
+      int st, c;
+      heap_range(base + s, N, st, c);
+      s_start[s] = st - rstart;
+      s_cnt[s] = c;
+      s_best[s] = -1;
+      s_dim[s] = 0;
+      s_bmin[s] = 0;
+      if (c > leaf) s_any = 1;
+    }
+    __syncthreads();
+    if (!s_any) break;
+    for (int k = 0; k < D; ++k) {
+      for (int s = threadIdx.x; s < nslots; s += kSubTpb) { s_min[s] = INT32_MAX; s_max[s] = INT32_MIN; }
+      __syncthreads();
+      for (int e = threadIdx.x; e < rcnt; e += kSubTpb) {
+        const int s = enode[e] - base;
+        if (s >= 0 && s < nslots && s_cnt[s] > leaf) {
+          const int32_t v = V[(size_t)(key[e] & idmask) * stride + k];
+          atomicMin(&s_min[s], v);
+          atomicMax(&s_max[s], v);
+        }
+      }
+      __syncthreads();
+      for (int s = threadIdx.x; s < nslots; s += kSubTpb) {
+        if (s_cnt[s] > leaf) {
+          const int32_t spread = s_max[s] - s_min[s];
+          if (spread > s_best[s]) { s_best[s] = spread; s_dim[s] = k; s_bmin[s] = s_min[s]; }
+        }
+      }
+      __syncthreads();
+    }
+    for (int e = threadIdx.x; e < rcnt; e += kSubTpb) {
+      const uint64_t id = key[e] & idmask;
+      const int s = enode[e] - base;
+      uint64_t sub = 0;
+      if (s >= 0 && s < nslots && s_cnt[s] > leaf)
+        sub = (uint64_t)(uint32_t)(V[(size_t)id * stride + s_dim[s]] - s_bmin[s]) << 22;
+      key[e] = ((uint64_t)eseg[e] << 42) | sub | id;
+    }
+    __syncthreads();
+    bitonic_sort(key, P);
+    for (int s = threadIdx.x; s < nslots; s += kSubTpb) {
+      if (s_cnt[s] > leaf) {
+        const int h = s_cnt[s] >> 1;
+        const uint64_t pid = key[s_start[s] + h] & idmask;
+        node_dim[base + s] = s_dim[s];
+        node_split[base + s] = V[(size_t)pid * stride + s_dim[s]];
+      }
+    }
+    for (int e = threadIdx.x; e < rcnt; e += kSubTpb) {
+      const int s = enode[e] - base;
+      if (s >= 0 && s < nslots && s_cnt[s] > leaf) {
+        const int h = s_cnt[s] >> 1;
+        const int node = base + s;
+        if (e < s_start[s] + h) {
+          enode[e] = 2 * node + 1;
+        } else {
+          enode[e] = 2 * node + 2;
+          eseg[e] = (uint16_t)(s_start[s] + h);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // leaves: ascending pixel index inside every segment
+  for (int e = threadIdx.x; e < rcnt; e += kSubTpb) key[e] = ((uint64_t)eseg[e] << 42) | (key[e] & idmask);
+  __syncthreads();
+  bitonic_sort(key, P);
+  for (int e = threadIdx.x; e < rcnt; e += kSubTpb) perm_out[rstart + e] = (int32_t)(key[e] & idmask);
+}
+
+ff_status enqueue_tree_build(const int32_t* V, int N, int D, int stride, int leaf, const TreeLayout& L, char* ws,
+                             hipStream_t stream) {
+  int32_t* node_dim = reinterpret_cast<int32_t*>(ws + L.off_dim);
+  int32_t* node_split = reinterpret_cast<int32_t*>(ws + L.off_split);
+  int32_t* perm = reinterpret_cast<int32_t*>(ws + L.off_perm);
+  int32_t* perm2 = reinterpret_cast<int32_t*>(ws + L.off_perm2);
+  int32_t* mm = reinterpret_cast<int32_t*>(ws + L.off_minmax);
+  int32_t* hist = reinterpret_cast<int32_t*>(ws + L.off_hist);
+  int32_t* cnt = reinterpret_cast<int32_t*>(ws + L.off_cnt);
+  const int topnodes = (1 << L.top) - 1;
+  fill_i32(node_dim, L.nodes, -1, stream);
+  fill_i32(node_split, L.nodes, 0, stream);
+  k_iota<<<(N + 255) / 256, 256, 0, stream>>>(perm, N);
+  if (L.top > 0) {
+    k_minmax_init<<<(topnodes * 64 + 255) / 256, 256, 0, stream>>>(mm, topnodes * 64);
+    fill_i32(hist, (size_t)topnodes * kSelPasses * kSelBins, 0, stream);
+    fill_i32(cnt, (size_t)topnodes * 2, 0, stream);
+  }
+  int32_t* cur = perm;
+  int32_t* nxt = perm2;
+  for (int d = 0; d < L.top; ++d) {
+    const int maxcnt = (int)(((int64_t)N + (1LL << d) - 1) >> d);
+    const dim3 grid((maxcnt + kChunk - 1) / kChunk, 1 << d);
+    k_tree_minmax<<<grid, kTpb, 0, stream>>>(V, stride, D, N, d, cur, mm);
+    for (int p = 0; p < kSelPasses; ++p)
+      k_tree_hist<<<grid, kTpb, 0, stream>>>(V, stride, D, N, d, cur, mm, hist, node_dim, p);
+    k_tree_partition<<<grid, kTpb, 0, stream>>>(V, stride, D, N, d, cur, nxt, mm, hist, cnt, node_split);
+    int32_t* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  k_tree_subtree<<<1 << L.top, kSubTpb, 0, stream>>>(V, stride, D, N, L.top, leaf, cur, perm, node_dim, node_split);
+  return launch_status();
+}
+
+}  // namespace ff
+
+using namespace ff;
+
+extern "C" {
+
+int32_t ff_tree_nodes(int32_t n_points, int32_t leaf) {
+  if (n_points < 1 || leaf < 1) return 0;
+  return (2 << tree_depth_of(n_points, leaf)) - 1;
+}
+
+}  // extern "C"

@@ -1,0 +1,244 @@
+"""Python binding of libff (ctypes).
+
+Argument marshalling only: every step of the search runs in the library's
+HIP kernels.  PyTorch supplies device memory (tensors) and streams.  If the
+library is not built the import fails loudly -- there is no fallback.
+
+Names follow the C ABI in include/ff.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libff.so")
+
+FF_EMPTY = -2147450880
+FF_COST_INF = 2147483647
+MAX_RADII = 4
+
+STATUS = {0: "FF_OK", -1: "FF_ERR_ARG", -2: "FF_ERR_SIZE", -3: "FF_ERR_WORKSPACE", -4: "FF_ERR_UNSUPPORTED",
+          -5: "FF_ERR_HIP", -6: "FF_ERR_DEVICE"}
+
+
+class FFError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {STATUS.get(code, code)}")
+        self.code = code
+
+
+class ff_image(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("channels", C.c_int32), ("row_stride", C.c_int32)]
+
+
+class ff_desc(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("channels", C.c_int32), ("k", C.c_int32),
+                ("subpel", C.c_int32), ("n_radii", C.c_int32), ("radii", C.c_int32 * MAX_RADII),
+                ("wht_dims", C.c_int32), ("wht_stride", C.c_int32), ("off_lab", C.c_size_t),
+                ("off_smooth", C.c_size_t), ("off_census", C.c_size_t), ("off_wht", C.c_size_t),
+                ("plane_bytes", C.c_size_t), ("bytes", C.c_size_t)]
+
+
+class ff_match_params(C.Structure):
+    _fields_ = [("k", C.c_int32), ("R", C.c_int32), ("leaf", C.c_int32), ("n_prop", C.c_int32),
+                ("n_rs", C.c_int32), ("use_kdtree", C.c_int32), ("max_steps", C.c_int32),
+                ("field_id", C.c_uint32), ("pair_id", C.c_uint32), ("reserved", C.c_uint32),
+                ("seed", C.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() (the GPU path has no fallback)")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        i32 = C.c_int32
+        L.ff_init.restype = i32
+        L.ff_default_params.argtypes = [C.POINTER(ff_match_params)]
+        L.ff_default_params.restype = None
+        L.ff_desc_init.argtypes = [C.POINTER(ff_desc), C.POINTER(ff_image), i32, i32, P, i32]
+        L.ff_desc_init.restype = i32
+        L.ff_compute_descriptors.argtypes = [C.POINTER(ff_desc), C.POINTER(ff_image), P, P, C.c_size_t, P]
+        L.ff_compute_descriptors.restype = i32
+        L.ff_match_workspace_bytes.argtypes = [C.POINTER(ff_desc), C.POINTER(ff_desc), i32,
+                                               C.POINTER(ff_match_params)]
+        L.ff_match_workspace_bytes.restype = C.c_size_t
+        L.ff_match_field.argtypes = [C.POINTER(ff_desc), P, C.POINTER(ff_desc), P, i32, C.POINTER(ff_match_params),
+                                     P, P, P, P, C.c_size_t, P]
+        L.ff_match_field.restype = i32
+        L.ff_consistency_filter.argtypes = [P, i32, i32, P, i32, i32, i32, i32, i32, P, P, P]
+        L.ff_consistency_filter.restype = i32
+        L.ff_tree_nodes.argtypes = [i32, i32]
+        L.ff_tree_nodes.restype = i32
+        L.ff_build_kdtree.argtypes = [C.POINTER(ff_desc), P, i32, i32, P, P, P, P, C.c_size_t, P]
+        L.ff_build_kdtree.restype = i32
+        L.ff_read_status.argtypes = [P, C.POINTER(C.c_int32)]
+        L.ff_read_status.restype = i32
+        L.ff_status_string.argtypes = [i32]
+        L.ff_status_string.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(code, what):
+    if code != 0:
+        raise FFError(code, what)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------------ C ABI
+def ff_init():
+    _check(lib().ff_init(), "ff_init")
+
+
+def ff_default_params(**overrides) -> ff_match_params:
+    p = ff_match_params()
+    lib().ff_default_params(C.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def ff_desc_init(width, height, channels=3, k=3, subpel=4, radii=(8, 6)) -> ff_desc:
+    d = ff_desc()
+    img = ff_image(width, height, channels, width * channels)
+    r = (C.c_int32 * MAX_RADII)(*radii)
+    _check(lib().ff_desc_init(C.byref(d), C.byref(img), k, subpel, C.cast(r, C.c_void_p), len(radii)),
+           "ff_desc_init")
+    return d
+
+
+def ff_compute_descriptors(d: ff_desc, pixels: torch.Tensor, blob: torch.Tensor, stream=None):
+    """pixels: H x W x C uint8 device tensor (contiguous); blob: d.bytes
+    device bytes (uint8 tensor)."""
+    assert pixels.is_cuda and pixels.dtype == torch.uint8 and pixels.is_contiguous()
+    H, W = pixels.shape[:2]
+    Cc = 1 if pixels.dim() == 2 else pixels.shape[2]
+    img = ff_image(W, H, Cc, W * Cc)
+    _check(lib().ff_compute_descriptors(C.byref(d), C.byref(img), _ptr(pixels), _ptr(blob), blob.numel(),
+                                        _stream(stream)), "ff_compute_descriptors")
+
+
+def ff_match_workspace_bytes(src: ff_desc, dst: ff_desc, radius: int, p: ff_match_params) -> int:
+    n = lib().ff_match_workspace_bytes(C.byref(src), C.byref(dst), radius, C.byref(p))
+    if n == 0:
+        raise FFError(-1, "ff_match_workspace_bytes")
+    return n
+
+
+def ff_match_field(src: ff_desc, src_blob, dst: ff_desc, dst_blob, radius: int, p: ff_match_params, proposal,
+                   flow, cost, workspace, stream=None):
+    _check(lib().ff_match_field(C.byref(src), _ptr(src_blob), C.byref(dst), _ptr(dst_blob), radius, C.byref(p),
+                                _ptr(proposal), _ptr(flow), _ptr(cost), _ptr(workspace), workspace.numel(),
+                                _stream(stream)), "ff_match_field")
+
+
+def ff_consistency_filter(flow_fwd, flows_bwd, subpel, eps_q, keep, flow_filtered, stream=None):
+    h1, w1 = flow_fwd.shape
+    h2, w2 = flows_bwd[0].shape
+    arr = (C.c_void_p * len(flows_bwd))(*[b.data_ptr() for b in flows_bwd])
+    _check(lib().ff_consistency_filter(_ptr(flow_fwd), w1, h1, C.cast(arr, C.c_void_p), len(flows_bwd), w2, h2,
+                                       subpel, eps_q, _ptr(keep), _ptr(flow_filtered), _stream(stream)),
+           "ff_consistency_filter")
+
+
+def ff_tree_nodes(n_points: int, leaf: int) -> int:
+    return lib().ff_tree_nodes(n_points, leaf)
+
+
+def ff_build_kdtree(d: ff_desc, blob, radius, leaf, node_dim, node_split, perm, workspace, stream=None):
+    _check(lib().ff_build_kdtree(C.byref(d), _ptr(blob), radius, leaf, _ptr(node_dim), _ptr(node_split), _ptr(perm),
+                                 _ptr(workspace), workspace.numel(), _stream(stream)), "ff_build_kdtree")
+
+
+def ff_read_status(workspace) -> int:
+    s = C.c_int32(0)
+    _check(lib().ff_read_status(_ptr(workspace), C.byref(s)), "ff_read_status")
+    return s.value
+
+
+# ------------------------------------------------------------------ helpers
+def blob_views(d: ff_desc, blob: torch.Tensor):
+    """Typed views of a descriptor blob's sections (for inspection)."""
+    N = d.width * d.height
+    H, W, Cc, K, Q = d.height, d.width, d.channels, d.k, d.subpel
+    lab = blob[d.off_lab:d.off_lab + Cc * N].view(Cc, H, W)
+    smooth = blob[d.off_smooth:d.off_smooth + (K + 1) * Cc * N * 2].view(torch.int16).view(K + 1, Cc, H, W)
+    census = blob[d.off_census:d.off_census + (K + 1) * Q * Q * N * 4].view(torch.int32).view(K + 1, Q, Q, H, W)
+    whts = {}
+    for i in range(d.n_radii):
+        o = d.off_wht + i * N * d.wht_stride * 4
+        whts[d.radii[i]] = blob[o:o + N * d.wht_stride * 4].view(torch.int32).view(H, W, d.wht_stride)
+    return dict(lab=lab, smooth=smooth, census=census, wht=whts)
+
+
+class PairMatcher:
+    """The whole hot path for one image pair on three streams: descriptors of
+    both images, F = I1 -> I2 (r), B1 = I2 -> I1 (r), B2 = I2 -> I1 (r2), then
+    the two-way consistency filter (sections 3.1-3.4).  Buffers are allocated
+    once for a given image size and reused."""
+
+    def __init__(self, width, height, channels=3, r=8, r2=6, k=3, subpel=4, eps=5, n_bwd=2, device="cuda",
+                 **params):
+        self.W, self.H, self.C = width, height, channels
+        self.r, self.r2, self.k, self.Q, self.eps, self.n_bwd = r, r2, k, subpel, eps, n_bwd
+        radii = (r,) if (n_bwd == 1 or r2 == r) else (r, r2)
+        self.desc = ff_desc_init(width, height, channels, k, subpel, radii)
+        self.blob1 = torch.empty(self.desc.bytes, dtype=torch.uint8, device=device)
+        self.blob2 = torch.empty(self.desc.bytes, dtype=torch.uint8, device=device)
+        self.params = [ff_default_params(k=k, field_id=i, **params) for i in range(3)]
+        self.fields = [("F", r, 0), ("B1", r, 1)] + ([("B2", r2, 2)] if n_bwd == 2 else [])
+        self.ws = []
+        self.flow = {}
+        self.cost = {}
+        for name, rad, fid in self.fields:
+            nb = ff_match_workspace_bytes(self.desc, self.desc, rad, self.params[fid])
+            self.ws.append(torch.empty(nb, dtype=torch.uint8, device=device))
+            self.flow[name] = torch.empty((height, width), dtype=torch.int32, device=device)
+            self.cost[name] = torch.empty((height, width), dtype=torch.int32, device=device)
+        self.keep = torch.empty((height, width), dtype=torch.uint8, device=device)
+        self.filtered = torch.empty((height, width), dtype=torch.int32, device=device)
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(3)]
+
+    def run(self, img1: torch.Tensor, img2: torch.Tensor, seed: int = 0, pair_id: int = 0, proposal=None):
+        main = torch.cuda.current_stream()
+        ff_compute_descriptors(self.desc, img1, self.blob1, main)
+        ff_compute_descriptors(self.desc, img2, self.blob2, main)
+        ev = torch.cuda.Event()
+        ev.record(main)
+        for (name, rad, fid), ws, s in zip(self.fields, self.ws, self.streams):
+            s.wait_event(ev)
+            p = self.params[fid]
+            p.seed = seed
+            p.pair_id = pair_id
+            src, sb, dst, db = ((self.desc, self.blob1, self.desc, self.blob2) if name == "F"
+                                else (self.desc, self.blob2, self.desc, self.blob1))
+            ff_match_field(src, sb, dst, db, rad, p, proposal if name == "F" else None, self.flow[name],
+                           self.cost[name], ws, s)
+        for s in self.streams[:len(self.fields)]:
+            e = torch.cuda.Event()
+            e.record(s)
+            main.wait_event(e)
+        bwd = [self.flow["B1"]] + ([self.flow["B2"]] if self.n_bwd == 2 else [])
+        ff_consistency_filter(self.flow["F"], bwd, self.Q, self.eps * self.Q, self.keep, self.filtered, main)
+        return dict(F=self.flow["F"], CF=self.cost["F"], B1=self.flow["B1"], CB1=self.cost["B1"],
+                    B2=self.flow.get("B2"), CB2=self.cost.get("B2"), keep=self.keep, filtered=self.filtered)
+
+    def status(self):
+        return [ff_read_status(w) for w in self.ws]

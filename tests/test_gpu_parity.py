@@ -1,0 +1,192 @@
+"""GPU parity: every stage of the HIP path against the CPU oracle, bit for bit
+(all of the path is integer arithmetic).  Calls go through the C ABI
+(paper_1508_05151_amd.ff); inputs come from the seeded generator."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ffo
+from synth import pairs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+Q = 4
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ff():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1508_05151_amd import ff as _ff
+    _ff.ff_init()
+    return _ff
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _gpu_desc(ff, img, k=3, radii=(8, 6)):
+    img = np.ascontiguousarray(img)
+    if img.ndim == 2:
+        img = img[:, :, None]
+    H, W, C = img.shape
+    d = ff.ff_desc_init(W, H, C, k, Q, radii)
+    blob = torch.zeros(d.bytes, dtype=torch.uint8, device="cuda")
+    ff.ff_compute_descriptors(d, _dev(img), blob)
+    return d, blob
+
+
+def _ragged_pair(seed, W, H, C=3, nlayers=2):
+    p = pairs.config1_pair(seed=seed, W=W, H=H, nlayers=nlayers)
+    if C == 1:
+        g = lambda im: np.ascontiguousarray(im[:, :, :1])
+        p.img1, p.img2 = g(p.img1), g(p.img2)
+    return p
+
+
+CASES = [("config0", lambda: pairs.config0_pair(0), 3, (8, 6)),
+         ("ragged97x61", lambda: _ragged_pair(5, 97, 61), 3, (8, 6)),
+         ("gray75x50", lambda: _ragged_pair(6, 75, 50, C=1), 2, (5,)),
+         ("tiny13x9", lambda: _ragged_pair(7, 13, 9), 1, (3,))]
+
+
+@pytest.mark.parametrize("name,make,k,radii", CASES, ids=[c[0] for c in CASES])
+def test_descriptors_bit_exact(ff, name, make, k, radii):
+    p = make()
+    _say("descriptors", name, p.img1.shape)
+    d, blob = _gpu_desc(ff, p.img1, k, radii)
+    torch.cuda.synchronize()
+    v = ff.blob_views(d, blob)
+    o = ffo.Desc(p.img1, k, Q, radii)
+    assert np.array_equal(v["lab"].cpu().numpy(), o.lab())
+    for lev in range(k + 1):
+        assert np.array_equal(v["smooth"][lev].cpu().numpy(), o.smooth(lev)), f"smooth level {lev}"
+        cen = v["census"][lev].cpu().numpy().view(np.uint32)
+        for b in range(Q):
+            for a in range(Q):
+                assert np.array_equal(cen[b, a], o.plane(lev, a, b)), f"census level {lev} phase {(a, b)}"
+    for rho in radii:
+        g = v["wht"][rho].cpu().numpy()[:, :, :9 * d.channels]
+        assert np.array_equal(g, o.wht(rho)), f"wht {rho}"
+
+
+def test_lab8_all_24bit_colours(ff):
+    _say("lab8 exhaustive")
+    v = np.arange(1 << 24, dtype=np.uint32)
+    img = np.stack([(v >> 16) & 255, (v >> 8) & 255, v & 255], -1).astype(np.uint8).reshape(4, 1024, 4096, 3)
+    # four 4096 x 1024 images (the library's limit is 2^22 pixels per image)
+    d = ff.ff_desc_init(4096, 1024, 3, 0, 1, ())
+    blob = torch.zeros(d.bytes, dtype=torch.uint8, device="cuda")
+    for i in range(4):
+        ff.ff_compute_descriptors(d, _dev(img[i]), blob)
+        got = ff.blob_views(d, blob)["lab"].cpu().numpy()
+        assert np.array_equal(got, ffo.lab8(img[i])), f"quarter {i}"
+
+
+@pytest.mark.parametrize("W,H,rho", [(128, 96, 8), (320, 240, 6), (61, 37, 3)])
+def test_kdtree_bit_exact(ff, W, H, rho):
+    _say("kdtree", W, H, rho)
+    p = _ragged_pair(W + H, W, H)
+    d, blob = _gpu_desc(ff, p.img2, 0, (rho,))
+    N = W * H
+    leaf = 8
+    nn = ff.ff_tree_nodes(N, leaf)
+    nd = torch.empty(nn, dtype=torch.int32, device="cuda")
+    ns = torch.empty(nn, dtype=torch.int32, device="cuda")
+    perm = torch.empty(N, dtype=torch.int32, device="cuda")
+    prm = ff.ff_default_params(k=0, leaf=leaf)
+    ws = torch.empty(ff.ff_match_workspace_bytes(d, d, rho, prm), dtype=torch.uint8, device="cuda")
+    ff.ff_build_kdtree(d, blob, rho, leaf, nd, ns, perm, ws)
+    torch.cuda.synchronize()
+    V = ffo.Desc(p.img2, 0, Q, (rho,)).wht(rho).reshape(N, -1)
+    rnd, rns, rperm = ffo.kdtree_build(V, leaf)
+    nd, ns, perm = nd.cpu().numpy(), ns.cpu().numpy(), perm.cpu().numpy()
+    assert np.array_equal(nd, rnd)
+    internal = rnd >= 0
+    assert np.array_equal(ns[internal], rns[internal])
+    assert np.array_equal(perm, rperm)
+
+
+def _gpu_field(ff, d1, b1, d2, b2, r, **kw):
+    prop = kw.pop("proposal", None)
+    prm = ff.ff_default_params(**kw)
+    ws = torch.empty(ff.ff_match_workspace_bytes(d1, d2, r, prm), dtype=torch.uint8, device="cuda")
+    F = torch.empty((d1.height, d1.width), dtype=torch.int32, device="cuda")
+    Cc = torch.empty_like(F)
+    ff.ff_match_field(d1, b1, d2, b2, r, prm, prop, F, Cc, ws)
+    torch.cuda.synchronize()
+    assert ff.ff_read_status(ws) == 0
+    return F.cpu().numpy(), Cc.cpu().numpy()
+
+
+def test_field_every_step_config0(ff):
+    p = pairs.config0_pair(0)
+    k, r = 3, 8
+    d1, b1 = _gpu_desc(ff, p.img1, k, (r,))
+    d2, b2 = _gpu_desc(ff, p.img2, k, (r,))
+    o1, o2 = ffo.Desc(p.img1, k, Q, (r,)), ffo.Desc(p.img2, k, Q, (r,))
+    for s in range(1, 1 + 7 + 8 * k + 1):
+        _say("step", s)
+        gF, gC = _gpu_field(ff, d1, b1, d2, b2, r, k=k, max_steps=s, seed=17)
+        oF, oC = ffo.match_field(o1, o2, r, k=k, max_steps=s, seed=17)
+        assert np.array_equal(gF, oF), f"flow differs after step {s}: {(gF != oF).sum()} px"
+        assert np.array_equal(gC, oC), f"cost differs after step {s}"
+
+
+@pytest.mark.parametrize("name,make,k,radii", CASES, ids=[c[0] for c in CASES])
+def test_whole_pair_bit_exact(ff, name, make, k, radii):
+    p = make()
+    _say("pair", name)
+    r = radii[0]
+    r2 = radii[1] if len(radii) > 1 else radii[0]
+    H, W = p.img1.shape[:2]
+    Cc = 1 if p.img1.ndim == 2 else p.img1.shape[2]
+    m = ff.PairMatcher(W, H, Cc, r=r, r2=r2, k=k, subpel=Q, eps=5, n_bwd=2 if len(radii) > 1 else 1)
+    out = m.run(_dev(p.img1), _dev(p.img2), seed=1234, pair_id=3)
+    torch.cuda.synchronize()
+    assert m.status() == [0] * len(m.fields)
+    ref = ffo.match_pair(p.img1, p.img2, r=r, r2=r2, k=k, Q=Q, eps=5, seed=1234, pair_id=3,
+                         n_bwd=2 if len(radii) > 1 else 1)
+    for key in ("F", "CF", "B1", "CB1", "keep", "filtered") + (("B2", "CB2") if len(radii) > 1 else ()):
+        assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
+
+
+def test_proposal_paths(ff):
+    p = pairs.config0_pair(2)
+    k, r = 3, 8
+    d1, b1 = _gpu_desc(ff, p.img1, k, (r,))
+    d2, b2 = _gpu_desc(ff, p.img2, k, (r,))
+    o1, o2 = ffo.Desc(p.img1, k, Q, (r,)), ffo.Desc(p.img2, k, Q, (r,))
+    rng = np.random.default_rng(0)
+    prop = ffo.pack(rng.integers(-200, 200, (12, 16)), rng.integers(-100, 100, (12, 16)))
+    prop[rng.random((12, 16)) < 0.3] = ffo.EMPTY
+    for use_tree in (1, 0):
+        _say("proposal use_tree", use_tree)
+        gF, gC = _gpu_field(ff, d1, b1, d2, b2, r, k=k, seed=5, use_kdtree=use_tree, proposal=_dev(prop))
+        oF, oC = ffo.match_field(o1, o2, r, k=k, seed=5, use_kdtree=bool(use_tree), proposal=prop)
+        assert np.array_equal(gF, oF) and np.array_equal(gC, oC)
+
+
+def test_repeat_runs_identical(ff):
+    """Schedule/race check: the wavefront's inter-band waits decide the
+    result; repeated runs on a larger field must give the same bytes."""
+    p = _ragged_pair(9, 256, 200, nlayers=4)
+    k, r = 3, 8
+    d1, b1 = _gpu_desc(ff, p.img1, k, (r,))
+    d2, b2 = _gpu_desc(ff, p.img2, k, (r,))
+    base = _gpu_field(ff, d1, b1, d2, b2, r, k=k, seed=3)
+    for i in range(4):
+        _say("repeat", i)
+        got = _gpu_field(ff, d1, b1, d2, b2, r, k=k, seed=3)
+        assert np.array_equal(got[0], base[0]) and np.array_equal(got[1], base[1])
+    o1, o2 = ffo.Desc(p.img1, k, Q, (r,)), ffo.Desc(p.img2, k, Q, (r,))
+    oF, oC = ffo.match_field(o1, o2, r, k=k, seed=3)
+    assert np.array_equal(base[0], oF) and np.array_equal(base[1], oC)
