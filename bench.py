@@ -1,0 +1,161 @@
+#!/usr/bin/env python
+"""Benchmark of the Flow Fields hot path on one MI355X.
+
+One step = the whole path on one 1024x436 RGB pair (Sintel-shaped synthetic
+pair, seeded): descriptors of both images, the three fields F = I1->I2 (r=8),
+B1 = I2->I1 (r=8), B2 = I2->I1 (r2=6) each with its kd-tree, and the two-way
+consistency filter (sections 3.1-3.4, parameters of section 4: k=3, R=1,
+l=8, eps=5).  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line with the throughput (Mpixel/s = W*H / time per pair),
+the dominant kernel's measured rate against its roofline and the CPU oracle
+timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks and chip figures
+HBM_PEAK_GBS = 8000.0
+CUS, LANES_PER_CU, CLOCK_GHZ = 256, 64, 2.4
+INT_PEAK_TOPS = CUS * LANES_PER_CU * CLOCK_GHZ / 1000.0   # 32-bit integer VALU ops, 39.3 T/s
+
+PROF_CLASS = {"descriptors": 1, "tree": 2, "seed": 3, "level_entry": 4, "propagate": 5, "random_search": 6,
+              "filter": 7}
+
+
+def grid_points(W, H, k):
+    return [((W + (1 << l) - 1) >> l) * ((H + (1 << l) - 1) >> l) for l in range(k + 1)]
+
+
+def propagate_ops_per_pair(W, H, k, radii, n_prop=4):
+    """Algorithmic integer ops of all propagation sweeps of one pair: per grid
+    point and sweep, two candidates costed by sliding windows, each 2(2r+1)
+    census terms of one XOR and one popcount-accumulate (2 ops)."""
+    pts = sum(grid_points(W, H, k))
+    return sum(n_prop * pts * 2 * 2 * (2 * r + 1) * 2 for r in radii)
+
+
+def cpu_sample(budget_s, crop_w, crop_h):
+    """The oracle (plain single-threaded C++) on the same hot path over a
+    crop of the benchmark pair; returns Mpixel/s of that sample."""
+    from oracle import ffo
+    from synth import pairs
+    p = pairs.config1_pair(1000)
+    i1 = p.img1[:crop_h, :crop_w].copy()
+    i2 = p.img2[:crop_h, :crop_w].copy()
+    t0 = time.perf_counter()
+    ffo.match_pair(i1, i2, r=8, r2=6, k=3, Q=4, eps=5, seed=1000)
+    dt = time.perf_counter() - t0
+    return crop_w * crop_h / dt / 1e6, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--crop", default="256x128", help="CPU baseline sample: crop WxH of the pair")
+    ap.add_argument("--dominant", default="propagate", choices=sorted(PROF_CLASS))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: each pair is matched on one MI355X; "
+                                   "--gpus must be 1"}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1508_05151_amd import ff
+    from synth import pairs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    pair = pairs.config1_pair(1000)
+    H, W, C = pair.img1.shape
+    k, r, r2, Q, eps = 3, 8, 6, 4, 5
+    img1 = torch.from_numpy(pair.img1).to(dev)
+    img2 = torch.from_numpy(pair.img2).to(dev)
+    ff.ff_init()
+    m = ff.PairMatcher(W, H, C, r=r, r2=r2, k=k, subpel=Q, eps=eps)
+    for _ in range(args.warmup):
+        m.run(img1, img2, seed=1000)
+    torch.cuda.synchronize()
+    assert m.status() == [0, 0, 0], m.status()
+
+    # timed region: K whole-path steps; the dominant kernel class is bracketed
+    # with HIP events on the streams it runs on (library profiling hook)
+    launches_per_step = {"propagate": 3 * (k + 1) * 4, "random_search": 3 * (k + 1) * 3, "descriptors": 2,
+                         "tree": 3, "seed": 3, "level_entry": 3 * k, "filter": 1}[args.dominant]
+    ff._check(ff.lib().ff_profile_begin(PROF_CLASS[args.dominant], launches_per_step * args.steps + 8),
+              "ff_profile_begin")
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record()
+        out = m.run(img1, img2, seed=1000)
+        ends[i].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    import ctypes
+    tot = ctypes.c_double(0)
+    nl = ctypes.c_int32(0)
+    ff._check(ff.lib().ff_profile_end(ctypes.byref(tot), ctypes.byref(nl)), "ff_profile_end")
+    assert m.status() == [0, 0, 0], m.status()
+    per_step = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    value = W * H / (ms_per_step / 1000.0) / 1e6
+
+    # dominant kernel against its roofline (integer VALU: census terms)
+    avg_launch_ms = tot.value / max(nl.value, 1)
+    roof = None
+    if args.dominant == "propagate":
+        ops_per_launch = propagate_ops_per_pair(W, H, k, (r, r, r2)) / launches_per_step
+        achieved = ops_per_launch / (avg_launch_ms / 1000.0) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(INT_PEAK_TOPS, 2), "unit": "TOP/s",
+                "frac": round(achieved / INT_PEAK_TOPS, 5), "traffic": None,
+                "kernel": "k_propagate", "avg_launch_ms": round(avg_launch_ms, 4), "launches": nl.value,
+                "ops_per_launch": int(ops_per_launch)}
+
+    keep = out["keep"].float().mean().item()
+    rate = pairs.inlier_rate(out["F"].cpu().numpy(), pair, Q)
+    line = {
+        "metric": "flow-field Mpixel/s at 1024x436 (plain)",
+        "value": round(value, 3),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "median_ms_per_step": round(statistics.median(per_step), 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "one 1024x436 RGB pair (config 1 recipe, seed 1000): descriptors x2, "
+                               "F/B1/B2 fields with kd-trees, two-way consistency filter",
+                   "k": k, "r": r, "r2": r2, "R": 1, "leaf": 8, "subpel": Q, "eps": eps},
+        "roofline": roof,
+        "quality": {"F_inlier_rate_epe_lt_3px": round(rate, 4), "kept_fraction": round(keep, 4)},
+    }
+    if not args.no_cpu:
+        cw, ch = (int(v) for v in args.crop.split("x"))
+        mpx, dt = cpu_sample(30.0, cw, ch)
+        line["cpu_baseline"] = {"value": round(mpx, 5), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+                                "sample": f"whole hot path on the top-left {cw}x{ch} crop of the same pair "
+                                          f"({cw * ch} px, {dt:.1f} s single-threaded)"}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

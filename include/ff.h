@@ -66,6 +66,8 @@ typedef struct {
  *            patch of Eq. 3), on I^n shifted by the subpixel phase (a/Q, b/Q)
  *            with bilinear weights (section 3.1); byte c = channel c;
  *            plane index = level * Q*Q + b*Q + a;
+ *  - census_t: the same planes transposed (W rows of H words), so that the
+ *            column walks of the propagation read contiguous words;
  *  - wht:    n_radii blocks of H*W vectors of wht_stride int32: the first 9
  *            Walsh-Hadamard projections per channel of the patch of radius
  *            rho (section 3.1; odd extents split into rho and rho+1).
@@ -75,8 +77,8 @@ typedef struct {
   int32_t radii[FF_MAX_RADII];
   int32_t wht_dims;    /* 9 * channels */
   int32_t wht_stride;  /* int32 words per WHT vector (32 for RGB, 16 gray) */
-  size_t off_lab, off_smooth, off_census, off_wht;
-  size_t plane_bytes;  /* H*W*4, the census plane pitch */
+  size_t off_lab, off_smooth, off_census, off_census_t, off_wht;
+  size_t plane_bytes;  /* H*W*4, the census plane pitch (both layouts) */
   size_t bytes;        /* total device bytes of the blob */
 } ff_desc;
 
@@ -172,6 +174,27 @@ ff_status ff_build_kdtree(const ff_desc* d, const void* blob, int32_t radius, in
 ff_status ff_read_status(const void* workspace, int32_t* status_host);
 
 const char* ff_status_string(ff_status s);
+
+/*
+ * Profiling hook (measurement only; not used on the search path).  Arm one
+ * kernel class: every later launch of it (for the multi-kernel classes, every
+ * launch sequence) is bracketed by two HIP events recorded on the stream it
+ * runs on, for up to max_launches launches.  ff_profile_begin creates the
+ * events (host allocation: call it outside any capture or timed loop);
+ * ff_profile_end waits for them, returns the summed elapsed milliseconds and
+ * the number of launches, destroys the events and disarms the hook.
+ */
+typedef enum {
+  FF_PROF_DESCRIPTORS = 1,   /* the whole ff_compute_descriptors sequence */
+  FF_PROF_TREE = 2,          /* the kd-tree build sequence of a match */
+  FF_PROF_SEED = 3,
+  FF_PROF_LEVEL_ENTRY = 4,
+  FF_PROF_PROPAGATE = 5,     /* one propagation sweep kernel */
+  FF_PROF_RANDOM_SEARCH = 6,
+  FF_PROF_FILTER = 7
+} ff_prof_class;
+ff_status ff_profile_begin(int32_t kernel_class, int32_t max_launches);
+ff_status ff_profile_end(double* total_ms, int32_t* launches);
 
 #ifdef __cplusplus
 }

@@ -249,6 +249,24 @@ __global__ void k_census(const int16_t* __restrict__ S, int W, int H, int C, int
   for (int i = 0; i < Q * Q; ++i) out[i * plane_words + o] = word[i];
 }
 
+// 32x32 tiled transpose of every census plane (LDS tile, padded against
+// bank conflicts): out[p][x][y] = in[p][y][x]
+__global__ __launch_bounds__(256) void k_transpose(const uint32_t* __restrict__ in, int W, int H,
+                                                   uint32_t* __restrict__ out) {
+  __shared__ uint32_t tile[32][33];
+  const size_t plane = (size_t)blockIdx.z * W * H;
+  const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+  for (int i = threadIdx.y; i < 32; i += 8) {
+    const int x = x0 + threadIdx.x, y = y0 + i;
+    if (x < W && y < H) tile[i][threadIdx.x] = in[plane + (size_t)y * W + x];
+  }
+  __syncthreads();
+  for (int i = threadIdx.y; i < 32; i += 8) {
+    const int y = y0 + threadIdx.x, x = x0 + i;
+    if (x < W && y < H) out[plane + (size_t)x * H + y] = tile[threadIdx.x][i];
+  }
+}
+
 // ---------------------------------------------------------------- WHT
 // 1-D Walsh functions in sequency order on [-rho, rho]; odd extents split
 // rho | rho+1, the second split puts the smaller part first.
@@ -357,6 +375,8 @@ ff_status ff_desc_init(ff_desc* d, const ff_image* img, int32_t k, int32_t subpe
   if (sm > scratch) scratch = sm;
   if (scratch > census) census = scratch;
   off = align_up(off + census, 256);
+  d->off_census_t = off;
+  off = align_up(off + (size_t)(k + 1) * subpel * subpel * N * 4, 256);
   d->off_wht = off;
   off = align_up(off + (size_t)n_radii * N * d->wht_stride * 4, 256);
   d->bytes = off;
@@ -381,6 +401,7 @@ ff_status ff_compute_descriptors(const ff_desc* d, const ff_image* img, const ui
   const dim3 tb(256);
   const unsigned gx = (unsigned)((W + 255) / 256);
 
+  prof_mark(FF_PROF_DESCRIPTORS, stream, true);
   k_lab8<<<dim3(gx, H), tb, 0, stream>>>(pixels, W, H, C, img->row_stride, lab);
   k_scale16<<<(unsigned)((C * N + 255) / 256), tb, 0, stream>>>(lab, smooth, C * N);
   for (int lev = 1; lev <= d->k; ++lev) {
@@ -410,6 +431,12 @@ ff_status ff_compute_descriptors(const ff_desc* d, const ff_image* img, const ui
       default: k_census<8><<<dim3(gx, H), tb, 0, stream>>>(S, W, H, C, n, out, pw); break;
     }
   }
+  {
+    const unsigned planes = (unsigned)((d->k + 1) * d->subpel * d->subpel);
+    k_transpose<<<dim3((W + 31) / 32, (H + 31) / 32, planes), dim3(32, 8), 0, stream>>>(
+        reinterpret_cast<const uint32_t*>(base + d->off_census), W, H, reinterpret_cast<uint32_t*>(base + d->off_census_t));
+  }
+  prof_mark(FF_PROF_DESCRIPTORS, stream, false);
   return launch_status();
 }
 

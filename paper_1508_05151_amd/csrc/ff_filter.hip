@@ -55,7 +55,9 @@ extern "C" ff_status ff_consistency_filter(const int32_t* flow_fwd, int32_t w1, 
     if (!flow_bwd[j]) return FF_ERR_ARG;
     B.p[j] = flow_bwd[j];
   }
+  prof_mark(FF_PROF_FILTER, stream, true);
   k_consistency<<<dim3((w1 + 255) / 256, h1), 256, 0, stream>>>(flow_fwd, w1, h1, B, n_bwd, w2, h2, ilog2i(subpel),
                                                                (int64_t)eps_q * eps_q, keep, flow_filtered);
+  prof_mark(FF_PROF_FILTER, stream, false);
   return launch_status();
 }

@@ -53,6 +53,10 @@ inline const uint32_t* census_plane(const ff_desc* d, const void* blob, int lev,
   return reinterpret_cast<const uint32_t*>(static_cast<const char*>(blob) + d->off_census +
                                            d->plane_bytes * ((size_t)lev * d->subpel * d->subpel + b * d->subpel + a));
 }
+inline const uint32_t* census_plane_t(const ff_desc* d, const void* blob, int lev, int a, int b) {
+  return reinterpret_cast<const uint32_t*>(static_cast<const char*>(blob) + d->off_census_t +
+                                           d->plane_bytes * ((size_t)lev * d->subpel * d->subpel + b * d->subpel + a));
+}
 inline const int32_t* wht_block(const ff_desc* d, const void* blob, int radius) {
   for (int i = 0; i < d->n_radii; ++i)
     if (d->radii[i] == radius)
@@ -67,4 +71,11 @@ ff_status launch_status();   // maps hipGetLastError to FF_ERR_HIP
 // fill a device int32 buffer with a value (graph-safe: a kernel, no memset)
 void fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t s);
 
+}  // namespace ff
+
+namespace ff {
+// Profiling hook: when a kernel class is armed with ff_profile_begin, each
+// launch (or launch sequence) of that class is bracketed by two events on its
+// stream.  prof_mark is a no-op otherwise.
+void prof_mark(int kernel_class, hipStream_t stream, bool start);
 }  // namespace ff

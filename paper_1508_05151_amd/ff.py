@@ -38,7 +38,8 @@ class ff_desc(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("channels", C.c_int32), ("k", C.c_int32),
                 ("subpel", C.c_int32), ("n_radii", C.c_int32), ("radii", C.c_int32 * MAX_RADII),
                 ("wht_dims", C.c_int32), ("wht_stride", C.c_int32), ("off_lab", C.c_size_t),
-                ("off_smooth", C.c_size_t), ("off_census", C.c_size_t), ("off_wht", C.c_size_t),
+                ("off_smooth", C.c_size_t), ("off_census", C.c_size_t), ("off_census_t", C.c_size_t),
+                ("off_wht", C.c_size_t),
                 ("plane_bytes", C.c_size_t), ("bytes", C.c_size_t)]
 
 
@@ -181,11 +182,12 @@ def blob_views(d: ff_desc, blob: torch.Tensor):
     lab = blob[d.off_lab:d.off_lab + Cc * N].view(Cc, H, W)
     smooth = blob[d.off_smooth:d.off_smooth + (K + 1) * Cc * N * 2].view(torch.int16).view(K + 1, Cc, H, W)
     census = blob[d.off_census:d.off_census + (K + 1) * Q * Q * N * 4].view(torch.int32).view(K + 1, Q, Q, H, W)
+    census_t = blob[d.off_census_t:d.off_census_t + (K + 1) * Q * Q * N * 4].view(torch.int32).view(K + 1, Q, Q, W, H)
     whts = {}
     for i in range(d.n_radii):
         o = d.off_wht + i * N * d.wht_stride * 4
         whts[d.radii[i]] = blob[o:o + N * d.wht_stride * 4].view(torch.int32).view(H, W, d.wht_stride)
-    return dict(lab=lab, smooth=smooth, census=census, wht=whts)
+    return dict(lab=lab, smooth=smooth, census=census, census_t=census_t, wht=whts)
 
 
 class PairMatcher:

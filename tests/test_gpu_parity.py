@@ -70,9 +70,12 @@ def test_descriptors_bit_exact(ff, name, make, k, radii):
     for lev in range(k + 1):
         assert np.array_equal(v["smooth"][lev].cpu().numpy(), o.smooth(lev)), f"smooth level {lev}"
         cen = v["census"][lev].cpu().numpy().view(np.uint32)
+        cent = v["census_t"][lev].cpu().numpy().view(np.uint32)
         for b in range(Q):
             for a in range(Q):
-                assert np.array_equal(cen[b, a], o.plane(lev, a, b)), f"census level {lev} phase {(a, b)}"
+                ref = o.plane(lev, a, b)
+                assert np.array_equal(cen[b, a], ref), f"census level {lev} phase {(a, b)}"
+                assert np.array_equal(cent[b, a], ref.T), f"transposed census level {lev} phase {(a, b)}"
     for rho in radii:
         g = v["wht"][rho].cpu().numpy()[:, :, :9 * d.channels]
         assert np.array_equal(g, o.wht(rho)), f"wht {rho}"
