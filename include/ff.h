@@ -95,7 +95,8 @@ typedef struct {
                          level) and write the current grid -- for inspection */
   uint32_t field_id;  /* 0..3, part of the random-search counter */
   uint32_t pair_id;   /* part of the random-search counter */
-  uint32_t reserved;
+  int32_t band_rows;  /* propagation band height: 8, 16 (default) or 32 rows per
+                         workgroup; results are identical for every value */
   uint64_t seed;      /* Philox key */
 } ff_match_params;
 
@@ -140,6 +141,34 @@ size_t ff_match_workspace_bytes(const ff_desc* src, const ff_desc* dst, int32_t 
 ff_status ff_match_field(const ff_desc* src, const void* src_blob, const ff_desc* dst, const void* dst_blob,
                          int32_t radius, const ff_match_params* p, const int32_t* proposal, int32_t* flow,
                          int32_t* cost, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * Batched matching: many fields (of pairs of any sizes) in one call, every
+ * stage launched once for all of them.  One job = one ff_match_field call's
+ * arguments; p supplies the shared parameters (k, R, leaf, n_prop, n_rs,
+ * use_kdtree, max_steps, band_rows) and each job its own radius, field_id,
+ * pair_id, seed and proposal.  All descriptors must share subpel.  Each job's
+ * flow/cost equal, byte for byte, what ff_match_field gives for it alone.
+ * jobs: host array (read during the call only); workspace: device,
+ * ff_match_batch_workspace_bytes() bytes.
+ */
+typedef struct {
+  const ff_desc* src;      /* host */
+  const void* src_blob;    /* device */
+  const ff_desc* dst;      /* host */
+  const void* dst_blob;    /* device */
+  int32_t radius;
+  uint32_t field_id, pair_id;
+  uint32_t reserved;
+  uint64_t seed;
+  const int32_t* proposal; /* device, nullable */
+  int32_t* flow;           /* device, src H*W */
+  int32_t* cost;           /* device, src H*W */
+} ff_field_job;
+
+size_t ff_match_batch_workspace_bytes(const ff_field_job* jobs, int32_t n_jobs, const ff_match_params* p);
+ff_status ff_match_batch(const ff_field_job* jobs, int32_t n_jobs, const ff_match_params* p, void* workspace,
+                         size_t workspace_bytes, hipStream_t stream);
 
 /*
  * Eq. 5 (section 3.4): two-way forward/backward consistency check.  Keep p iff

@@ -43,10 +43,35 @@ struct TreeLayout {
 TreeLayout tree_layout(int N, int leaf, size_t base);
 int tree_depth_of(int N, int leaf);
 
-// Builds the tree over V (N x stride int32, D dims) into the workspace
-// regions of `L` (and optionally copies nothing else).  Enqueues only.
-ff_status enqueue_tree_build(const int32_t* V, int N, int D, int stride, int leaf, const TreeLayout& L,
-                             char* ws, hipStream_t stream);
+// Device record of one field of a match call (src -> dst, patch radius r).
+// Kernels of every stage read it, so one launch serves all fields of a batch.
+struct FieldRec {
+  const uint32_t* src;   // source census planes (level 0, phase 0); level l at + l Q^2 pws
+  const uint32_t* srcT;  // the same, transposed
+  const uint32_t* dst;   // target census planes
+  const uint32_t* dstT;
+  const int32_t* Vsrc;   // WHT vectors of this radius (tree queries / tree keys)
+  const int32_t* Vdst;
+  const int32_t* proposal;
+  int32_t* flow;         // outputs (also the level-1 grid)
+  int32_t* cost;
+  char* ws;              // this field's workspace region
+  uint32_t pws, pwd;     // plane words of source / target
+  int32_t Ws, Hs, Wd, Hd;
+  int32_t r, D, vstride, pad0;
+  uint32_t k0, k1, c3, pad1;
+  // kd-tree over the target (offsets into ws)
+  int32_t t_nodes, t_top, pad2, pad3;
+  uint32_t o_dim, o_split, o_perm, o_perm2, o_mm, o_hist, o_cnt, pad4;
+  // level grids n = 2..2^k (flow then cost) and the band handoff words
+  uint32_t o_grid[5];
+  uint32_t o_xch;
+  uint32_t pad5[2];
+};
+
+// Enqueue the kd-tree builds of `nf` fields whose records are in `table`
+// (device).  maxN / maxTop bound the launch geometry.
+ff_status enqueue_tree_build(const FieldRec* table, int nf, int maxN, int maxTop, int leaf, hipStream_t stream);
 
 // ---------------------------------------------------------------- descriptors
 inline const uint32_t* census_plane(const ff_desc* d, const void* blob, int lev, int a, int b) {

@@ -16,64 +16,58 @@
 // with sliding windows: E(p, F(q)) = C(q) - (row or column leaving the patch)
 // + (row or column entering it), 2(2r+1) terms instead of (2r+1)^2, exact
 // because every sample lookup clamps per coordinate.
+#include <algorithm>
+#include <vector>
+
 #include "ff_internal.h"
 
 namespace ff {
 
-constexpr int kBandRows = 16;     // BH: grid rows per propagation workgroup
 constexpr int kLanesProp = 16;    // lanes per point in the propagation sweep
 constexpr int kLanesPt = 16;      // lanes per point in recost / random search
 constexpr int kStatusBytes = 256;
+constexpr int kMinBandRows = 8;   // smallest band height (sizes the handoff buffer)
+constexpr int kRecsPerWrite = 16; // table records per writer launch (kernel argument size)
 
-// ---------------------------------------------------------------- layout
-struct MatchLayout {
-  TreeLayout tree;
-  bool has_tree;
-  size_t off_grid[5];     // per level 1..k: flow then cost (level 0 = outputs)
-  size_t off_sync;        // per propagation launch: its band ticket
-  size_t off_xch;         // band handoff words, bands x Gw (largest level)
-  size_t xch_words;
-  int launches;
-  size_t bytes;
-};
-
-static MatchLayout match_layout(const ff_desc* src, const ff_desc* dst, const ff_match_params* p) {
-  MatchLayout M{};
-  size_t off = kStatusBytes;
-  M.has_tree = p->use_kdtree != 0;
-  if (M.has_tree) {
-    M.tree = tree_layout(dst->width * dst->height, p->leaf, off);
-    off += M.tree.bytes;
-  }
-  for (int lev = 1; lev <= p->k; ++lev) {
-    const int n = 1 << lev;
-    const size_t G = (size_t)((src->width + n - 1) / n) * ((src->height + n - 1) / n);
-    off = align_up(off, 256);
-    M.off_grid[lev] = off;
-    off += G * 8;
-  }
-  off = align_up(off, 256);
-  M.off_sync = off;
-  M.launches = (p->k + 1) * p->n_prop;
-  off = align_up(off + (size_t)M.launches * 4, 256);
-  M.off_xch = off;
-  M.xch_words = (size_t)((src->height + kBandRows - 1) / kBandRows) * src->width;
-  off += M.xch_words * 8;
-  M.bytes = align_up(off, 256);
-  return M;
-}
-
-// ---------------------------------------------------------------- device helpers
+// ---------------------------------------------------------------- per-field cost context
 struct CostCtx {
   const uint32_t* src;   // source plane, level n, phase (0,0)
   const uint32_t* dst;   // target planes of level n (phase i at dst + i * pw)
   const uint32_t* srcT;  // the same, transposed (x-major, pitch Hs / Hd)
   const uint32_t* dstT;
-  size_t pw;
+  uint32_t pw;           // target plane words
   int Ws, Hs, Wd, Hd;
   int qshift, qmask, Q;
   int n, r;
 };
+
+__device__ __forceinline__ CostCtx ctx_of(const FieldRec& f, int lev, int qshift) {
+  CostCtx c;
+  const int Q = 1 << qshift;
+  c.src = f.src + (size_t)lev * Q * Q * f.pws;
+  c.srcT = f.srcT + (size_t)lev * Q * Q * f.pws;
+  c.dst = f.dst + (size_t)lev * Q * Q * f.pwd;
+  c.dstT = f.dstT + (size_t)lev * Q * Q * f.pwd;
+  c.pw = f.pwd;
+  c.Ws = f.Ws;
+  c.Hs = f.Hs;
+  c.Wd = f.Wd;
+  c.Hd = f.Hd;
+  c.Q = Q;
+  c.qshift = qshift;
+  c.qmask = Q - 1;
+  c.n = 1 << lev;
+  c.r = f.r;
+  return c;
+}
+
+// level grids: n = 1 is the output pair itself
+__device__ __forceinline__ int32_t* grid_flow(const FieldRec& f, int lev) {
+  return lev == 0 ? f.flow : reinterpret_cast<int32_t*>(f.ws + f.o_grid[lev]);
+}
+__device__ __forceinline__ int32_t* grid_cost(const FieldRec& f, int lev, int G) {
+  return lev == 0 ? f.cost : reinterpret_cast<int32_t*>(f.ws + f.o_grid[lev]) + G;
+}
 
 // Philox4x32-10 (Salmon et al., SC 2011): 10 rounds of the two multiplier
 // S-boxes with Weyl-sequence key schedule.  Returns the first two words.
@@ -109,7 +103,7 @@ __device__ __forceinline__ bool centre_valid(const CostCtx& c, int px, int py, i
 __device__ __forceinline__ int32_t patch_partial(const CostCtx& c, int px, int py, int fx, int fy, int lane, int L) {
   const int mx = px * c.Q + fx, my = py * c.Q + fy;
   const int Mx = mx >> c.qshift, My = my >> c.qshift;
-  const uint32_t* D2 = c.dst + c.pw * (size_t)(((my & c.qmask) << c.qshift) + (mx & c.qmask));
+  const uint32_t* D2 = c.dst + (size_t)c.pw * (size_t)(((my & c.qmask) << c.qshift) + (mx & c.qmask));
   const int S = 2 * c.r + 1;
   int dy = lane / S, dx = lane - dy * S;
   const int stepy = L / S, stepx = L - stepy * S;
@@ -145,15 +139,32 @@ __device__ __forceinline__ int32_t row16_sum(int32_t v) {
   return v;
 }
 
+// ---------------------------------------------------------------- field table
+struct RecChunk {
+  FieldRec r[kRecsPerWrite];
+};
+
+__global__ void k_write_table(RecChunk chunk, int n, FieldRec* __restrict__ out) {
+  if ((int)threadIdx.x < n) out[threadIdx.x] = chunk.r[threadIdx.x];
+}
+
+// zero every field's band handoff words (grid: chunks x fields)
+__global__ void k_clear_xch(const FieldRec* __restrict__ table, int bands_rows) {
+  const FieldRec& f = table[blockIdx.y];
+  uint64_t* x = reinterpret_cast<uint64_t*>(f.ws + f.o_xch);
+  const size_t nw = (size_t)((f.Hs + bands_rows - 1) / bands_rows) * f.Ws;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += (size_t)gridDim.x * blockDim.x) x[i] = 0;
+}
+
 // ---------------------------------------------------------------- seeds (Eq. 1 / Eq. 4)
 // One wavefront per coarse grid point: descend the kd-tree with the source
 // patch's WHT vector, then re-rank the leaf (ascending pixel index) and the
 // optional proposal by the data term; the first minimum wins.
-__global__ __launch_bounds__(256) void k_seed(CostCtx c, int Gw, int Gh, const int32_t* __restrict__ Vsrc, int vstride,
-                                              const int32_t* __restrict__ node_dim, const int32_t* __restrict__ node_split,
-                                              const int32_t* __restrict__ perm, int Nd, int n_nodes, int use_tree,
-                                              const int32_t* __restrict__ proposal, int32_t* __restrict__ F,
-                                              int32_t* __restrict__ C) {
+// grid: (points / 4, fields)
+__global__ __launch_bounds__(256) void k_seed(const FieldRec* __restrict__ table, int lev, int qshift, int use_tree) {
+  const FieldRec& f = table[blockIdx.y];
+  const CostCtx c = ctx_of(f, lev, qshift);
+  const int Gw = (f.Ws + c.n - 1) >> lev, Gh = (f.Hs + c.n - 1) >> lev;
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (wave >= Gw * Gh) return;
@@ -161,11 +172,15 @@ __global__ __launch_bounds__(256) void k_seed(CostCtx c, int Gw, int Gh, const i
   const int px = gx * c.n, py = gy * c.n;
   int32_t bestF = kEmpty, bestC = kInf;
   if (use_tree) {
-    const int32_t* q = Vsrc + ((size_t)py * c.Ws + px) * vstride;
+    const int32_t* node_dim = reinterpret_cast<const int32_t*>(f.ws + f.o_dim);
+    const int32_t* node_split = reinterpret_cast<const int32_t*>(f.ws + f.o_split);
+    const int32_t* perm = reinterpret_cast<const int32_t*>(f.ws + f.o_perm);
+    const int Nd = f.Wd * f.Hd;
+    const int32_t* q = f.Vsrc + ((size_t)py * c.Ws + px) * f.vstride;
     int node = 0, start = 0, cnt = Nd;
     for (;;) {
       const int dim = node_dim[node];
-      if (dim < 0 || 2 * node + 2 >= n_nodes) break;
+      if (dim < 0 || 2 * node + 2 >= f.t_nodes) break;
       const int h = cnt >> 1;
       if (q[dim] >= node_split[node]) { node = 2 * node + 2; start += h; cnt -= h; }
       else { node = 2 * node + 1; cnt = h; }
@@ -177,37 +192,42 @@ __global__ __launch_bounds__(256) void k_seed(CostCtx c, int Gw, int Gh, const i
       if (e < bestC) { bestC = e; bestF = packf(fx, fy); }
     }
   }
-  if (proposal) {
-    const int32_t fp = proposal[(size_t)gy * Gw + gx];
+  if (f.proposal) {
+    const int32_t fp = f.proposal[(size_t)gy * Gw + gx];
     if (fp != kEmpty && centre_valid(c, px, py, fx_of(fp), fy_of(fp))) {
       const int32_t e = group_sum<64>(patch_partial(c, px, py, fx_of(fp), fy_of(fp), lane, 64));
       if (e < bestC) { bestC = e; bestF = fp; }
     }
   }
   if (lane == 0) {
-    F[(size_t)gy * Gw + gx] = bestF;
-    C[(size_t)gy * Gw + gx] = bestC;
+    grid_flow(f, lev)[(size_t)gy * Gw + gx] = bestF;
+    grid_cost(f, lev, Gw * Gh)[(size_t)gy * Gw + gx] = bestC;
   }
 }
 
 // ---------------------------------------------------------------- level entry
 // Section 3.2: points of the coarser grid keep their flow and are re-costed
-// with this level's patch; new points start empty.
+// with this level's patch; new points start empty.  grid: (pts L / 256, fields)
 template <int L>
-__global__ __launch_bounds__(256) void k_level_entry(CostCtx c, int Gw, int Gh, const int32_t* __restrict__ Fc,
-                                                     int Gwc, int32_t* __restrict__ F, int32_t* __restrict__ C) {
+__global__ __launch_bounds__(256) void k_level_entry(const FieldRec* __restrict__ table, int lev, int qshift) {
+  const FieldRec& f = table[blockIdx.y];
+  const CostCtx c = ctx_of(f, lev, qshift);
+  const int Gw = (f.Ws + c.n - 1) >> lev, Gh = (f.Hs + c.n - 1) >> lev;
   const int pid = (blockIdx.x * blockDim.x + threadIdx.x) / L;
   const int lane = threadIdx.x % L;
   if (pid >= Gw * Gh) return;
+  const int Gwc = (f.Ws + 2 * c.n - 1) >> (lev + 1), Ghc = (f.Hs + 2 * c.n - 1) >> (lev + 1);
+  const int32_t* Fc = grid_flow(f, lev + 1);
   const int gx = pid % Gw, gy = pid / Gw;
-  int32_t f = kEmpty, e = kInf;
+  int32_t fl = kEmpty, e = kInf;
   if (!(gx & 1) && !(gy & 1)) {
-    f = Fc[(size_t)(gy >> 1) * Gwc + (gx >> 1)];
-    if (f != kEmpty) e = group_sum<L>(patch_partial(c, gx * c.n, gy * c.n, fx_of(f), fy_of(f), lane, L));
+    fl = Fc[(size_t)(gy >> 1) * Gwc + (gx >> 1)];
+    if (fl != kEmpty) e = group_sum<L>(patch_partial(c, gx * c.n, gy * c.n, fx_of(fl), fy_of(fl), lane, L));
   }
+  (void)Ghc;
   if (lane == 0) {
-    F[pid] = f;
-    C[pid] = e;
+    grid_flow(f, lev)[pid] = fl;
+    grid_cost(f, lev, Gw * Gh)[pid] = e;
   }
 }
 
@@ -216,22 +236,27 @@ __global__ __launch_bounds__(256) void k_level_entry(CostCtx c, int Gw, int Gh, 
 // [-nRQ, nRQ] 1/Q px, from Philox keyed by the seed with counter (pixel, level,
 // step, field | pair << 2); replace only on a strictly lower cost.
 template <int L>
-__global__ __launch_bounds__(256) void k_random_search(CostCtx c, int Gw, int Gh, int lev, int step, int rad,
-                                                       uint32_t c3, uint32_t k0, uint32_t k1, int32_t* __restrict__ F,
-                                                       int32_t* __restrict__ C) {
+__global__ __launch_bounds__(256) void k_random_search(const FieldRec* __restrict__ table, int lev, int qshift, int step,
+                                                       int R) {
+  const FieldRec& f = table[blockIdx.y];
+  const CostCtx c = ctx_of(f, lev, qshift);
+  const int Gw = (f.Ws + c.n - 1) >> lev, Gh = (f.Hs + c.n - 1) >> lev;
   const int pid = (blockIdx.x * blockDim.x + threadIdx.x) / L;
   const int lane = threadIdx.x % L;
   if (pid >= Gw * Gh) return;
-  const int32_t f = F[pid];
-  if (f == kEmpty) return;
+  int32_t* F = grid_flow(f, lev);
+  int32_t* C = grid_cost(f, lev, Gw * Gh);
+  const int32_t fl = F[pid];
+  if (fl == kEmpty) return;
   const int gx = pid % Gw, gy = pid / Gw;
   const int px = gx * c.n, py = gy * c.n;
+  const int rad = c.n * R * c.Q;
   uint32_t u0, u1;
-  philox2((uint32_t)(py * c.Ws + px), (uint32_t)lev, (uint32_t)step, c3, k0, k1, u0, u1);
+  philox2((uint32_t)(py * c.Ws + px), (uint32_t)lev, (uint32_t)step, f.c3, f.k0, f.k1, u0, u1);
   const uint64_t span = (uint64_t)(2 * rad + 1);
   const int ox = (int)((u0 * span) >> 32) - rad;
   const int oy = (int)((u1 * span) >> 32) - rad;
-  const int fx = fx_of(f) + ox, fy = fy_of(f) + oy;
+  const int fx = fx_of(fl) + ox, fy = fy_of(fl) + oy;
   if (!centre_valid(c, px, py, fx, fy)) return;
   const int32_t e = group_sum<L>(patch_partial(c, px, py, fx, fy, lane, L));
   if (lane == 0 && e < C[pid]) {
@@ -252,9 +277,6 @@ __global__ __launch_bounds__(256) void k_random_search(CostCtx c, int Gw, int Gh
 // relaxed agent-scope store; row 0 of the band below polls that word until
 // the tag matches.  One single-copy-atomic word carries data and readiness,
 // so no fence (L2 write-back or invalidate) is needed on the critical path.
-// Everything that does not depend on the wavefront -- the point's own flow
-// and cost, the source census terms, the next handoff word -- is loaded one
-// step ahead.
 __device__ __forceinline__ uint64_t rt_clock() { return __builtin_amdgcn_s_memrealtime(); }
 
 __device__ __forceinline__ uint64_t xch_pack(int32_t f, int32_t cst, uint32_t tag) {
@@ -277,31 +299,49 @@ __device__ __forceinline__ uint64_t xch_pack(int32_t f, int32_t cst, uint32_t ta
 // slots; the S % 16 remaining offsets of the four groups are packed into TAIL
 // extra slots.
 constexpr int kBatch = 32;
-constexpr int kMaxTileWords = (kBandRows + 2 * kMaxRadius + 1) * ((kBatch + kBandRows + 2 * kMaxRadius) | 1);
 
-template <int FULL, int TAIL>
-__global__ __launch_bounds__(kBandRows * kLanesProp) void k_propagate(CostCtx c, int Gw, int Gh, int sx, int sy,
-                                                                      int32_t* __restrict__ F, int32_t* __restrict__ C,
-                                                                      uint64_t* __restrict__ xch, uint32_t tag,
-                                                                      int32_t* __restrict__ ticket,
-                                                                      int32_t* __restrict__ status,
-                                                                      uint64_t timeout_ticks) {
-  constexpr int BH = kBandRows, L = kLanesProp, CH = kBatch;
+template <int FULL, int TAIL, int BH>
+__global__ __launch_bounds__(BH * kLanesProp) void k_propagate(const FieldRec* __restrict__ table, int f0, int nf,
+                                                               int lev, int qshift, int sx, int sy, uint32_t tag,
+                                                               int32_t* __restrict__ ticket,
+                                                               int32_t* __restrict__ status,
+                                                               uint64_t timeout_ticks) {
+  constexpr int L = kLanesProp, CH = kBatch;
   constexpr int NS = 4 * FULL + TAIL;   // term slots per lane
   static_assert(L == 16 && CH % 2 == 0 && CH % L == 0, "layout");
-  __shared__ int32_t s_band;
+  constexpr int kTileWords = (BH + 2 * kMaxRadius + 1) * ((kBatch + BH + 2 * kMaxRadius) | 1);
+  __shared__ int32_t s_band, s_field;
   __shared__ int32_t bufF[2][BH], bufC[2][BH];
   __shared__ int32_t inF[BH][CH], inC[BH][CH], outF[BH][CH], outC[BH][CH];
-  __shared__ uint32_t tile[kMaxTileWords];
+  __shared__ uint32_t tile[kTileWords];
   const int row = threadIdx.x / L, lane = threadIdx.x % L;
-  if (threadIdx.x == 0) s_band = atomicAdd(ticket, 1);
+  const int n = 1 << lev;
+  if (threadIdx.x == 0) {
+    // tickets are handed out in launch order; field-major, band-minor
+    int tk = atomicAdd(ticket, 1), fi = f0;
+    for (; fi < f0 + nf; ++fi) {
+      const int gh = (table[fi].Hs + n - 1) >> lev;
+      const int nb = (gh + BH - 1) / BH;
+      if (tk < nb) break;
+      tk -= nb;
+    }
+    s_band = tk;
+    s_field = fi;
+  }
   __syncthreads();
+  if (s_field >= f0 + nf) return;
+  const FieldRec& fr = table[s_field];
+  const CostCtx c = ctx_of(fr, lev, qshift);
+  const int Gw = (fr.Ws + n - 1) >> lev, Gh = (fr.Hs + n - 1) >> lev;
+  int32_t* const F = grid_flow(fr, lev);
+  int32_t* const C = grid_cost(fr, lev, Gw * Gh);
+  uint64_t* const xch = reinterpret_cast<uint64_t*>(fr.ws + fr.o_xch);
   const int band = s_band;
   const int v0 = band * BH;
   if (v0 >= Gh) return;
   const int rows = min(BH, Gh - v0);
   const int nsteps = Gw + rows - 1;
-  const int r = c.r, S = 2 * r + 1, n = c.n, Q = c.Q;
+  const int r = c.r, S = 2 * r + 1, Q = c.Q;
   const int TH = BH + 2 * r + 1;          // tile rows: v0-r-1 .. v0+BH-1+r
   const int TW = (CH + BH + 2 * r) | 1;   // tile cols: tb-BH-r .. tb+CH-1+r; odd pitch (banks)
   const bool rowok = row < rows;
@@ -500,35 +540,85 @@ __global__ __launch_bounds__(kBandRows * kLanesProp) void k_propagate(CostCtx c,
   }
 }
 
-__global__ void k_write_grid(const int32_t* __restrict__ Fg, const int32_t* __restrict__ Cg, int Gw, int n, int W, int H,
-                             int32_t* __restrict__ F, int32_t* __restrict__ C) {
+// write the grid of level lev into the full-resolution outputs (inspection
+// stops); grid: (W / 256, H, fields)
+__global__ void k_write_grid(const FieldRec* __restrict__ table, int lev) {
+  const FieldRec& f = table[blockIdx.z];
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
-  if (x >= W) return;
-  const size_t o = (size_t)y * W + x;
+  if (x >= f.Ws || y >= f.Hs) return;
+  const int n = 1 << lev;
+  const int Gw = (f.Ws + n - 1) >> lev, Gh = (f.Hs + n - 1) >> lev;
+  const size_t o = (size_t)y * f.Ws + x;
   if ((x % n) == 0 && (y % n) == 0) {
-    F[o] = Fg[(size_t)(y / n) * Gw + x / n];
-    C[o] = Cg[(size_t)(y / n) * Gw + x / n];
+    f.flow[o] = grid_flow(f, lev)[(size_t)(y / n) * Gw + x / n];
+    f.cost[o] = grid_cost(f, lev, Gw * Gh)[(size_t)(y / n) * Gw + x / n];
   } else {
-    F[o] = kEmpty;
-    C[o] = kInf;
+    f.flow[o] = kEmpty;
+    f.cost[o] = kInf;
   }
 }
 
-static void launch_propagate(int r, int bands, hipStream_t stream, const CostCtx& c, int Gw, int Gh, int sx, int sy,
-                             int32_t* F, int32_t* C, uint64_t* xch, uint32_t tag, int32_t* ticket, int32_t* status,
-                             uint64_t timeout) {
-  const dim3 grid(bands), block(kBandRows * kLanesProp);
+template <int BH>
+static void launch_propagate_bh(int r, int bands, hipStream_t stream, const FieldRec* table, int f0, int nf, int lev,
+                                int qshift, int sx, int sy, uint32_t tag, int32_t* ticket, int32_t* status,
+                                uint64_t timeout) {
+  const dim3 grid(bands), block(BH * kLanesProp);
   const int S = 2 * r + 1, full = S / 16, tl = S - 16 * full, tail = (4 * tl + 15) / 16;
-#define FF_PROP(FU, TA)                                                                                      \
-  if (full == FU && tail == TA) {                                                                          \
-    k_propagate<FU, TA><<<grid, block, 0, stream>>>(c, Gw, Gh, sx, sy, F, C, xch, tag, ticket, status, timeout); \
-    return;                                                                                                \
+#define FF_PROP(FU, TA)                                                                                        \
+  if (full == FU && tail == TA) {                                                                            \
+    k_propagate<FU, TA, BH><<<grid, block, 0, stream>>>(table, f0, nf, lev, qshift, sx, sy, tag, ticket, status, \
+                                                       timeout);                                            \
+    return;                                                                                                  \
   }
   FF_PROP(0, 1) FF_PROP(0, 2) FF_PROP(0, 3) FF_PROP(0, 4)
-  FF_PROP(1, 0) FF_PROP(1, 1) FF_PROP(1, 2) FF_PROP(1, 3) FF_PROP(1, 4)
+  FF_PROP(1, 1) FF_PROP(1, 2) FF_PROP(1, 3) FF_PROP(1, 4)
 #undef FF_PROP
 }
+
+static void launch_propagate(int bh, int r, int bands, hipStream_t stream, const FieldRec* table, int f0, int nf,
+                             int lev, int qshift, int sx, int sy, uint32_t tag, int32_t* ticket, int32_t* status,
+                             uint64_t timeout) {
+  if (bh == 8)
+    launch_propagate_bh<8>(r, bands, stream, table, f0, nf, lev, qshift, sx, sy, tag, ticket, status, timeout);
+  else if (bh == 32)
+    launch_propagate_bh<32>(r, bands, stream, table, f0, nf, lev, qshift, sx, sy, tag, ticket, status, timeout);
+  else
+    launch_propagate_bh<16>(r, bands, stream, table, f0, nf, lev, qshift, sx, sy, tag, ticket, status, timeout);
+}
+
+// ---------------------------------------------------------------- host plans
+struct FieldPlan {
+  bool has_tree;
+  TreeLayout tree;        // offsets relative to the field region
+  size_t off_grid[5];
+  size_t off_xch;
+  size_t bytes;
+};
+
+static FieldPlan field_plan(const ff_desc* src, const ff_desc* dst, const ff_match_params* p) {
+  FieldPlan P{};
+  size_t off = 0;
+  P.has_tree = p->use_kdtree != 0;
+  if (P.has_tree) {
+    P.tree = tree_layout(dst->width * dst->height, p->leaf, 0);
+    off = P.tree.bytes;
+  }
+  for (int lev = 1; lev <= p->k; ++lev) {
+    const int n = 1 << lev;
+    const size_t G = (size_t)((src->width + n - 1) / n) * ((src->height + n - 1) / n);
+    off = align_up(off, 256);
+    P.off_grid[lev] = off;
+    off += G * 8;
+  }
+  off = align_up(off, 256);
+  P.off_xch = off;
+  off += (size_t)((src->height + kMinBandRows - 1) / kMinBandRows) * src->width * 8;
+  P.bytes = align_up(off, 256);
+  return P;
+}
+
+static int band_rows_of(const ff_match_params* p) { return p->band_rows == 0 ? 16 : p->band_rows; }
 
 static ff_status check_params(const ff_desc* src, const ff_desc* dst, int radius, const ff_match_params* p) {
   if (!src || !dst || !p) return FF_ERR_ARG;
@@ -537,6 +627,7 @@ static ff_status check_params(const ff_desc* src, const ff_desc* dst, int radius
   if (radius < 1 || radius > kMaxRadius) return FF_ERR_ARG;
   if (p->R < 0 || p->R > 64 || p->n_prop < 0 || p->n_prop > 64 || p->n_rs < 0 || p->n_rs > p->n_prop) return FF_ERR_ARG;
   if (p->field_id > 3) return FF_ERR_ARG;
+  if (p->band_rows != 0 && p->band_rows != 8 && p->band_rows != 16 && p->band_rows != 32) return FF_ERR_ARG;
   if (p->use_kdtree) {
     if (p->leaf < 2 || p->leaf > kMaxLeaf) return FF_ERR_ARG;
     bool hs = false, hd = false;
@@ -547,23 +638,189 @@ static ff_status check_params(const ff_desc* src, const ff_desc* dst, int radius
   return FF_OK;
 }
 
-static CostCtx make_ctx(const ff_desc* src, const void* sb, const ff_desc* dst, const void* db, int lev, int r) {
-  CostCtx c;
-  c.src = census_plane(src, sb, lev, 0, 0);
-  c.dst = census_plane(dst, db, lev, 0, 0);
-  c.srcT = census_plane_t(src, sb, lev, 0, 0);
-  c.dstT = census_plane_t(dst, db, lev, 0, 0);
-  c.pw = (size_t)dst->width * dst->height;
-  c.Ws = src->width;
-  c.Hs = src->height;
-  c.Wd = dst->width;
-  c.Hd = dst->height;
-  c.Q = dst->subpel;
-  c.qshift = ilog2i(dst->subpel);
-  c.qmask = dst->subpel - 1;
-  c.n = 1 << lev;
-  c.r = r;
-  return c;
+static ff_status check_job(const ff_field_job& j, const ff_match_params* p) {
+  ff_match_params q = *p;
+  q.field_id = j.field_id;
+  ff_status st = check_params(j.src, j.dst, j.radius, &q);
+  if (st != FF_OK) return st;
+  if (!j.src_blob || !j.dst_blob || !j.flow || !j.cost) return FF_ERR_ARG;
+  if (!p->use_kdtree && !j.proposal) return FF_ERR_ARG;
+  return FF_OK;
+}
+
+struct BatchLayout {
+  size_t off_tickets, off_table;
+  int launches;
+  std::vector<size_t> off_field;   // per table entry
+  std::vector<int> order;          // table entry -> job index (grouped by radius)
+  size_t bytes;
+};
+
+static BatchLayout batch_layout(const ff_field_job* jobs, int n, const ff_match_params* p) {
+  BatchLayout B;
+  B.order.resize(n);
+  for (int i = 0; i < n; ++i) B.order[i] = i;
+  std::stable_sort(B.order.begin(), B.order.end(), [&](int a, int b) { return jobs[a].radius > jobs[b].radius; });
+  int groups = 0;
+  for (int i = 0; i < n; ++i)
+    if (i == 0 || jobs[B.order[i]].radius != jobs[B.order[i - 1]].radius) ++groups;
+  size_t off = kStatusBytes;
+  B.off_tickets = off;
+  B.launches = (p->k + 1) * p->n_prop * groups;
+  off = align_up(off + (size_t)B.launches * 4, 256);
+  B.off_table = off;
+  off = align_up(off + (size_t)n * sizeof(FieldRec), 256);
+  B.off_field.resize(n);
+  for (int i = 0; i < n; ++i) {
+    const ff_field_job& j = jobs[B.order[i]];
+    B.off_field[i] = off;
+    off = align_up(off + field_plan(j.src, j.dst, p).bytes, 256);
+  }
+  B.bytes = off;
+  return B;
+}
+
+static FieldRec make_rec(const ff_field_job& j, const ff_match_params* p, char* fws) {
+  const ff_desc* s = j.src;
+  const ff_desc* d = j.dst;
+  const FieldPlan P = field_plan(s, d, p);
+  FieldRec r{};
+  r.src = census_plane(s, j.src_blob, 0, 0, 0);
+  r.srcT = census_plane_t(s, j.src_blob, 0, 0, 0);
+  r.dst = census_plane(d, j.dst_blob, 0, 0, 0);
+  r.dstT = census_plane_t(d, j.dst_blob, 0, 0, 0);
+  r.Vsrc = p->use_kdtree ? wht_block(s, j.src_blob, j.radius) : nullptr;
+  r.Vdst = p->use_kdtree ? wht_block(d, j.dst_blob, j.radius) : nullptr;
+  r.proposal = j.proposal;
+  r.flow = j.flow;
+  r.cost = j.cost;
+  r.ws = fws;
+  r.pws = (uint32_t)(s->width * s->height);
+  r.pwd = (uint32_t)(d->width * d->height);
+  r.Ws = s->width;
+  r.Hs = s->height;
+  r.Wd = d->width;
+  r.Hd = d->height;
+  r.r = j.radius;
+  r.D = d->wht_dims;
+  r.vstride = d->wht_stride;
+  r.k0 = (uint32_t)(j.seed & 0xFFFFFFFFu);
+  r.k1 = (uint32_t)(j.seed >> 32);
+  r.c3 = j.field_id | (j.pair_id << 2);
+  if (P.has_tree) {
+    r.t_nodes = P.tree.nodes;
+    r.t_top = P.tree.top;
+    r.o_dim = (uint32_t)P.tree.off_dim;
+    r.o_split = (uint32_t)P.tree.off_split;
+    r.o_perm = (uint32_t)P.tree.off_perm;
+    r.o_perm2 = (uint32_t)P.tree.off_perm2;
+    r.o_mm = (uint32_t)P.tree.off_minmax;
+    r.o_hist = (uint32_t)P.tree.off_hist;
+    r.o_cnt = (uint32_t)P.tree.off_cnt;
+  }
+  for (int l = 0; l < 5; ++l) r.o_grid[l] = (uint32_t)P.off_grid[l];
+  r.o_xch = (uint32_t)P.off_xch;
+  return r;
+}
+
+static void write_table(const std::vector<FieldRec>& recs, FieldRec* dev, hipStream_t stream) {
+  for (size_t i = 0; i < recs.size(); i += kRecsPerWrite) {
+    RecChunk ch{};
+    const int n = (int)std::min<size_t>(kRecsPerWrite, recs.size() - i);
+    for (int k = 0; k < n; ++k) ch.r[k] = recs[i + k];
+    k_write_table<<<1, kRecsPerWrite, 0, stream>>>(ch, n, dev + i);
+  }
+}
+
+// The whole search for a batch of fields.  Every stage is one launch over
+// all fields (propagation: one launch per patch radius).
+static ff_status run_batch(const ff_field_job* jobs, int n, const ff_match_params* p, char* ws, const BatchLayout& B,
+                           hipStream_t stream) {
+  int32_t* status = reinterpret_cast<int32_t*>(ws);
+  int32_t* tickets = reinterpret_cast<int32_t*>(ws + B.off_tickets);
+  FieldRec* table = reinterpret_cast<FieldRec*>(ws + B.off_table);
+  std::vector<FieldRec> recs(n);
+  int maxW = 0, maxH = 0, maxN = 0, maxTop = 0, maxG = 0;
+  for (int i = 0; i < n; ++i) {
+    const ff_field_job& j = jobs[B.order[i]];
+    recs[i] = make_rec(j, p, ws + B.off_field[i]);
+    maxW = std::max(maxW, recs[i].Ws);
+    maxH = std::max(maxH, recs[i].Hs);
+    maxN = std::max(maxN, recs[i].Wd * recs[i].Hd);
+    maxTop = std::max(maxTop, recs[i].t_top);
+    maxG = std::max(maxG, recs[i].Ws * recs[i].Hs);
+  }
+  const int qshift = ilog2i(jobs[0].dst->subpel);
+  const int k = p->k;
+  const int bh = band_rows_of(p);
+  fill_i32(status, 1, 0, stream);
+  fill_i32(tickets, (size_t)B.launches, 0, stream);
+  write_table(recs, table, stream);
+  k_clear_xch<<<dim3(64, n), 256, 0, stream>>>(table, kMinBandRows);
+  if (p->use_kdtree) {
+    prof_mark(FF_PROF_TREE, stream, true);
+    ff_status st = enqueue_tree_build(table, n, maxN, maxTop, p->leaf, stream);
+    prof_mark(FF_PROF_TREE, stream, false);
+    if (st != FF_OK) return st;
+  }
+  auto pts = [&](int lev) { return ((maxW + (1 << lev) - 1) >> lev) * ((maxH + (1 << lev) - 1) >> lev); };
+  int steps = 0, cur_lev = k;
+  auto stop = [&]() { return p->max_steps >= 0 && steps >= p->max_steps; };
+  auto finish = [&]() -> ff_status {
+    if (cur_lev > 0) k_write_grid<<<dim3((maxW + 255) / 256, maxH, n), 256, 0, stream>>>(table, cur_lev);
+    return launch_status();
+  };
+  prof_mark(FF_PROF_SEED, stream, true);
+  k_seed<<<dim3((pts(k) + 3) / 4, n), 256, 0, stream>>>(table, k, qshift, p->use_kdtree ? 1 : 0);
+  prof_mark(FF_PROF_SEED, stream, false);
+  ++steps;
+  if (stop()) return finish();
+  // watchdog for the propagation's inter-band waits: 2 s of the 100 MHz clock
+  const uint64_t timeout = 200000000ull;
+  int launch = 0;
+  for (int lev = k; lev >= 0; --lev) {
+    cur_lev = lev;
+    const unsigned gpts = (unsigned)((pts(lev) * kLanesPt + 255) / 256);
+    if (lev < k) {
+      prof_mark(FF_PROF_LEVEL_ENTRY, stream, true);
+      k_level_entry<kLanesPt><<<dim3(gpts, n), 256, 0, stream>>>(table, lev, qshift);
+      prof_mark(FF_PROF_LEVEL_ENTRY, stream, false);
+      ++steps;
+      if (stop()) return finish();
+    }
+    for (int i = 0; i < p->n_prop; ++i) {
+      const int dir = i & 3;
+      const int sx = (dir == 0 || dir == 3) ? 1 : -1;
+      const int sy = (dir == 0 || dir == 2) ? 1 : -1;
+      prof_mark(FF_PROF_PROPAGATE, stream, true);
+      for (int g0 = 0; g0 < n;) {
+        int g1 = g0;
+        int bands = 0;
+        while (g1 < n && recs[g1].r == recs[g0].r) {
+          const int gh = (recs[g1].Hs + (1 << lev) - 1) >> lev;
+          bands += (gh + bh - 1) / bh;
+          ++g1;
+        }
+        launch_propagate(bh, recs[g0].r, bands, stream, table, g0, g1 - g0, lev, qshift, sx, sy,
+                         (uint32_t)(launch + 1), tickets + launch, status, timeout);
+        ++launch;
+        g0 = g1;
+      }
+      prof_mark(FF_PROF_PROPAGATE, stream, false);
+      ++steps;
+      if (stop()) return finish();
+      if (i < p->n_rs) {
+        prof_mark(FF_PROF_RANDOM_SEARCH, stream, true);
+        k_random_search<kLanesPt><<<dim3(gpts, n), 256, 0, stream>>>(table, lev, qshift, i, p->R);
+        prof_mark(FF_PROF_RANDOM_SEARCH, stream, false);
+        ++steps;
+        if (stop()) return finish();
+      }
+    }
+  }
+  (void)maxG;
+  cur_lev = 0;
+  return finish();
 }
 
 }  // namespace ff
@@ -582,11 +839,66 @@ void ff_default_params(ff_match_params* p) {
   p->n_rs = 3;
   p->use_kdtree = 1;
   p->max_steps = -1;
+  p->band_rows = 16;
+}
+
+size_t ff_match_batch_workspace_bytes(const ff_field_job* jobs, int32_t n_jobs, const ff_match_params* p) {
+  if (!jobs || !p || n_jobs < 1 || n_jobs > 4096) return 0;
+  for (int i = 0; i < n_jobs; ++i) {
+    ff_match_params q = *p;
+    q.field_id = jobs[i].field_id;
+    if (!jobs[i].src || !jobs[i].dst || check_params(jobs[i].src, jobs[i].dst, jobs[i].radius, &q) != FF_OK) return 0;
+    if (jobs[i].dst->subpel != jobs[0].dst->subpel) return 0;
+  }
+  return batch_layout(jobs, n_jobs, p).bytes;
+}
+
+ff_status ff_match_batch(const ff_field_job* jobs, int32_t n_jobs, const ff_match_params* p, void* workspace,
+                         size_t workspace_bytes, hipStream_t stream) {
+  if (!jobs || !p || !workspace || n_jobs < 1 || n_jobs > 4096) return FF_ERR_ARG;
+  for (int i = 0; i < n_jobs; ++i) {
+    if (!jobs[i].src || !jobs[i].dst) return FF_ERR_ARG;
+    ff_status st = check_job(jobs[i], p);
+    if (st != FF_OK) return st;
+    if (jobs[i].dst->subpel != jobs[0].dst->subpel) return FF_ERR_ARG;
+  }
+  const BatchLayout B = batch_layout(jobs, n_jobs, p);
+  if (workspace_bytes < B.bytes) return FF_ERR_WORKSPACE;
+  ff_status st = ensure_init();
+  if (st != FF_OK) return st;
+  return run_batch(jobs, n_jobs, p, static_cast<char*>(workspace), B, stream);
+}
+
+static ff_field_job single_job(const ff_desc* src, const void* src_blob, const ff_desc* dst, const void* dst_blob,
+                               int32_t radius, const ff_match_params* p, const int32_t* proposal, int32_t* flow,
+                               int32_t* cost) {
+  ff_field_job j{};
+  j.src = src;
+  j.src_blob = src_blob;
+  j.dst = dst;
+  j.dst_blob = dst_blob;
+  j.radius = radius;
+  j.field_id = p ? p->field_id : 0;
+  j.pair_id = p ? p->pair_id : 0;
+  j.seed = p ? p->seed : 0;
+  j.proposal = proposal;
+  j.flow = flow;
+  j.cost = cost;
+  return j;
 }
 
 size_t ff_match_workspace_bytes(const ff_desc* src, const ff_desc* dst, int32_t radius, const ff_match_params* p) {
   if (check_params(src, dst, radius, p) != FF_OK) return 0;
-  return match_layout(src, dst, p).bytes;
+  const ff_field_job j = single_job(src, nullptr, dst, nullptr, radius, p, nullptr, nullptr, nullptr);
+  return batch_layout(&j, 1, p).bytes;
+}
+
+ff_status ff_match_field(const ff_desc* src, const void* src_blob, const ff_desc* dst, const void* dst_blob,
+                         int32_t radius, const ff_match_params* p, const int32_t* proposal, int32_t* flow,
+                         int32_t* cost, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!p) return FF_ERR_ARG;
+  const ff_field_job j = single_job(src, src_blob, dst, dst_blob, radius, p, proposal, flow, cost);
+  return ff_match_batch(&j, 1, p, workspace, workspace_bytes, stream);
 }
 
 ff_status ff_read_status(const void* workspace, int32_t* status_host) {
@@ -600,134 +912,31 @@ ff_status ff_build_kdtree(const ff_desc* d, const void* blob, int32_t radius, in
                           hipStream_t stream) {
   if (!d || !blob || !node_dim || !node_split || !perm || !workspace) return FF_ERR_ARG;
   if (leaf < 2 || leaf > kMaxLeaf) return FF_ERR_ARG;
-  const int32_t* V = wht_block(d, blob, radius);
-  if (!V) return FF_ERR_ARG;
-  const int N = d->width * d->height;
-  TreeLayout L = tree_layout(N, leaf, kStatusBytes);
-  if (workspace_bytes < kStatusBytes + L.bytes) return FF_ERR_WORKSPACE;
+  if (!wht_block(d, blob, radius)) return FF_ERR_ARG;
+  ff_match_params p;
+  ff_default_params(&p);
+  p.k = 0;
+  p.leaf = leaf;
+  const ff_field_job j = single_job(d, blob, d, blob, radius, &p, nullptr, node_dim, node_split);
+  const BatchLayout B = batch_layout(&j, 1, &p);
+  if (workspace_bytes < B.bytes) return FF_ERR_WORKSPACE;
   ff_status st = ensure_init();
   if (st != FF_OK) return st;
   char* ws = static_cast<char*>(workspace);
-  st = enqueue_tree_build(V, N, d->wht_dims, d->wht_stride, leaf, L, ws, stream);
+  std::vector<FieldRec> recs(1, make_rec(j, &p, ws + B.off_field[0]));
+  FieldRec* table = reinterpret_cast<FieldRec*>(ws + B.off_table);
+  write_table(recs, table, stream);
+  st = enqueue_tree_build(table, 1, d->width * d->height, recs[0].t_top, leaf, stream);
   if (st != FF_OK) return st;
-  if (hipMemcpyAsync(node_dim, ws + L.off_dim, (size_t)L.nodes * 4, hipMemcpyDeviceToDevice, stream) != hipSuccess ||
-      hipMemcpyAsync(node_split, ws + L.off_split, (size_t)L.nodes * 4, hipMemcpyDeviceToDevice, stream) != hipSuccess ||
-      hipMemcpyAsync(perm, ws + L.off_perm, (size_t)N * 4, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+  const char* fws = ws + B.off_field[0];
+  const int N = d->width * d->height;
+  if (hipMemcpyAsync(node_dim, fws + recs[0].o_dim, (size_t)recs[0].t_nodes * 4, hipMemcpyDeviceToDevice, stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(node_split, fws + recs[0].o_split, (size_t)recs[0].t_nodes * 4, hipMemcpyDeviceToDevice,
+                     stream) != hipSuccess ||
+      hipMemcpyAsync(perm, fws + recs[0].o_perm, (size_t)N * 4, hipMemcpyDeviceToDevice, stream) != hipSuccess)
     return FF_ERR_HIP;
   return FF_OK;
-}
-
-ff_status ff_match_field(const ff_desc* src, const void* src_blob, const ff_desc* dst, const void* dst_blob,
-                         int32_t radius, const ff_match_params* p, const int32_t* proposal, int32_t* flow,
-                         int32_t* cost, void* workspace, size_t workspace_bytes, hipStream_t stream) {
-  ff_status st = check_params(src, dst, radius, p);
-  if (st != FF_OK) return st;
-  if (!src_blob || !dst_blob || !flow || !cost || !workspace) return FF_ERR_ARG;
-  if (!p->use_kdtree && !proposal) return FF_ERR_ARG;
-  const MatchLayout M = match_layout(src, dst, p);
-  if (workspace_bytes < M.bytes) return FF_ERR_WORKSPACE;
-  st = ensure_init();
-  if (st != FF_OK) return st;
-  char* ws = static_cast<char*>(workspace);
-  int32_t* status = reinterpret_cast<int32_t*>(ws);
-  int32_t* sync = reinterpret_cast<int32_t*>(ws + M.off_sync);
-  fill_i32(status, 1, 0, stream);
-  uint64_t* xch = reinterpret_cast<uint64_t*>(ws + M.off_xch);
-  fill_i32(sync, (size_t)M.launches, 0, stream);
-  fill_i32(reinterpret_cast<int32_t*>(xch), M.xch_words * 2, 0, stream);
-  const int Ws = src->width, Hs = src->height;
-  const int k = p->k;
-  if (M.has_tree) {
-    prof_mark(FF_PROF_TREE, stream, true);
-    st = enqueue_tree_build(wht_block(dst, dst_blob, radius), dst->width * dst->height, dst->wht_dims, dst->wht_stride,
-                            p->leaf, M.tree, ws, stream);
-    prof_mark(FF_PROF_TREE, stream, false);
-    if (st != FF_OK) return st;
-  }
-  auto gridF = [&](int lev) -> int32_t* {
-    return lev == 0 ? flow : reinterpret_cast<int32_t*>(ws + M.off_grid[lev]);
-  };
-  auto gridC = [&](int lev) -> int32_t* {
-    if (lev == 0) return cost;
-    const int n = 1 << lev;
-    const size_t G = (size_t)((Ws + n - 1) / n) * ((Hs + n - 1) / n);
-    return reinterpret_cast<int32_t*>(ws + M.off_grid[lev]) + G;
-  };
-  int steps = 0;
-  int cur_lev = k;
-  auto stop = [&]() { return p->max_steps >= 0 && steps >= p->max_steps; };
-  auto finish = [&]() -> ff_status {
-    if (cur_lev > 0) {
-      const int n = 1 << cur_lev;
-      k_write_grid<<<dim3((Ws + 255) / 256, Hs), 256, 0, stream>>>(gridF(cur_lev), gridC(cur_lev), (Ws + n - 1) / n, n,
-                                                                   Ws, Hs, flow, cost);
-    }
-    return launch_status();
-  };
-  {
-    const CostCtx c = make_ctx(src, src_blob, dst, dst_blob, k, radius);
-    const int n = 1 << k;
-    const int Gw = (Ws + n - 1) / n, Gh = (Hs + n - 1) / n;
-    const int32_t* Vs = M.has_tree ? wht_block(src, src_blob, radius) : nullptr;
-    const int32_t* nd = M.has_tree ? reinterpret_cast<const int32_t*>(ws + M.tree.off_dim) : nullptr;
-    const int32_t* ns = M.has_tree ? reinterpret_cast<const int32_t*>(ws + M.tree.off_split) : nullptr;
-    const int32_t* pm = M.has_tree ? reinterpret_cast<const int32_t*>(ws + M.tree.off_perm) : nullptr;
-    const int waves = Gw * Gh;
-    prof_mark(FF_PROF_SEED, stream, true);
-    k_seed<<<(waves + 3) / 4, 256, 0, stream>>>(c, Gw, Gh, Vs, src->wht_stride, nd, ns, pm, dst->width * dst->height,
-                                                 M.has_tree ? M.tree.nodes : 0, M.has_tree ? 1 : 0, proposal,
-                                                 gridF(k), gridC(k));
-    prof_mark(FF_PROF_SEED, stream, false);
-  }
-  ++steps;
-  if (stop()) return finish();
-  const uint32_t c3base = p->field_id | (p->pair_id << 2);
-  const uint32_t k0 = (uint32_t)(p->seed & 0xFFFFFFFFu), k1 = (uint32_t)(p->seed >> 32);
-  // watchdog for the propagation's inter-band waits: 2 s of the 100 MHz
-  // constant clock
-  const uint64_t timeout = 200000000ull;
-  int launch = 0;
-  for (int lev = k; lev >= 0; --lev) {
-    cur_lev = lev;
-    const int n = 1 << lev;
-    const int Gw = (Ws + n - 1) / n, Gh = (Hs + n - 1) / n;
-    const CostCtx c = make_ctx(src, src_blob, dst, dst_blob, lev, radius);
-    int32_t* F = gridF(lev);
-    int32_t* C = gridC(lev);
-    const int G = Gw * Gh;
-    if (lev < k) {
-      const int nc = n * 2;
-      prof_mark(FF_PROF_LEVEL_ENTRY, stream, true);
-      k_level_entry<kLanesPt><<<(G * kLanesPt + 255) / 256, 256, 0, stream>>>(c, Gw, Gh, gridF(lev + 1),
-                                                                             (Ws + nc - 1) / nc, F, C);
-      prof_mark(FF_PROF_LEVEL_ENTRY, stream, false);
-      ++steps;
-      if (stop()) return finish();
-    }
-    for (int i = 0; i < p->n_prop; ++i) {
-      const int dir = i & 3;
-      const int sx = (dir == 0 || dir == 3) ? 1 : -1;
-      const int sy = (dir == 0 || dir == 2) ? 1 : -1;
-      const int bands = (Gh + kBandRows - 1) / kBandRows;
-      prof_mark(FF_PROF_PROPAGATE, stream, true);
-      launch_propagate(radius, bands, stream, c, Gw, Gh, sx, sy, F, C, xch, (uint32_t)(launch + 1), sync + launch, status,
-                       timeout);
-      prof_mark(FF_PROF_PROPAGATE, stream, false);
-      ++launch;
-      ++steps;
-      if (stop()) return finish();
-      if (i < p->n_rs) {
-        prof_mark(FF_PROF_RANDOM_SEARCH, stream, true);
-        k_random_search<kLanesPt><<<(G * kLanesPt + 255) / 256, 256, 0, stream>>>(
-            c, Gw, Gh, lev, i, n * p->R * dst->subpel, c3base, k0, k1, F, C);
-        prof_mark(FF_PROF_RANDOM_SEARCH, stream, false);
-        ++steps;
-        if (stop()) return finish();
-      }
-    }
-  }
-  cur_lev = 0;
-  return finish();
 }
 
 }  // extern "C"

@@ -61,25 +61,64 @@ __device__ __forceinline__ void node_range(int d, int j, int N, int& start, int&
   }
 }
 
-__global__ void k_iota(int32_t* p, int n) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = i;
+// per-field views of the tree arrays
+struct TreeView {
+  const int32_t* V;
+  int N, D, stride, top, nodes;
+  int32_t *dim, *split, *perm, *perm2, *mm, *hist, *cnt;
+};
+
+__device__ __forceinline__ TreeView tree_view(const FieldRec& f) {
+  TreeView t;
+  t.V = f.Vdst;
+  t.N = f.Wd * f.Hd;
+  t.D = f.D;
+  t.stride = f.vstride;
+  t.top = f.t_top;
+  t.nodes = f.t_nodes;
+  t.dim = reinterpret_cast<int32_t*>(f.ws + f.o_dim);
+  t.split = reinterpret_cast<int32_t*>(f.ws + f.o_split);
+  t.perm = reinterpret_cast<int32_t*>(f.ws + f.o_perm);
+  t.perm2 = reinterpret_cast<int32_t*>(f.ws + f.o_perm2);
+  t.mm = reinterpret_cast<int32_t*>(f.ws + f.o_mm);
+  t.hist = reinterpret_cast<int32_t*>(f.ws + f.o_hist);
+  t.cnt = reinterpret_cast<int32_t*>(f.ws + f.o_cnt);
+  return t;
 }
 
-__global__ void k_minmax_init(int32_t* mm, int n) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) mm[i] = (i & 1) ? INT32_MIN : INT32_MAX;   // pairs (min, max)
+// node arrays -1 / 0, identity permutation, min/max sentinels, zero
+// histograms and partition counters (grid-stride over the largest array)
+__global__ void k_tree_init(const FieldRec* __restrict__ table) {
+  const TreeView t = tree_view(table[blockIdx.y]);
+  const int topnodes = (1 << t.top) - 1;
+  const size_t nh = (size_t)topnodes * kSelPasses * kSelBins;
+  const size_t total = (size_t)t.N + (size_t)t.nodes + (size_t)topnodes * 64 + nh + (size_t)topnodes * 2;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    size_t j = i;
+    if (j < (size_t)t.N) { t.perm[j] = (int32_t)j; continue; }
+    j -= t.N;
+    if (j < (size_t)t.nodes) { t.dim[j] = -1; t.split[j] = 0; continue; }
+    j -= t.nodes;
+    if (j < (size_t)topnodes * 64) { t.mm[j] = (j & 1) ? INT32_MIN : INT32_MAX; continue; }   // pairs (min, max)
+    j -= (size_t)topnodes * 64;
+    if (j < nh) { t.hist[j] = 0; continue; }
+    j -= nh;
+    t.cnt[j] = 0;
+  }
 }
 
 // ---------------------------------------------------------------- top levels
-__global__ __launch_bounds__(kTpb) void k_tree_minmax(const int32_t* __restrict__ V, int stride, int D, int N, int d,
-                                                      const int32_t* __restrict__ perm, int32_t* __restrict__ mm) {
+// grid: (chunks, nodes at depth d, fields)
+__global__ __launch_bounds__(kTpb) void k_tree_minmax(const FieldRec* __restrict__ table, int d) {
+  const TreeView t = tree_view(table[blockIdx.z]);
+  if (d >= t.top) return;
   const int j = blockIdx.y;
   int start, cnt;
-  node_range(d, j, N, start, cnt);
+  node_range(d, j, t.N, start, cnt);
   const int lo = blockIdx.x * kChunk;
   if (lo >= cnt) return;
   const int hi = min(cnt, lo + kChunk);
+  const int32_t* perm = (d & 1) ? t.perm2 : t.perm;
   __shared__ int32_t smin[32], smax[32];
   if (threadIdx.x < 32) { smin[threadIdx.x] = INT32_MAX; smax[threadIdx.x] = INT32_MIN; }
   __syncthreads();
@@ -87,14 +126,14 @@ __global__ __launch_bounds__(kTpb) void k_tree_minmax(const int32_t* __restrict_
 #pragma unroll
   for (int k = 0; k < 27; ++k) { mn[k] = INT32_MAX; mx[k] = INT32_MIN; }
   for (int e = lo + threadIdx.x; e < hi; e += kTpb) {
-    const int32_t* v = V + (size_t)perm[start + e] * stride;
+    const int32_t* v = t.V + (size_t)perm[start + e] * t.stride;
 #pragma unroll
     for (int k = 0; k < 27; ++k)
-      if (k < D) { const int32_t x = v[k]; mn[k] = min(mn[k], x); mx[k] = max(mx[k], x); }
+      if (k < t.D) { const int32_t x = v[k]; mn[k] = min(mn[k], x); mx[k] = max(mx[k], x); }
   }
 #pragma unroll
   for (int k = 0; k < 27; ++k) {
-    if (k >= D) break;
+    if (k >= t.D) break;
     int32_t a = mn[k], b = mx[k];
     for (int o = 32; o > 0; o >>= 1) {
       a = min(a, __shfl_xor(a, o));
@@ -104,9 +143,9 @@ __global__ __launch_bounds__(kTpb) void k_tree_minmax(const int32_t* __restrict_
   }
   __syncthreads();
   const int node = (1 << d) - 1 + j;
-  if (threadIdx.x < D) {
-    atomicMin(&mm[((size_t)node * 32 + threadIdx.x) * 2], smin[threadIdx.x]);
-    atomicMax(&mm[((size_t)node * 32 + threadIdx.x) * 2 + 1], smax[threadIdx.x]);
+  if (threadIdx.x < t.D) {
+    atomicMin(&t.mm[((size_t)node * 32 + threadIdx.x) * 2], smin[threadIdx.x]);
+    atomicMax(&t.mm[((size_t)node * 32 + threadIdx.x) * 2 + 1], smax[threadIdx.x]);
   }
 }
 
@@ -163,57 +202,58 @@ __device__ void select_state(const int32_t* __restrict__ hist, int node, int pas
   }
 }
 
-__global__ __launch_bounds__(kTpb) void k_tree_hist(const int32_t* __restrict__ V, int stride, int D, int N, int d,
-                                                    const int32_t* __restrict__ perm, const int32_t* __restrict__ mm,
-                                                    int32_t* __restrict__ hist, int32_t* __restrict__ node_dim,
-                                                    int pass) {
+__global__ __launch_bounds__(kTpb) void k_tree_hist(const FieldRec* __restrict__ table, int d, int pass) {
+  const TreeView t = tree_view(table[blockIdx.z]);
+  if (d >= t.top) return;
   const int j = blockIdx.y;
   int start, cnt;
-  node_range(d, j, N, start, cnt);
+  node_range(d, j, t.N, start, cnt);
   const int lo = blockIdx.x * kChunk;
   if (lo >= cnt) return;
   const int hi = min(cnt, lo + kChunk);
+  const int32_t* perm = (d & 1) ? t.perm2 : t.perm;
   const int node = (1 << d) - 1 + j;
   int dim;
   int32_t mn;
-  node_split_dim(mm, node, D, dim, mn);
-  if (pass == 0 && blockIdx.x == 0 && threadIdx.x == 0) node_dim[node] = dim;
+  node_split_dim(t.mm, node, t.D, dim, mn);
+  if (pass == 0 && blockIdx.x == 0 && threadIdx.x == 0) t.dim[node] = dim;
   uint64_t prefix;
   int rank;
-  select_state(hist, node, pass, cnt >> 1, prefix, rank);
+  select_state(t.hist, node, pass, cnt >> 1, prefix, rank);
   __shared__ int32_t lh[kSelBins];
   for (int i = threadIdx.x; i < kSelBins; i += kTpb) lh[i] = 0;
   __syncthreads();
   const int shift = 33 - 11 * pass;
   for (int e = lo + threadIdx.x; e < hi; e += kTpb) {
     const int id = perm[start + e];
-    const uint64_t ck = ((uint64_t)(uint32_t)(V[(size_t)id * stride + dim] - mn) << 22) | (uint64_t)id;
+    const uint64_t ck = ((uint64_t)(uint32_t)(t.V[(size_t)id * t.stride + dim] - mn) << 22) | (uint64_t)id;
     if ((ck >> (shift + 11)) == prefix) atomicAdd(&lh[(ck >> shift) & (kSelBins - 1)], 1);
   }
   __syncthreads();
-  int32_t* g = hist + ((size_t)node * kSelPasses + pass) * kSelBins;
+  int32_t* g = t.hist + ((size_t)node * kSelPasses + pass) * kSelBins;
   for (int i = threadIdx.x; i < kSelBins; i += kTpb)
     if (lh[i]) atomicAdd(&g[i], lh[i]);
 }
 
-__global__ __launch_bounds__(kTpb) void k_tree_partition(const int32_t* __restrict__ V, int stride, int D, int N, int d,
-                                                         const int32_t* __restrict__ perm, int32_t* __restrict__ out,
-                                                         const int32_t* __restrict__ mm, const int32_t* __restrict__ hist,
-                                                         int32_t* __restrict__ counters, int32_t* __restrict__ node_split) {
+__global__ __launch_bounds__(kTpb) void k_tree_partition(const FieldRec* __restrict__ table, int d) {
+  const TreeView t = tree_view(table[blockIdx.z]);
+  if (d >= t.top) return;
   const int j = blockIdx.y;
   int start, cnt;
-  node_range(d, j, N, start, cnt);
+  node_range(d, j, t.N, start, cnt);
   const int lo = blockIdx.x * kChunk;
   if (lo >= cnt) return;
   const int hi = min(cnt, lo + kChunk);
+  const int32_t* perm = (d & 1) ? t.perm2 : t.perm;
+  int32_t* out = (d & 1) ? t.perm : t.perm2;
   const int node = (1 << d) - 1 + j;
   int dim;
   int32_t mn;
-  node_split_dim(mm, node, D, dim, mn);
+  node_split_dim(t.mm, node, t.D, dim, mn);
   uint64_t pivot;
   int rank;
-  select_state(hist, node, kSelPasses, cnt >> 1, pivot, rank);
-  if (blockIdx.x == 0 && threadIdx.x == 0) node_split[node] = (int32_t)(pivot >> 22) + mn;
+  select_state(t.hist, node, kSelPasses, cnt >> 1, pivot, rank);
+  if (blockIdx.x == 0 && threadIdx.x == 0) t.split[node] = (int32_t)(pivot >> 22) + mn;
   constexpr int EPT = kChunk / kTpb;
   int ids[EPT];
   uint32_t leftmask = 0;
@@ -225,7 +265,7 @@ __global__ __launch_bounds__(kTpb) void k_tree_partition(const int32_t* __restri
     if (e < hi) {
       const int id = perm[start + e];
       ids[i] = id;
-      const uint64_t ck = ((uint64_t)(uint32_t)(V[(size_t)id * stride + dim] - mn) << 22) | (uint64_t)id;
+      const uint64_t ck = ((uint64_t)(uint32_t)(t.V[(size_t)id * t.stride + dim] - mn) << 22) | (uint64_t)id;
       if (ck < pivot) { leftmask |= 1u << i; ++nl; }
       ++nv;
     }
@@ -244,8 +284,8 @@ __global__ __launch_bounds__(kTpb) void k_tree_partition(const int32_t* __restri
     __syncthreads();
   }
   if (threadIdx.x == kTpb - 1) {
-    baseL = atomicAdd(&counters[node * 2], sl[kTpb - 1]);
-    baseR = atomicAdd(&counters[node * 2 + 1], sr[kTpb - 1]);
+    baseL = atomicAdd(&t.cnt[node * 2], sl[kTpb - 1]);
+    baseR = atomicAdd(&t.cnt[node * 2 + 1], sr[kTpb - 1]);
   }
   __syncthreads();
   int pl = start + baseL + sl[threadIdx.x] - nl;
@@ -290,10 +330,15 @@ __device__ void bitonic_sort(uint64_t* key, int P) {
   }
 }
 
-__global__ __launch_bounds__(kSubTpb) void k_tree_subtree(const int32_t* __restrict__ V, int stride, int D, int N,
-                                                          int top, int leaf, const int32_t* __restrict__ perm_in,
-                                                          int32_t* __restrict__ perm_out, int32_t* __restrict__ node_dim,
-                                                          int32_t* __restrict__ node_split) {
+// grid: (2^maxTop, fields); block x finishes the subtree rooted at node x of
+// depth top (of its field)
+__global__ __launch_bounds__(kSubTpb) void k_tree_subtree(const FieldRec* __restrict__ table, int leaf) {
+  const TreeView t = tree_view(table[blockIdx.y]);
+  if ((int)blockIdx.x >= (1 << t.top)) return;
+  const int32_t* perm_in = (t.top & 1) ? t.perm2 : t.perm;
+  int32_t* perm_out = t.perm;
+  const int32_t* V = t.V;
+  const int stride = t.stride, D = t.D, N = t.N;
   __shared__ uint64_t key[kTreeLds];
   __shared__ int32_t enode[kTreeLds];       // heap node of the segment holding position e
   __shared__ uint16_t eseg[kTreeLds];       // local start of that segment
@@ -301,7 +346,7 @@ __global__ __launch_bounds__(kSubTpb) void k_tree_subtree(const int32_t* __restr
   __shared__ int32_t s_min[kTreeLds / 2], s_max[kTreeLds / 2];
   __shared__ int32_t s_best[kTreeLds / 2], s_dim[kTreeLds / 2], s_bmin[kTreeLds / 2];
   __shared__ int s_any;
-  const int root = (1 << top) - 1 + blockIdx.x;
+  const int root = (1 << t.top) - 1 + blockIdx.x;
   int rstart, rcnt;
   heap_range(root, N, rstart, rcnt);
   int P = 1;
@@ -317,8 +362,8 @@ __global__ __launch_bounds__(kSubTpb) void k_tree_subtree(const int32_t* __restr
   }
   __syncthreads();
   const uint64_t idmask = (1ull << 22) - 1;
-  for (int t = 0;; ++t) {
-    const int nslots = 1 << t;
+  for (int lvl = 0;; ++lvl) {
+    const int nslots = 1 << lvl;
     const int base = (root + 1) * nslots - 1;    // first heap index at this relative depth
     if (threadIdx.x == 0) s_any = 0;
     __syncthreads();
@@ -368,8 +413,8 @@ __global__ __launch_bounds__(kSubTpb) void k_tree_subtree(const int32_t* __restr
       if (s_cnt[s] > leaf) {
         const int h = s_cnt[s] >> 1;
         const uint64_t pid = key[s_start[s] + h] & idmask;
-        node_dim[base + s] = s_dim[s];
-        node_split[base + s] = V[(size_t)pid * stride + s_dim[s]];
+        t.dim[base + s] = s_dim[s];
+        t.split[base + s] = V[(size_t)pid * stride + s_dim[s]];
       }
     }
     for (int e = threadIdx.x; e < rcnt; e += kSubTpb) {
@@ -394,38 +439,17 @@ __global__ __launch_bounds__(kSubTpb) void k_tree_subtree(const int32_t* __restr
   for (int e = threadIdx.x; e < rcnt; e += kSubTpb) perm_out[rstart + e] = (int32_t)(key[e] & idmask);
 }
 
-ff_status enqueue_tree_build(const int32_t* V, int N, int D, int stride, int leaf, const TreeLayout& L, char* ws,
-                             hipStream_t stream) {
-  int32_t* node_dim = reinterpret_cast<int32_t*>(ws + L.off_dim);
-  int32_t* node_split = reinterpret_cast<int32_t*>(ws + L.off_split);
-  int32_t* perm = reinterpret_cast<int32_t*>(ws + L.off_perm);
-  int32_t* perm2 = reinterpret_cast<int32_t*>(ws + L.off_perm2);
-  int32_t* mm = reinterpret_cast<int32_t*>(ws + L.off_minmax);
-  int32_t* hist = reinterpret_cast<int32_t*>(ws + L.off_hist);
-  int32_t* cnt = reinterpret_cast<int32_t*>(ws + L.off_cnt);
-  const int topnodes = (1 << L.top) - 1;
-  fill_i32(node_dim, L.nodes, -1, stream);
-  fill_i32(node_split, L.nodes, 0, stream);
-  k_iota<<<(N + 255) / 256, 256, 0, stream>>>(perm, N);
-  if (L.top > 0) {
-    k_minmax_init<<<(topnodes * 64 + 255) / 256, 256, 0, stream>>>(mm, topnodes * 64);
-    fill_i32(hist, (size_t)topnodes * kSelPasses * kSelBins, 0, stream);
-    fill_i32(cnt, (size_t)topnodes * 2, 0, stream);
+ff_status enqueue_tree_build(const FieldRec* table, int nf, int maxN, int maxTop, int leaf, hipStream_t stream) {
+  (void)leaf;
+  k_tree_init<<<dim3(512, nf), 256, 0, stream>>>(table);
+  for (int d = 0; d < maxTop; ++d) {
+    const int maxcnt = (int)(((int64_t)maxN + (1LL << d) - 1) >> d);
+    const dim3 grid((maxcnt + kChunk - 1) / kChunk, 1 << d, nf);
+    k_tree_minmax<<<grid, kTpb, 0, stream>>>(table, d);
+    for (int p = 0; p < kSelPasses; ++p) k_tree_hist<<<grid, kTpb, 0, stream>>>(table, d, p);
+    k_tree_partition<<<grid, kTpb, 0, stream>>>(table, d);
   }
-  int32_t* cur = perm;
-  int32_t* nxt = perm2;
-  for (int d = 0; d < L.top; ++d) {
-    const int maxcnt = (int)(((int64_t)N + (1LL << d) - 1) >> d);
-    const dim3 grid((maxcnt + kChunk - 1) / kChunk, 1 << d);
-    k_tree_minmax<<<grid, kTpb, 0, stream>>>(V, stride, D, N, d, cur, mm);
-    for (int p = 0; p < kSelPasses; ++p)
-      k_tree_hist<<<grid, kTpb, 0, stream>>>(V, stride, D, N, d, cur, mm, hist, node_dim, p);
-    k_tree_partition<<<grid, kTpb, 0, stream>>>(V, stride, D, N, d, cur, nxt, mm, hist, cnt, node_split);
-    int32_t* t = cur;
-    cur = nxt;
-    nxt = t;
-  }
-  k_tree_subtree<<<1 << L.top, kSubTpb, 0, stream>>>(V, stride, D, N, L.top, leaf, cur, perm, node_dim, node_split);
+  k_tree_subtree<<<dim3(1 << maxTop, nf), kSubTpb, 0, stream>>>(table, leaf);
   return launch_status();
 }
 

@@ -46,8 +46,15 @@ class ff_desc(C.Structure):
 class ff_match_params(C.Structure):
     _fields_ = [("k", C.c_int32), ("R", C.c_int32), ("leaf", C.c_int32), ("n_prop", C.c_int32),
                 ("n_rs", C.c_int32), ("use_kdtree", C.c_int32), ("max_steps", C.c_int32),
-                ("field_id", C.c_uint32), ("pair_id", C.c_uint32), ("reserved", C.c_uint32),
+                ("field_id", C.c_uint32), ("pair_id", C.c_uint32), ("band_rows", C.c_int32),
                 ("seed", C.c_uint64)]
+
+
+class ff_field_job(C.Structure):
+    _fields_ = [("src", C.POINTER(ff_desc)), ("src_blob", C.c_void_p), ("dst", C.POINTER(ff_desc)),
+                ("dst_blob", C.c_void_p), ("radius", C.c_int32), ("field_id", C.c_uint32), ("pair_id", C.c_uint32),
+                ("reserved", C.c_uint32), ("seed", C.c_uint64), ("proposal", C.c_void_p), ("flow", C.c_void_p),
+                ("cost", C.c_void_p)]
 
 
 _lib = None
@@ -74,6 +81,14 @@ def lib():
         L.ff_match_field.argtypes = [C.POINTER(ff_desc), P, C.POINTER(ff_desc), P, i32, C.POINTER(ff_match_params),
                                      P, P, P, P, C.c_size_t, P]
         L.ff_match_field.restype = i32
+        L.ff_match_batch_workspace_bytes.argtypes = [C.POINTER(ff_field_job), i32, C.POINTER(ff_match_params)]
+        L.ff_match_batch_workspace_bytes.restype = C.c_size_t
+        L.ff_match_batch.argtypes = [C.POINTER(ff_field_job), i32, C.POINTER(ff_match_params), P, C.c_size_t, P]
+        L.ff_match_batch.restype = i32
+        L.ff_profile_begin.argtypes = [i32, i32]
+        L.ff_profile_begin.restype = i32
+        L.ff_profile_end.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+        L.ff_profile_end.restype = i32
         L.ff_consistency_filter.argtypes = [P, i32, i32, P, i32, i32, i32, i32, i32, P, P, P]
         L.ff_consistency_filter.restype = i32
         L.ff_tree_nodes.argtypes = [i32, i32]
@@ -148,6 +163,37 @@ def ff_match_field(src: ff_desc, src_blob, dst: ff_desc, dst_blob, radius: int, 
     _check(lib().ff_match_field(C.byref(src), _ptr(src_blob), C.byref(dst), _ptr(dst_blob), radius, C.byref(p),
                                 _ptr(proposal), _ptr(flow), _ptr(cost), _ptr(workspace), workspace.numel(),
                                 _stream(stream)), "ff_match_field")
+
+
+def make_job(src: ff_desc, src_blob, dst: ff_desc, dst_blob, radius, flow, cost, field_id=0, pair_id=0, seed=0,
+             proposal=None) -> ff_field_job:
+    j = ff_field_job()
+    j.src = C.pointer(src)
+    j.src_blob = src_blob.data_ptr()
+    j.dst = C.pointer(dst)
+    j.dst_blob = dst_blob.data_ptr()
+    j.radius = radius
+    j.field_id = field_id
+    j.pair_id = pair_id
+    j.seed = seed
+    j.proposal = None if proposal is None else proposal.data_ptr()
+    j.flow = flow.data_ptr()
+    j.cost = cost.data_ptr()
+    return j
+
+
+def ff_match_batch_workspace_bytes(jobs, p: ff_match_params) -> int:
+    arr = (ff_field_job * len(jobs))(*jobs)
+    n = lib().ff_match_batch_workspace_bytes(arr, len(jobs), C.byref(p))
+    if n == 0:
+        raise FFError(-1, "ff_match_batch_workspace_bytes")
+    return n
+
+
+def ff_match_batch(jobs, p: ff_match_params, workspace, stream=None):
+    arr = (ff_field_job * len(jobs))(*jobs)
+    _check(lib().ff_match_batch(arr, len(jobs), C.byref(p), _ptr(workspace), workspace.numel(), _stream(stream)),
+           "ff_match_batch")
 
 
 def ff_consistency_filter(flow_fwd, flows_bwd, subpel, eps_q, keep, flow_filtered, stream=None):
@@ -244,3 +290,85 @@ class PairMatcher:
 
     def status(self):
         return [ff_read_status(w) for w in self.ws]
+
+
+class BatchMatcher:
+    """The whole hot path for many pairs (any sizes) at once: descriptors of
+    every image, then one ff_match_batch call for all 3 fields of all pairs
+    (each stage one launch), then the consistency filter of every pair.
+    `run` can be captured in a HIP graph (see `capture`)."""
+
+    def __init__(self, shapes, channels=3, r=8, r2=6, k=3, subpel=4, eps=5, device="cuda", band_rows=16,
+                 proposals=False):
+        self.shapes = list(shapes)            # (W, H) per pair
+        self.C, self.r, self.r2, self.k, self.Q, self.eps = channels, r, r2, k, subpel, eps
+        self.params = ff_default_params(k=k, band_rows=band_rows)
+        self.descs, self.blobs1, self.blobs2, self.out = [], [], [], []
+        for (W, H) in self.shapes:
+            d = ff_desc_init(W, H, channels, k, subpel, (r, r2) if r2 != r else (r,))
+            self.descs.append(d)
+            self.blobs1.append(torch.empty(d.bytes, dtype=torch.uint8, device=device))
+            self.blobs2.append(torch.empty(d.bytes, dtype=torch.uint8, device=device))
+            o = {name: (torch.empty((H, W), dtype=torch.int32, device=device),
+                        torch.empty((H, W), dtype=torch.int32, device=device)) for name in ("F", "B1", "B2")}
+            o["keep"] = torch.empty((H, W), dtype=torch.uint8, device=device)
+            o["filtered"] = torch.empty((H, W), dtype=torch.int32, device=device)
+            self.out.append(o)
+        self.proposals = [None] * len(self.shapes)
+        self.seeds = [0] * len(self.shapes)
+        self._jobs_cache = None
+        self.ws = None
+
+    def jobs(self):
+        jobs = []
+        for i, d in enumerate(self.descs):
+            o = self.out[i]
+            for name, rad, fid, (s, sb, t, tb) in (("F", self.r, 0, (d, self.blobs1[i], d, self.blobs2[i])),
+                                                    ("B1", self.r, 1, (d, self.blobs2[i], d, self.blobs1[i])),
+                                                    ("B2", self.r2, 2, (d, self.blobs2[i], d, self.blobs1[i]))):
+                jobs.append(make_job(s, sb, t, tb, rad, o[name][0], o[name][1], field_id=fid, pair_id=i,
+                                     seed=self.seeds[i], proposal=self.proposals[i] if name == "F" else None))
+        return jobs
+
+    def run(self, imgs1, imgs2, seeds=None, proposals=None, stream=None):
+        stream = stream or torch.cuda.current_stream()
+        if seeds is not None:
+            self.seeds = list(seeds)
+        if proposals is not None:
+            self.proposals = list(proposals)
+        for i, d in enumerate(self.descs):
+            ff_compute_descriptors(d, imgs1[i], self.blobs1[i], stream)
+            ff_compute_descriptors(d, imgs2[i], self.blobs2[i], stream)
+        jobs = self.jobs()
+        need = ff_match_batch_workspace_bytes(jobs, self.params)
+        if self.ws is None or self.ws.numel() < need:
+            self.ws = torch.empty(need, dtype=torch.uint8, device=self.blobs1[0].device)
+        ff_match_batch(jobs, self.params, self.ws, stream)
+        for o in self.out:
+            ff_consistency_filter(o["F"][0], [o["B1"][0], o["B2"][0]], self.Q, self.eps * self.Q, o["keep"],
+                                  o["filtered"], stream)
+        return self.out
+
+    def status(self):
+        return ff_read_status(self.ws)
+
+    def autotune(self, imgs1, imgs2, candidates=(8, 16, 32), reps=2):
+        """Time the propagation band height on this batch; keep the fastest
+        (every candidate gives identical bytes)."""
+        best = None
+        for bh in candidates:
+            self.params.band_rows = bh
+            self.run(imgs1, imgs2)
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            for _ in range(reps):
+                self.run(imgs1, imgs2)
+            t1.record()
+            torch.cuda.synchronize()
+            ms = t0.elapsed_time(t1) / reps
+            if best is None or ms < best[1]:
+                best = (bh, ms)
+        self.params.band_rows = best[0]
+        return best
