@@ -342,6 +342,19 @@ def config3_pairs(n_pairs: int = 64, seed0: int = 3000, sizes=CONFIG3_SIZES):
     return out
 
 
+def _config3_one(args):
+    i, seed0, sizes = args
+    return config3_pairs(1, seed0 + i, sizes)[0]
+
+
+def config3_pairs_parallel(n_pairs: int = 64, seed0: int = 3000, sizes=CONFIG3_SIZES, workers: int = 8):
+    """config3_pairs with the pairs drawn in a process pool (same bytes:
+    pair i only depends on its own seed seed0 + i)."""
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(workers) as pool:
+        return pool.map(_config3_one, [(i, seed0, sizes) for i in range(n_pairs)])
+
+
 def config4_batch(first_seed: int, batch: int = 16, W: int = 1024, H: int = 436):
     """A batch of config-1-recipe pairs (seeds first_seed .. first_seed+batch-1)."""
     return [config1_pair(first_seed + i, W, H) for i in range(batch)]
