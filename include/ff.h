@@ -198,6 +198,55 @@ ff_status ff_build_kdtree(const ff_desc* d, const void* blob, int32_t radius, in
                           int32_t* node_split, int32_t* perm, void* workspace, size_t workspace_bytes,
                           hipStream_t stream);
 
+/*
+ * Learned coarse-flow proposal (an extension outside the paper: the paper's
+ * initial matches come from the kd-tree of section 3.1 only).  A fixed 6-layer
+ * 3x3 convolutional network maps the stacked RGB pair to one flow per point
+ * of the 1/8 grid, i.e. the seed grid of a k = 3 match (section 3.2), whose
+ * rounded value the seed step evaluates as one more candidate through
+ * ff_field_job.proposal / ff_match_field's proposal: the data term of Eq. 1
+ * still decides.
+ *
+ * Layers (Cin, Cout, stride, dilation, ReLU): (6,32,2,1,y) (32,32,2,1,y)
+ * (32,32,2,1,y) (32,32,1,4,y) (32,32,1,8,y) (32,2,1,1,n); zero padding equal
+ * to the dilation, so an output is ceil(size / stride).  Input x = RGB / 255
+ * - 1/2 of both frames (6 channels); flow in px = 32 x output.  Weights and
+ * activations are rounded to bf16 (nearest even); sums accumulate in fp32.
+ *
+ * params: device float32[ff_net_param_count()], per layer W[co][ci][ky][kx]
+ *   then b[co] (39330 values).
+ * img1, img2: device u8, batch x height x width x 3 each (RGB, rows packed).
+ * workspace: device, ff_net_workspace_bytes(batch, width, height) bytes.
+ * Errors: FF_ERR_ARG for null pointers, subpel not in {1,2,4,8}, batch not
+ * in 1..256 or a side under 8 or above 8191; FF_ERR_SIZE if batch x width x
+ * height exceeds 2^30; FF_ERR_WORKSPACE if the workspace is too small.
+ */
+int32_t ff_net_param_count(void);
+size_t ff_net_workspace_bytes(int32_t batch, int32_t width, int32_t height);
+
+/* Inference.  proposal: device int32, batch x ceil(height/8) x ceil(width/8)
+ * packed flows in 1/subpel px (round to nearest even of 32 x out x subpel,
+ * clamped to +-32767); flow_out (device, nullable): the same points as fp32
+ * (x, y) pairs in output units (px / 32). */
+ff_status ff_proposal_forward(const float* params, const uint8_t* img1, const uint8_t* img2, int32_t batch,
+                              int32_t width, int32_t height, int32_t subpel, int32_t* proposal, float* flow_out,
+                              void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* One training step.  labels: device int32, batch x ceil(height/8) x
+ * ceil(width/8) packed flows in 1/subpel px, FF_EMPTY where unlabelled.
+ * Loss = mean over labelled points of |out_x - t_x| + |out_y - t_y| with t
+ * the label in px / 32.  Gradients of the stored activations are rounded to
+ * bf16; weight gradients are summed in a fixed order (run to run identical).
+ * With adam_m and adam_v (device float32, param count each, zero at step 1)
+ * params get one Adam update (beta 0.9 / 0.999, eps 1e-8, bias-corrected by
+ * step >= 1, rate lr); with both null params are left unchanged.
+ * grad_out (device float32[param count], nullable): the gradient;
+ * loss_out (device float32[1], nullable): the loss before the update. */
+ff_status ff_proposal_train_step(float* params, float* adam_m, float* adam_v, int32_t step, float lr,
+                                 const uint8_t* img1, const uint8_t* img2, const int32_t* labels, int32_t batch,
+                                 int32_t width, int32_t height, int32_t subpel, float* grad_out, float* loss_out,
+                                 void* workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* After the stream has finished: read the device status word a match call
  * left in its workspace (FF_OK, or FF_ERR_DEVICE if a watchdog fired). */
 ff_status ff_read_status(const void* workspace, int32_t* status_host);
@@ -220,7 +269,9 @@ typedef enum {
   FF_PROF_LEVEL_ENTRY = 4,
   FF_PROF_PROPAGATE = 5,     /* one propagation sweep kernel */
   FF_PROF_RANDOM_SEARCH = 6,
-  FF_PROF_FILTER = 7
+  FF_PROF_FILTER = 7,
+  FF_PROF_PROPOSAL = 8,      /* the whole ff_proposal_forward sequence */
+  FF_PROF_TRAIN = 9          /* the whole ff_proposal_train_step sequence */
 } ff_prof_class;
 ff_status ff_profile_begin(int32_t kernel_class, int32_t max_launches);
 ff_status ff_profile_end(double* total_ms, int32_t* launches);

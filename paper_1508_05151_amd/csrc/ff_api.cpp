@@ -36,7 +36,7 @@ extern "C" {
 
 ff_status ff_profile_begin(int32_t kernel_class, int32_t max_launches) {
   using namespace ff;
-  if (kernel_class < 1 || kernel_class > 7 || max_launches < 1 || max_launches > 1 << 20) return FF_ERR_ARG;
+  if (kernel_class < 1 || kernel_class > 9 || max_launches < 1 || max_launches > 1 << 20) return FF_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   for (auto e : g_prof_start) hipEventDestroy(e);
   for (auto e : g_prof_stop) hipEventDestroy(e);

@@ -99,6 +99,15 @@ def lib():
         L.ff_read_status.restype = i32
         L.ff_status_string.argtypes = [i32]
         L.ff_status_string.restype = C.c_char_p
+        L.ff_net_param_count.argtypes = []
+        L.ff_net_param_count.restype = i32
+        L.ff_net_workspace_bytes.argtypes = [i32, i32, i32]
+        L.ff_net_workspace_bytes.restype = C.c_size_t
+        L.ff_proposal_forward.argtypes = [P, P, P, i32, i32, i32, i32, P, P, P, C.c_size_t, P]
+        L.ff_proposal_forward.restype = i32
+        L.ff_proposal_train_step.argtypes = [P, P, P, i32, C.c_float, P, P, P, i32, i32, i32, i32, P, P, P,
+                                             C.c_size_t, P]
+        L.ff_proposal_train_step.restype = i32
         _lib = L
     return _lib
 
@@ -299,10 +308,10 @@ class BatchMatcher:
     `run` can be captured in a HIP graph (see `capture`)."""
 
     def __init__(self, shapes, channels=3, r=8, r2=6, k=3, subpel=4, eps=5, device="cuda", band_rows=16,
-                 proposals=False):
+                 use_kdtree=1):
         self.shapes = list(shapes)            # (W, H) per pair
         self.C, self.r, self.r2, self.k, self.Q, self.eps = channels, r, r2, k, subpel, eps
-        self.params = ff_default_params(k=k, band_rows=band_rows)
+        self.params = ff_default_params(k=k, band_rows=band_rows, use_kdtree=use_kdtree)
         self.descs, self.blobs1, self.blobs2, self.out = [], [], [], []
         for (W, H) in self.shapes:
             d = ff_desc_init(W, H, channels, k, subpel, (r, r2) if r2 != r else (r,))
@@ -319,6 +328,14 @@ class BatchMatcher:
         self._jobs_cache = None
         self.ws = None
 
+    def _proposal(self, i, name):
+        """Per pair: None, a tensor (F only) or (forward, backward) where the
+        backward proposal serves B1 and B2."""
+        p = self.proposals[i]
+        if isinstance(p, (tuple, list)):
+            return p[0] if name == "F" else p[1]
+        return p if name == "F" else None
+
     def jobs(self):
         jobs = []
         for i, d in enumerate(self.descs):
@@ -327,7 +344,7 @@ class BatchMatcher:
                                                     ("B1", self.r, 1, (d, self.blobs2[i], d, self.blobs1[i])),
                                                     ("B2", self.r2, 2, (d, self.blobs2[i], d, self.blobs1[i]))):
                 jobs.append(make_job(s, sb, t, tb, rad, o[name][0], o[name][1], field_id=fid, pair_id=i,
-                                     seed=self.seeds[i], proposal=self.proposals[i] if name == "F" else None))
+                                     seed=self.seeds[i], proposal=self._proposal(i, name)))
         return jobs
 
     def run(self, imgs1, imgs2, seeds=None, proposals=None, stream=None):
@@ -372,3 +389,119 @@ class BatchMatcher:
                 best = (bh, ms)
         self.params.band_rows = best[0]
         return best
+
+
+# ------------------------------------------------------------------ learned proposal
+NET_FLOW_SCALE = 32.0   # flow in px = 32 x network output
+NET_LAYERS = [(6, 32, 2, 1, True), (32, 32, 2, 1, True), (32, 32, 2, 1, True),
+              (32, 32, 1, 4, True), (32, 32, 1, 8, True), (32, 2, 1, 1, False)]
+
+
+def ff_net_param_count() -> int:
+    return lib().ff_net_param_count()
+
+
+def ff_net_workspace_bytes(batch, width, height) -> int:
+    n = lib().ff_net_workspace_bytes(batch, width, height)
+    if n == 0:
+        raise FFError(-1, "ff_net_workspace_bytes")
+    return n
+
+
+def ff_proposal_forward(params, img1, img2, proposal, workspace, subpel=4, flow_out=None, stream=None):
+    B, H, W = img1.shape[:3]
+    _check(lib().ff_proposal_forward(_ptr(params), _ptr(img1), _ptr(img2), B, W, H, subpel, _ptr(proposal),
+                                     _ptr(flow_out), _ptr(workspace), workspace.numel(), _stream(stream)),
+           "ff_proposal_forward")
+
+
+def ff_proposal_train_step(params, adam_m, adam_v, step, lr, img1, img2, labels, workspace, subpel=4,
+                           grad_out=None, loss_out=None, stream=None):
+    B, H, W = img1.shape[:3]
+    _check(lib().ff_proposal_train_step(_ptr(params), _ptr(adam_m), _ptr(adam_v), step, lr, _ptr(img1), _ptr(img2),
+                                        _ptr(labels), B, W, H, subpel, _ptr(grad_out), _ptr(loss_out),
+                                        _ptr(workspace), workspace.numel(), _stream(stream)),
+           "ff_proposal_train_step")
+
+
+def net_init_params(seed=0):
+    """He-normal weights, zero biases, float32 on the host (parameter layout
+    of ff_proposal_forward)."""
+    g = torch.Generator().manual_seed(seed)
+    parts = []
+    for ci, co, _, _, relu in NET_LAYERS:
+        std = (2.0 / (ci * 9)) ** 0.5 if relu else (1.0 / (ci * 9)) ** 0.5
+        parts.append(torch.randn(co * ci * 9, generator=g, dtype=torch.float32) * std)
+        parts.append(torch.zeros(co, dtype=torch.float32))
+    return torch.cat(parts)
+
+
+def seed_grid(width, height, k=3):
+    s = 1 << k
+    return (height + s - 1) // s, (width + s - 1) // s
+
+
+class ProposalNet:
+    """Parameters, Adam state and workspaces of the proposal network on one
+    device.  Images: uint8 tensors batch x H x W x 3 (or H x W x 3)."""
+
+    def __init__(self, params=None, seed=0, device="cuda", subpel=4):
+        if ff_net_param_count() != sum(co * ci * 9 + co for ci, co, _, _, _ in NET_LAYERS):
+            raise FFError(-1, "network layout mismatch")
+        p = net_init_params(seed) if params is None else torch.as_tensor(params, dtype=torch.float32).reshape(-1)
+        self.device = device
+        self.subpel = subpel
+        self.params = p.to(device).contiguous()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self._ws = {}
+
+    def workspace(self, batch, width, height):
+        key = (batch, width, height)
+        if key not in self._ws:
+            self._ws[key] = torch.empty(ff_net_workspace_bytes(batch, width, height), dtype=torch.uint8,
+                                        device=self.device)
+        return self._ws[key]
+
+    @staticmethod
+    def _b(img):
+        return img if img.dim() == 4 else img.unsqueeze(0)
+
+    def forward(self, img1, img2, proposal=None, flow_out=None, stream=None):
+        i1, i2 = self._b(img1), self._b(img2)
+        B, H, W = i1.shape[:3]
+        hc, wc = seed_grid(W, H)
+        if proposal is None:
+            proposal = torch.empty((B, hc, wc), dtype=torch.int32, device=self.device)
+        ff_proposal_forward(self.params, i1, i2, proposal, self.workspace(B, W, H), self.subpel, flow_out, stream)
+        return proposal
+
+    def gradient(self, img1, img2, labels, stream=None):
+        """Loss and parameter gradient without an update."""
+        i1, i2 = self._b(img1), self._b(img2)
+        B, H, W = i1.shape[:3]
+        g = torch.empty_like(self.params)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        ff_proposal_train_step(self.params, None, None, 0, 0.0, i1, i2, labels, self.workspace(B, W, H),
+                               self.subpel, g, loss, stream)
+        return loss, g
+
+    def train_step(self, img1, img2, labels, lr, stream=None):
+        i1, i2 = self._b(img1), self._b(img2)
+        B, H, W = i1.shape[:3]
+        self.step += 1
+        ff_proposal_train_step(self.params, self.m, self.v, self.step, lr, i1, i2, labels,
+                               self.workspace(B, W, H), self.subpel, None, self.loss, stream)
+        return self.loss
+
+    def state_dict(self):
+        return dict(params=self.params.cpu(), m=self.m.cpu(), v=self.v.cpu(),
+                    step=torch.tensor(self.step, dtype=torch.int64))
+
+    def load_state_dict(self, sd):
+        self.params.copy_(sd["params"])
+        self.m.copy_(sd["m"])
+        self.v.copy_(sd["v"])
+        self.step = int(sd["step"])

@@ -74,3 +74,14 @@ def test_match_argument_checks_before_any_launch(ff):
     assert L.ff_consistency_filter(None, 4, 4, None, 1, 4, 4, 4, 20, None, None, None) == -1
     assert ff.ff_tree_nodes(446464, 8) == (2 << 16) - 1
     assert L.ff_status_string(-6) == b"device watchdog fired"
+
+
+def test_network_entry_points_validate(ff):
+    L = ff.lib()
+    assert ff.ff_net_param_count() == 39330
+    assert L.ff_net_workspace_bytes(0, 64, 64) == 0 and L.ff_net_workspace_bytes(1, 7, 64) == 0
+    assert L.ff_net_workspace_bytes(257, 64, 64) == 0
+    assert L.ff_net_workspace_bytes(2, 64, 48) > 0
+    assert L.ff_proposal_forward(None, None, None, 1, 64, 64, 4, None, None, None, 0, None) == -1
+    assert L.ff_proposal_train_step(None, None, None, 1, 1e-3, None, None, None, 1, 64, 64, 4, None, None, None, 0,
+                                    None) == -1
