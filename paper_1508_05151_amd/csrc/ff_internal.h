@@ -37,7 +37,7 @@ constexpr int kSelPasses = 4;
 struct TreeLayout {
   int N, depth, nodes;   // nodes = (2 << depth) - 1
   int top;               // levels handled by the global passes
-  size_t off_dim, off_split, off_perm, off_perm2, off_minmax, off_hist, off_cnt;
+  size_t off_dim, off_split, off_perm, off_perm2, off_minmax, off_hist, off_cnt, off_key;
   size_t bytes;
 };
 TreeLayout tree_layout(int N, int leaf, size_t base);
@@ -62,7 +62,7 @@ struct FieldRec {
   uint32_t k0, k1, c3, pad1;
   // kd-tree over the target (offsets into ws)
   int32_t t_nodes, t_top, pad2, pad3;
-  uint32_t o_dim, o_split, o_perm, o_perm2, o_mm, o_hist, o_cnt, pad4;
+  uint32_t o_dim, o_split, o_perm, o_perm2, o_mm, o_hist, o_cnt, o_key;
   // level grids n = 2..2^k (flow then cost) and the band handoff words
   uint32_t o_grid[5];
   uint32_t o_xch;

@@ -717,6 +717,7 @@ static FieldRec make_rec(const ff_field_job& j, const ff_match_params* p, char* 
     r.o_mm = (uint32_t)P.tree.off_minmax;
     r.o_hist = (uint32_t)P.tree.off_hist;
     r.o_cnt = (uint32_t)P.tree.off_cnt;
+    r.o_key = (uint32_t)P.tree.off_key;
   }
   for (int l = 0; l < 5; ++l) r.o_grid[l] = (uint32_t)P.off_grid[l];
   r.o_xch = (uint32_t)P.off_xch;

@@ -45,6 +45,7 @@ TreeLayout tree_layout(int N, int leaf, size_t base) {
   L.off_minmax = off; off = align_up(off + topnodes * 64 * 4, 256);
   L.off_hist = off;  off = align_up(off + topnodes * kSelPasses * kSelBins * 4, 256);
   L.off_cnt = off;   off = align_up(off + topnodes * 2 * 4, 256);
+  L.off_key = off;   off = align_up(off + (size_t)N * 4, 256);
   L.bytes = off - base;
   return L;
 }
@@ -66,6 +67,7 @@ struct TreeView {
   const int32_t* V;
   int N, D, stride, top, nodes;
   int32_t *dim, *split, *perm, *perm2, *mm, *hist, *cnt;
+  uint32_t* key;   // per position: value on the node's split dimension - node minimum
 };
 
 __device__ __forceinline__ TreeView tree_view(const FieldRec& f) {
@@ -83,6 +85,7 @@ __device__ __forceinline__ TreeView tree_view(const FieldRec& f) {
   t.mm = reinterpret_cast<int32_t*>(f.ws + f.o_mm);
   t.hist = reinterpret_cast<int32_t*>(f.ws + f.o_hist);
   t.cnt = reinterpret_cast<int32_t*>(f.ws + f.o_cnt);
+  t.key = reinterpret_cast<uint32_t*>(f.ws + f.o_key);
   return t;
 }
 
@@ -108,6 +111,14 @@ __global__ void k_tree_init(const FieldRec* __restrict__ table) {
 }
 
 // ---------------------------------------------------------------- top levels
+// Rows are read whole: 8 lanes per row, each lane 4 consecutive dimensions
+// (one 16-byte load), so a wavefront reads 8 full rows per instruction.
+constexpr int kLpr = 8;
+
+__device__ __forceinline__ int4 row_quad(const int32_t* V, int stride, int id, int j) {
+  return *reinterpret_cast<const int4*>(V + (size_t)id * stride + 4 * j);
+}
+
 // grid: (chunks, nodes at depth d, fields)
 __global__ __launch_bounds__(kTpb) void k_tree_minmax(const FieldRec* __restrict__ table, int d) {
   const TreeView t = tree_view(table[blockIdx.z]);
@@ -122,24 +133,30 @@ __global__ __launch_bounds__(kTpb) void k_tree_minmax(const FieldRec* __restrict
   __shared__ int32_t smin[32], smax[32];
   if (threadIdx.x < 32) { smin[threadIdx.x] = INT32_MAX; smax[threadIdx.x] = INT32_MIN; }
   __syncthreads();
-  int32_t mn[27], mx[27];
-#pragma unroll
-  for (int k = 0; k < 27; ++k) { mn[k] = INT32_MAX; mx[k] = INT32_MIN; }
-  for (int e = lo + threadIdx.x; e < hi; e += kTpb) {
-    const int32_t* v = t.V + (size_t)perm[start + e] * t.stride;
-#pragma unroll
-    for (int k = 0; k < 27; ++k)
-      if (k < t.D) { const int32_t x = v[k]; mn[k] = min(mn[k], x); mx[k] = max(mx[k], x); }
+  const int g = threadIdx.x / kLpr, q = threadIdx.x % kLpr;
+  const bool on = 4 * q < t.D;
+  int mn[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
+  int mx[4] = {INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN};
+  if (on) {
+#pragma unroll 4
+    for (int e = lo + g; e < hi; e += kTpb / kLpr) {
+      const int4 v = row_quad(t.V, t.stride, perm[start + e], q);
+      mn[0] = min(mn[0], v.x); mx[0] = max(mx[0], v.x);
+      mn[1] = min(mn[1], v.y); mx[1] = max(mx[1], v.y);
+      mn[2] = min(mn[2], v.z); mx[2] = max(mx[2], v.z);
+      mn[3] = min(mn[3], v.w); mx[3] = max(mx[3], v.w);
+    }
   }
 #pragma unroll
-  for (int k = 0; k < 27; ++k) {
-    if (k >= t.D) break;
-    int32_t a = mn[k], b = mx[k];
-    for (int o = 32; o > 0; o >>= 1) {
-      a = min(a, __shfl_xor(a, o));
-      b = max(b, __shfl_xor(b, o));
+  for (int i = 0; i < 4; ++i)
+    for (int o = kLpr; o < 64; o <<= 1) {
+      mn[i] = min(mn[i], __shfl_xor(mn[i], o));
+      mx[i] = max(mx[i], __shfl_xor(mx[i], o));
     }
-    if ((threadIdx.x & 63) == 0) { atomicMin(&smin[k], a); atomicMax(&smax[k], b); }
+  if ((threadIdx.x & 63) < kLpr && on) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (4 * q + i < t.D) { atomicMin(&smin[4 * q + i], mn[i]); atomicMax(&smax[4 * q + i], mx[i]); }
   }
   __syncthreads();
   const int node = (1 << d) - 1 + j;
@@ -226,7 +243,14 @@ __global__ __launch_bounds__(kTpb) void k_tree_hist(const FieldRec* __restrict__
   const int shift = 33 - 11 * pass;
   for (int e = lo + threadIdx.x; e < hi; e += kTpb) {
     const int id = perm[start + e];
-    const uint64_t ck = ((uint64_t)(uint32_t)(t.V[(size_t)id * t.stride + dim] - mn) << 22) | (uint64_t)id;
+    uint32_t kv;
+    if (pass == 0) {
+      kv = (uint32_t)(t.V[(size_t)id * t.stride + dim] - mn);
+      t.key[start + e] = kv;
+    } else {
+      kv = t.key[start + e];
+    }
+    const uint64_t ck = ((uint64_t)kv << 22) | (uint64_t)id;
     if ((ck >> (shift + 11)) == prefix) atomicAdd(&lh[(ck >> shift) & (kSelBins - 1)], 1);
   }
   __syncthreads();
@@ -265,7 +289,7 @@ __global__ __launch_bounds__(kTpb) void k_tree_partition(const FieldRec* __restr
     if (e < hi) {
       const int id = perm[start + e];
       ids[i] = id;
-      const uint64_t ck = ((uint64_t)(uint32_t)(t.V[(size_t)id * t.stride + dim] - mn) << 22) | (uint64_t)id;
+      const uint64_t ck = ((uint64_t)t.key[start + e] << 22) | (uint64_t)id;
       if (ck < pivot) { leftmask |= 1u << i; ++nl; }
       ++nv;
     }
@@ -343,8 +367,8 @@ __global__ __launch_bounds__(kSubTpb) void k_tree_subtree(const FieldRec* __rest
   __shared__ int32_t enode[kTreeLds];       // heap node of the segment holding position e
   __shared__ uint16_t eseg[kTreeLds];       // local start of that segment
   __shared__ int32_t s_start[kTreeLds / 2], s_cnt[kTreeLds / 2];
-  __shared__ int32_t s_min[kTreeLds / 2], s_max[kTreeLds / 2];
   __shared__ int32_t s_best[kTreeLds / 2], s_dim[kTreeLds / 2], s_bmin[kTreeLds / 2];
+  __shared__ int32_t s_pmin[kSubTpb / 64][32], s_pmax[kSubTpb / 64][32];
   __shared__ int s_any;
   const int root = (1 << t.top) - 1 + blockIdx.x;
   int rstart, rcnt;
@@ -379,23 +403,74 @@ __global__ __launch_bounds__(kSubTpb) void k_tree_subtree(const FieldRec* __rest
     }
     __syncthreads();
     if (!s_any) break;
-    for (int k = 0; k < D; ++k) {
-      for (int s = threadIdx.x; s < nslots; s += kSubTpb) { s_min[s] = INT32_MAX; s_max[s] = INT32_MIN; }
-      __syncthreads();
-      for (int e = threadIdx.x; e < rcnt; e += kSubTpb) {
-        const int s = enode[e] - base;
-        if (s >= 0 && s < nslots && s_cnt[s] > leaf) {
-          const int32_t v = V[(size_t)(key[e] & idmask) * stride + k];
-          atomicMin(&s_min[s], v);
-          atomicMax(&s_max[s], v);
+    // Split dimension of every splitting segment in one pass over its rows:
+    // 64 groups of 8 lanes, a lane holding 4 dimensions of a row.  With
+    // fewer than 64 segments, gps groups share a segment (partials merged by
+    // shuffles inside a wavefront, then through LDS across wavefronts); with
+    // more, each group walks spg segments.
+    {
+      const int g = threadIdx.x >> 3, q = threadIdx.x & 7, wv = threadIdx.x >> 6;
+      const int gps = nslots >= 64 ? 1 : 64 / nslots;
+      const int spg = nslots >= 64 ? nslots / 64 : 1;
+      for (int si = 0; si < spg; ++si) {
+        const int s = nslots >= 64 ? g * spg + si : g / gps;
+        const int part = nslots >= 64 ? 0 : g % gps;
+        const bool act = s_cnt[s] > leaf;
+        int mn[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
+        int mx[4] = {INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN};
+        if (act && 4 * q < D) {
+          const int c = s_cnt[s], st = s_start[s];
+          const int a = st + c * part / gps, b = st + c * (part + 1) / gps;
+#pragma unroll 4
+          for (int e = a; e < b; ++e) {
+            const int4 v = row_quad(V, stride, (int)(key[e] & idmask), q);
+            mn[0] = min(mn[0], v.x); mx[0] = max(mx[0], v.x);
+            mn[1] = min(mn[1], v.y); mx[1] = max(mx[1], v.y);
+            mn[2] = min(mn[2], v.z); mx[2] = max(mx[2], v.z);
+            mn[3] = min(mn[3], v.w); mx[3] = max(mx[3], v.w);
+          }
         }
-      }
-      __syncthreads();
-      for (int s = threadIdx.x; s < nslots; s += kSubTpb) {
-        if (s_cnt[s] > leaf) {
-          const int32_t spread = s_max[s] - s_min[s];
-          if (spread > s_best[s]) { s_best[s] = spread; s_dim[s] = k; s_bmin[s] = s_min[s]; }
+        for (int m = 1; m < gps && m < 8; m <<= 1)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            mn[i] = min(mn[i], __shfl_xor(mn[i], 8 * m));
+            mx[i] = max(mx[i], __shfl_xor(mx[i], 8 * m));
+          }
+        if (gps > 8) {
+          // 2..8 wavefronts per segment: merge their partials through LDS
+          if ((g & 7) == 0)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) { s_pmin[wv][4 * q + i] = mn[i]; s_pmax[wv][4 * q + i] = mx[i]; }
+          __syncthreads();
+          const int wps = gps / 8;
+          const int s2 = g < nslots ? g : 0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            mn[i] = INT32_MAX;
+            mx[i] = INT32_MIN;
+            for (int w = s2 * wps; w < (s2 + 1) * wps; ++w) {
+              mn[i] = min(mn[i], s_pmin[w][4 * q + i]);
+              mx[i] = max(mx[i], s_pmax[w][4 * q + i]);
+            }
+          }
         }
+        // best dimension of the group's segment: largest spread, lowest on ties
+        int bs = -1, bd = 0, bm = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int k = 4 * q + i;
+          if (k < D) {
+            const int sp = mx[i] - mn[i];
+            if (sp > bs) { bs = sp; bd = k; bm = mn[i]; }
+          }
+        }
+        for (int o = 1; o < 8; o <<= 1) {
+          const int obs = __shfl_xor(bs, o), obd = __shfl_xor(bd, o), obm = __shfl_xor(bm, o);
+          if (obs > bs || (obs == bs && obd < bd)) { bs = obs; bd = obd; bm = obm; }
+        }
+        const bool owner = gps > 8 ? (g < nslots) : (part == 0);
+        const int so = gps > 8 ? g : s;
+        if (owner && q == 0 && s_cnt[so] > leaf) { s_best[so] = bs; s_dim[so] = bd; s_bmin[so] = bm; }
       }
       __syncthreads();
     }
