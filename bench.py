@@ -48,7 +48,7 @@ def cpu_sample(crop_w, crop_h):
     crop of the benchmark pair; returns Mpixel/s of that sample."""
     from oracle import ffo
     from synth import pairs
-    p = pairs.config1_pair(1000)
+    p = pairs.layered_pair(1000)
     i1 = p.img1[:crop_h, :crop_w].copy()
     i2 = p.img2[:crop_h, :crop_w].copy()
     t0 = time.perf_counter()
@@ -65,11 +65,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--crop", default="512x218", help="CPU baseline sample: crop WxH of the pair")
     ap.add_argument("--dominant", default="propagate", choices=sorted(PROF_CLASS))
-    ap.add_argument("--config", type=int, default=1, choices=(1, 3),
-                    help="1: one 1024x436 pair (headline); 3: 64 mixed-size pairs in one batched call")
-    ap.add_argument("--pairs", type=int, default=64, help="config 3: number of pairs")
-    ap.add_argument("--gen-workers", type=int, default=8,
-                    help="config 3: processes drawing the synthetic pairs (0 = in-process; use 0 under a profiler)")
+    ap.add_argument("--mode", default="pair", choices=("pair", "batch"),
+                    help="pair: one 1024x436 pair (headline); batch: 64 mixed-size pairs in one batched call")
+    ap.add_argument("--pairs", type=int, default=64, help="batch mode: number of pairs")
+    ap.add_argument("--gen-workers", type=int, default=16,
+                    help="processes drawing the synthetic pairs (0 = in-process; use 0 under a profiler)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="pair mode: skip the learned-proposal comparison")
+    ap.add_argument("--learned-pairs", type=int, default=16,
+                    help="pair mode: held-out 1024x436 pairs of the learned-proposal comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: each pair is matched on one MI355X; "
@@ -77,14 +81,16 @@ def main():
         sys.exit(2)
 
     from synth import pairs
-    batch_pairs = None
-    if args.config == 3:
-        # drawn before anything touches the GPU (worker processes are started
-        # from a process that has not initialised it)
+    # synthetic pairs are drawn before anything touches the GPU (worker
+    # processes are started from a process that has not initialised it)
+    batch_pairs = eval_pairs = None
+    if args.mode == "batch":
         if args.gen_workers > 0:
-            batch_pairs = pairs.config3_pairs_parallel(args.pairs, workers=args.gen_workers)
+            batch_pairs = pairs.mixed_pairs_parallel(args.pairs, workers=args.gen_workers)
         else:
-            batch_pairs = pairs.config3_pairs(args.pairs)
+            batch_pairs = pairs.mixed_pairs(args.pairs)
+    elif not args.no_learned:
+        eval_pairs = pairs.layered_pairs(LEARNED_SEED0, args.learned_pairs, workers=args.gen_workers)
 
     import numpy as np
     import torch
@@ -92,9 +98,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    if args.config == 3:
+    if args.mode == "batch":
         return bench_batch(args, ff, batch_pairs, torch, dev)
-    pair = pairs.config1_pair(1000)
+    pair = pairs.layered_pair(1000)
     H, W, C = pair.img1.shape
     k, r, r2, Q, eps = 3, 8, 6, 4, 5
     img1 = torch.from_numpy(pair.img1).to(dev)
@@ -158,12 +164,14 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "one 1024x436 RGB pair (config 1 recipe, seed 1000): descriptors x2, "
+        "config": {"workload": "one 1024x436 RGB Sintel-shaped layered pair (seed 1000): descriptors x2, "
                                "F/B1/B2 fields with kd-trees, two-way consistency filter",
                    "k": k, "r": r, "r2": r2, "R": 1, "leaf": 8, "subpel": Q, "eps": eps},
         "roofline": roof,
         "quality": {"F_inlier_rate_epe_lt_3px": round(rate, 4), "kept_fraction": round(keep, 4)},
     }
+    if eval_pairs is not None:
+        line["learned_proposal"] = bench_learned(ff, pair, img1, img2, eval_pairs, torch, dev, value, rate)
     if not args.no_cpu:
         cw, ch = (int(v) for v in args.crop.split("x"))
         mpx, dt = cpu_sample(cw, ch)
@@ -171,6 +179,49 @@ def main():
                                 "sample": f"whole hot path on the top-left {cw}x{ch} crop of the same pair "
                                           f"({cw * ch} px, {dt:.1f} s single-threaded)"}
     print(json.dumps(line), flush=True)
+
+
+LEARNED_SEED0 = 4000
+WEIGHTS = os.path.join(ROOT, "paper_1508_05151_amd", "weights", "proposal_1024x436.safetensors")
+
+
+def bench_learned(ff, pair, img1, img2, eval_pairs, torch, dev, plain_value, plain_rate, steps=5):
+    """The learned proposal against the plain method: on the headline pair
+    (plain + learned candidate; learned only, no kd-tree; the network's
+    forward pass in both directions is inside the timed region) and on a
+    batch of held-out 1024x436 pairs matched in one batched call."""
+    from paper_1508_05151_amd import proposal
+    from synth import pairs
+    net = proposal.load(WEIGHTS)
+    H, W = pair.img1.shape[:2]
+    b1, b2 = img1.unsqueeze(0), img2.unsqueeze(0)
+    res = {"weights": os.path.relpath(WEIGHTS, ROOT),
+           "pair": {"plain": {"Mpixel_per_s": round(plain_value, 3), "inlier_F": round(plain_rate, 4)}}}
+    for mode, use_tree in (("plain+learned", 1), ("learned", 0)):
+        m = ff.PairMatcher(W, H, 3, r=8, r2=6, k=3, subpel=4, eps=5, use_kdtree=use_tree)
+
+        def once():
+            pf, pb = proposal.proposals_both_ways(net, b1, b2)
+            return m.run(img1, img2, seed=1000, proposal=(pf[0], pb[0]))
+
+        once()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = once()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / steps
+        assert m.status() == [0, 0, 0], m.status()
+        res["pair"][mode] = {"Mpixel_per_s": round(W * H / ms / 1e3, 3),
+                             "inlier_F": round(pairs.inlier_rate(out["F"].cpu().numpy(), pair, 4), 4)}
+    ev = proposal.evaluate(net, eval_pairs, reps=3, log=lambda s: None)
+    res["batch"] = {"workload": f"{len(eval_pairs)} held-out 1024x436 layered pairs (seeds {LEARNED_SEED0}.."
+                                f"{LEARNED_SEED0 + len(eval_pairs) - 1}) in one batched call",
+                    **{m: {"Mpixel_per_s": round(ev[m]["mpx_s"], 3), "inlier_F": round(ev[m]["inlier_F"], 4),
+                           "inlier_filtered": round(ev[m]["inlier_filtered"], 4)}
+                       for m in ("plain", "plain+learned", "learned")},
+                    "network_alone_at_seed_points": round(ev["network_only_seed_points"], 4)}
+    return res
 
 
 def bench_batch(args, ff, prs, torch, dev):
@@ -220,14 +271,15 @@ def bench_batch(args, ff, prs, torch, dev):
     same = all(torch.equal(singles[i].flow["F"], m.out[i]["F"][0]) and
                torch.equal(singles[i].keep, m.out[i]["keep"]) for i in range(len(prs)))
     line = {
-        "metric": "config-3 batch: pairs/s and Mpixel/s, batched persistent matching vs one pair per launch",
+        "metric": "batched matching of mixed-size pairs: Mpixel/s and pairs/s, one batched call vs one pair "
+                  "per launch",
         "value": round(total_px / (ms_batch / 1000.0) / 1e6, 3),
         "unit": "Mpixel/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_batch, 3),
         "pairs_per_s": round(len(prs) / (ms_batch / 1000.0), 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": f"{len(prs)} config-3 pairs (sizes from 320x240 to 1242x375, 2-8 layers), "
+        "config": {"workload": f"{len(prs)} layered pairs of mixed sizes (320x240 to 1242x375, 2-8 layers), "
                                f"{total_px} px per batch; whole batch replayed from one HIP graph",
                    "band_rows": best_bh},
         "one_pair_per_launch": {"ms_per_batch": round(ms_single, 3),

@@ -274,6 +274,8 @@ class PairMatcher:
         self.streams = [torch.cuda.Stream(device=device) for _ in range(3)]
 
     def run(self, img1: torch.Tensor, img2: torch.Tensor, seed: int = 0, pair_id: int = 0, proposal=None):
+        """proposal: None, a seed-grid tensor for F, or (forward, backward)
+        where the backward proposal serves B1 and B2."""
         main = torch.cuda.current_stream()
         ff_compute_descriptors(self.desc, img1, self.blob1, main)
         ff_compute_descriptors(self.desc, img2, self.blob2, main)
@@ -286,8 +288,11 @@ class PairMatcher:
             p.pair_id = pair_id
             src, sb, dst, db = ((self.desc, self.blob1, self.desc, self.blob2) if name == "F"
                                 else (self.desc, self.blob2, self.desc, self.blob1))
-            ff_match_field(src, sb, dst, db, rad, p, proposal if name == "F" else None, self.flow[name],
-                           self.cost[name], ws, s)
+            if isinstance(proposal, (tuple, list)):
+                prop = proposal[0] if name == "F" else proposal[1]
+            else:
+                prop = proposal if name == "F" else None
+            ff_match_field(src, sb, dst, db, rad, p, prop, self.flow[name], self.cost[name], ws, s)
         for s in self.streams[:len(self.fields)]:
             e = torch.cuda.Event()
             e.record(s)

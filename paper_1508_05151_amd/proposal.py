@@ -217,7 +217,7 @@ def main(argv=None):
         log(f"saved {a.out}")
     if a.eval_pairs:
         from synth import pairs as P
-        ev = [P.config1_pair(seed=4000 + i) for i in range(a.eval_pairs)]
+        ev = [P.layered_pair(seed=4000 + i) for i in range(a.eval_pairs)]
         res = evaluate(net, ev, log=log)
         log(json.dumps(res))
     return 0

@@ -1,5 +1,5 @@
 """Batched, device-side generator of the Sintel-shaped layered recipe (the
-same recipe as ``pairs.config1_pair``: 1/f background with a small affine
+same recipe as ``pairs.layered_pair``: 1/f background with a small affine
 motion plus star-polygon layers with affine motions, frame-2 gain and
 Gaussian noise), used to produce training pairs for the learned proposal in
 bulk.  Like ``pairs``, it holds none of the matching method's arithmetic.

@@ -23,7 +23,9 @@ Every pair is rendered from layers, back to front:
 
 Recipes (shapes and distributions of the paper's workloads, with synthetic
 content standing in for MPI-Sintel, KITTI and Middlebury, none of which is
-used): see ``make_pair``.
+used): ``square_pair`` (128x96), ``layered_pair`` (Sintel-shaped 1024x436),
+``driving_pair`` (KITTI-shaped 1242x375 gray), ``mixed_pairs`` (mixed sizes)
+and ``layered_pairs`` (batches of layered pairs).
 """
 from __future__ import annotations
 
@@ -34,12 +36,11 @@ import numpy as np
 
 __all__ = [
     "Pair",
-    "make_pair",
-    "config0_pair",
-    "config1_pair",
-    "config2_pair",
-    "config3_pairs",
-    "config4_batch",
+    "square_pair",
+    "layered_pair",
+    "driving_pair",
+    "mixed_pairs",
+    "layered_pairs",
     "inlier_rate",
 ]
 
@@ -226,7 +227,7 @@ def _flatten_blobs(rng, tex, frac, margin, W, H):
 # --------------------------------------------------------------------------
 # recipes
 
-def config0_pair(seed: int = 0) -> Pair:
+def square_pair(seed: int = 0) -> Pair:
     """128x96 RGB: 1/f background moving (+7,-3), a 24x24 square on top
     moving (+18,+11), frame-2 noise sigma = 2."""
     rng = np.random.default_rng(seed)
@@ -241,7 +242,7 @@ def config0_pair(seed: int = 0) -> Pair:
         _Layer(bg, m, lambda xs, ys: np.ones(xs.shape, bool), fb, ib),
         _Layer(sq, m, _rect_inside(x0, y0, 24, 24), fs, is_),
     ]
-    return _render(layers, W, H, C, rng, 2.0, None, seed, "config0")
+    return _render(layers, W, H, C, rng, 2.0, None, seed, "square")
 
 
 def _affine_layers_pair(rng, W, H, C, nlayers, seed, recipe, noise, gain_range,
@@ -270,17 +271,17 @@ def _affine_layers_pair(rng, W, H, C, nlayers, seed, recipe, noise, gain_range,
     return _render(layers, W, H, C, rng, noise, gain, seed, recipe)
 
 
-def config1_pair(seed: int = 1000, W: int = 1024, H: int = 436, nlayers: int = 6) -> Pair:
+def layered_pair(seed: int = 1000, W: int = 1024, H: int = 436, nlayers: int = 6) -> Pair:
     """Sintel-shaped RGB pair: 1/f background (translation U(+-10), rotation
     U(+-2 deg), scale U(0.97, 1.03)) plus `nlayers` star polygons of 5..30 %
     area, each with an affine motion about its centroid (translation
     200 * u * v^2 per axis with u, v ~ U(-1, 1), rotation U(+-5 deg), scale
     U(0.9, 1.1)); frame-2 gain U(0.9, 1.1) and noise sigma = 2."""
     rng = np.random.default_rng(seed)
-    return _affine_layers_pair(rng, W, H, 3, nlayers, seed, "config1", 2.0, (0.9, 1.1))
+    return _affine_layers_pair(rng, W, H, 3, nlayers, seed, "layered", 2.0, (0.9, 1.1))
 
 
-def config2_pair(seed: int = 2000, W: int = 1242, H: int = 375) -> Pair:
+def driving_pair(seed: int = 2000, W: int = 1242, H: int = 375) -> Pair:
     """KITTI-shaped gray pair: radial expansion from a random vanishing point,
     |flow| growing linearly along each ray to 250 px at the border; three
     60..150 px rectangles translating U(+-80); about 5 % flat blobs; noise
@@ -322,56 +323,47 @@ def config2_pair(seed: int = 2000, W: int = 1242, H: int = 375) -> Pair:
         y0 = rng.uniform(0, H - rh)
         f, i = _affine(0, 0, rng.uniform(-80, 80), rng.uniform(-80, 80), 0.0, 1.0)
         layers.append(_Layer(tex, m, _rect_inside(x0, y0, rw, rh), f, i))
-    return _render(layers, W, H, C, rng, 3.0, None, seed, "config2")
+    return _render(layers, W, H, C, rng, 3.0, None, seed, "driving")
 
 
-CONFIG3_SIZES = ((320, 240), (640, 480), (1024, 436), (1242, 375))
+MIXED_SIZES = ((320, 240), (640, 480), (1024, 436), (1242, 375))
 
 
-def config3_pairs(n_pairs: int = 64, seed0: int = 3000, sizes=CONFIG3_SIZES):
+def mixed_pairs(n_pairs: int = 64, seed0: int = 3000, sizes=MIXED_SIZES):
     """Mixed-size batch: sizes uniform over `sizes`, 2..8 affine layers each
-    (config-1 recipe, RGB)."""
+    (layered recipe, RGB)."""
     out = []
     for i in range(n_pairs):
         seed = seed0 + i
         rng = np.random.default_rng(seed)
         W, H = sizes[int(rng.integers(0, len(sizes)))]
         nl = int(rng.integers(2, 9))
-        out.append(_affine_layers_pair(rng, W, H, 3, nl, seed, "config3", 2.0, (0.9, 1.1),
+        out.append(_affine_layers_pair(rng, W, H, 3, nl, seed, "mixed", 2.0, (0.9, 1.1),
                                        max_t=min(200.0, 0.2 * W)))
     return out
 
 
-def _config3_one(args):
+def _mixed_one(args):
     i, seed0, sizes = args
-    return config3_pairs(1, seed0 + i, sizes)[0]
+    return mixed_pairs(1, seed0 + i, sizes)[0]
 
 
-def config3_pairs_parallel(n_pairs: int = 64, seed0: int = 3000, sizes=CONFIG3_SIZES, workers: int = 8):
-    """config3_pairs with the pairs drawn in a process pool (same bytes:
+def mixed_pairs_parallel(n_pairs: int = 64, seed0: int = 3000, sizes=MIXED_SIZES, workers: int = 8):
+    """mixed_pairs with the pairs drawn in a process pool (same bytes:
     pair i only depends on its own seed seed0 + i)."""
     import multiprocessing as mp
     with mp.get_context("spawn").Pool(workers) as pool:
-        return pool.map(_config3_one, [(i, seed0, sizes) for i in range(n_pairs)])
+        return pool.map(_mixed_one, [(i, seed0, sizes) for i in range(n_pairs)])
 
 
-def config4_batch(first_seed: int, batch: int = 16, W: int = 1024, H: int = 436):
-    """A batch of config-1-recipe pairs (seeds first_seed .. first_seed+batch-1)."""
-    return [config1_pair(first_seed + i, W, H) for i in range(batch)]
-
-
-def make_pair(config: int, index: int = 0) -> Pair:
-    """Pair `index` of a configuration, seed = 1000 * config + index."""
-    seed = 1000 * config + index
-    if config == 0:
-        return config0_pair(seed)
-    if config == 1:
-        return config1_pair(seed)
-    if config == 2:
-        return config2_pair(seed)
-    if config == 4:
-        return config1_pair(seed)
-    raise ValueError("config 3 is a batch: use config3_pairs()")
+def layered_pairs(first_seed: int, count: int = 16, W: int = 1024, H: int = 436, workers: int = 0):
+    """`count` layered pairs with seeds first_seed .. first_seed + count - 1
+    (drawn in a process pool when workers > 0; same bytes either way)."""
+    if workers <= 0:
+        return [layered_pair(first_seed + i, W, H) for i in range(count)]
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(workers) as pool:
+        return pool.starmap(layered_pair, [(first_seed + i, W, H) for i in range(count)])
 
 
 def inlier_rate(flow_q: np.ndarray, gt: Pair, Q: int, thresh_px: float = 3.0,

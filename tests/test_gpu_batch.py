@@ -33,7 +33,7 @@ def ff():
 
 @pytest.fixture(scope="module")
 def batch_pairs():
-    return [pairs.config1_pair(seed=3000 + i, W=W, H=H, nlayers=3) for i, (W, H) in enumerate(SIZES)]
+    return [pairs.layered_pair(seed=3000 + i, W=W, H=H, nlayers=3) for i, (W, H) in enumerate(SIZES)]
 
 
 def _dev(a):

@@ -31,7 +31,7 @@ def env():
         pytest.skip("no GPU")
     from paper_1508_05151_amd import ff, proposal
     ff.ff_init()
-    ev = [pairs.config1_pair(seed=4000 + i) for i in range(4)]
+    ev = [pairs.layered_pair(seed=4000 + i) for i in range(4)]
     return ff, proposal, ev
 
 

@@ -64,7 +64,7 @@ def _theta(seed):
 
 
 def _batch(seed, B, W, H):
-    ps = [pairs.config1_pair(seed=seed + i, W=W, H=H, nlayers=3) for i in range(B)]
+    ps = [pairs.layered_pair(seed=seed + i, W=W, H=H, nlayers=3) for i in range(B)]
     return np.stack([p.img1 for p in ps]), np.stack([p.img2 for p in ps]), ps
 
 
@@ -214,7 +214,7 @@ def test_proposal_as_seed_candidate_matches_oracle(ff):
     field as the oracle's match with that proposal (with and without the
     kd-tree candidates)."""
     th = _theta(4)
-    p = pairs.config0_pair(3)
+    p = pairs.square_pair(3)
     H, W = p.img1.shape[:2]
     net = ff.ProposalNet(th, subpel=Q)
     prop = net.forward(_dev(p.img1), _dev(p.img2))[0].contiguous()

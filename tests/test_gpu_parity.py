@@ -45,14 +45,14 @@ def _gpu_desc(ff, img, k=3, radii=(8, 6)):
 
 
 def _ragged_pair(seed, W, H, C=3, nlayers=2):
-    p = pairs.config1_pair(seed=seed, W=W, H=H, nlayers=nlayers)
+    p = pairs.layered_pair(seed=seed, W=W, H=H, nlayers=nlayers)
     if C == 1:
         g = lambda im: np.ascontiguousarray(im[:, :, :1])
         p.img1, p.img2 = g(p.img1), g(p.img2)
     return p
 
 
-CASES = [("config0", lambda: pairs.config0_pair(0), 3, (8, 6)),
+CASES = [("square", lambda: pairs.square_pair(0), 3, (8, 6)),
          ("ragged97x61", lambda: _ragged_pair(5, 97, 61), 3, (8, 6)),
          ("gray75x50", lambda: _ragged_pair(6, 75, 50, C=1), 2, (5,)),
          ("tiny13x9", lambda: _ragged_pair(7, 13, 9), 1, (3,))]
@@ -130,8 +130,8 @@ def _gpu_field(ff, d1, b1, d2, b2, r, **kw):
     return F.cpu().numpy(), Cc.cpu().numpy()
 
 
-def test_field_every_step_config0(ff):
-    p = pairs.config0_pair(0)
+def test_field_every_step_square_pair(ff):
+    p = pairs.square_pair(0)
     k, r = 3, 8
     d1, b1 = _gpu_desc(ff, p.img1, k, (r,))
     d2, b2 = _gpu_desc(ff, p.img2, k, (r,))
@@ -163,7 +163,7 @@ def test_whole_pair_bit_exact(ff, name, make, k, radii):
 
 
 def test_proposal_paths(ff):
-    p = pairs.config0_pair(2)
+    p = pairs.square_pair(2)
     k, r = 3, 8
     d1, b1 = _gpu_desc(ff, p.img1, k, (r,))
     d2, b2 = _gpu_desc(ff, p.img2, k, (r,))

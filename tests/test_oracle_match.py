@@ -72,7 +72,7 @@ def test_exact_shift_cost_zero_at_true_flow():
 
 def test_brute_force_nnf_is_lower_bound():
     """The exact NNF (Table 1's NNF row) bounds every field from below."""
-    pair = pairs.config1_pair(seed=11, W=24, H=18, nlayers=2)
+    pair = pairs.layered_pair(seed=11, W=24, H=18, nlayers=2)
     r, k = 2, 1
     d1, d2 = ffo.Desc(pair.img1, k, Q, (r,)), ffo.Desc(pair.img2, k, Q, (r,))
     F, Cf = ffo.match_field(d1, d2, r, k=k, leaf=4, seed=5)
@@ -100,7 +100,7 @@ def test_known_shift_field_found():
 
 
 def test_steps_monotone_and_stored_cost_exact():
-    pair = pairs.config1_pair(seed=21, W=48, H=36, nlayers=3)
+    pair = pairs.layered_pair(seed=21, W=48, H=36, nlayers=3)
     k, r = 2, 3
     d1, d2 = ffo.Desc(pair.img1, k, Q, (r,)), ffo.Desc(pair.img2, k, Q, (r,))
     total = 1 + 7 + 8 * k
@@ -144,15 +144,15 @@ def test_eleven_comparisons_per_point_per_level():
 
 
 def test_duplicate_skipping_changes_nothing():
-    pair = pairs.config1_pair(seed=31, W=40, H=30, nlayers=2)
+    pair = pairs.layered_pair(seed=31, W=40, H=30, nlayers=2)
     d1, d2 = ffo.Desc(pair.img1, 2, Q, (3,)), ffo.Desc(pair.img2, 2, Q, (3,))
     a = ffo.match_field(d1, d2, 3, k=2, seed=3, skip_dup=True)
     b = ffo.match_field(d1, d2, 3, k=2, seed=3, skip_dup=False)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
-def test_config0_inlier_rate():
-    p = pairs.config0_pair(0)
+def test_square_pair_inlier_rate():
+    p = pairs.square_pair(0)
     d1, d2 = ffo.Desc(p.img1, 3, Q, (8,)), ffo.Desc(p.img2, 3, Q, (8,))
     F, _ = ffo.match_field(d1, d2, 8, k=3, seed=0)
     assert pairs.inlier_rate(F, p, Q) > 0.9
@@ -161,7 +161,7 @@ def test_config0_inlier_rate():
 def test_two_seed_spread():
     """Fig. 5a/b: the hierarchy spreads a field seeded at only two points (all
     other seeds 'infinity') over almost the whole image."""
-    p = pairs.config0_pair(0)
+    p = pairs.square_pair(0)
     k = 3
     d1, d2 = ffo.Desc(p.img1, k, Q, (8,)), ffo.Desc(p.img2, k, Q, (8,))
     Gw, Gh = 128 // 8, 96 // 8
@@ -174,7 +174,7 @@ def test_two_seed_spread():
 
 
 def test_empty_or_invalid_proposal_changes_nothing():
-    p = pairs.config0_pair(1)
+    p = pairs.square_pair(1)
     k = 3
     d1, d2 = ffo.Desc(p.img1, k, Q, (8,)), ffo.Desc(p.img2, k, Q, (8,))
     base = ffo.match_field(d1, d2, 8, k=k, seed=4)
@@ -188,7 +188,7 @@ def test_empty_or_invalid_proposal_changes_nothing():
 
 def test_seed_is_first_minimum_over_leaf():
     """Eq. 1: a seed is the leaf entry of least cost, first one on ties."""
-    p = pairs.config1_pair(seed=41, W=64, H=40, nlayers=2)
+    p = pairs.layered_pair(seed=41, W=64, H=40, nlayers=2)
     k, r, leaf = 2, 3, 8
     d1, d2 = ffo.Desc(p.img1, k, Q, (r,)), ffo.Desc(p.img2, k, Q, (r,))
     F, Cf = ffo.match_field(d1, d2, r, k=k, leaf=leaf, max_steps=1)
