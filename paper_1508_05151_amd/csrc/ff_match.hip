@@ -294,21 +294,37 @@ __device__ __forceinline__ uint64_t xch_pack(int32_t f, int32_t cst, uint32_t ta
 // Term layout.  In sweep-transformed grid coordinates (u right, v down) the
 // sliding-window terms of a point are four groups of S = 2r+1: g0/g1 = row
 // v-r-1 / v+r (vertical candidate leaving / entering), g2/g3 = column u-r-1 /
-// u+r (horizontal candidate), each over offsets -r..r.  Lane l of a point
-// takes offset index l + 16 m of every group for the FULL = S / 16 full
-// slots; the S % 16 remaining offsets of the four groups are packed into TAIL
-// extra slots.
+// u+r (horizontal candidate), each over offsets -r..r.  Slot g of lane l
+// takes offset index l of group g (valid while l < S); for S > 16 the S - 16
+// remaining offsets of the four groups are packed into TAIL extra slots whose
+// group is a per-lane constant.
+//
+// A step is written for a short instruction stream (one wavefront per SIMD,
+// so a step's latency is its instruction count plus one memory round trip):
+// target words are read with 32-bit offsets from one scalar base (row-major
+// and transposed planes of a level lie in one blob), tail groups are chosen
+// with lane-constant masks, and the vertical and horizontal sums travel
+// packed in one 32-bit word through the DPP reduction.
 constexpr int kBatch = 32;
 
-template <int FULL, int TAIL, int BH>
+typedef __attribute__((address_space(1))) const char g_byte;
+
+__device__ __forceinline__ int med3i(int v, int lo, int hi) { return min(max(v, lo), hi); }
+// target word at a 32-bit word offset from a uniform base: the byte offset is
+// formed in 32 bits so the load takes the scalar-base + 32-bit-offset form
+__device__ __forceinline__ uint32_t tword(g_byte* base, uint32_t w) {
+  return *reinterpret_cast<__attribute__((address_space(1))) const uint32_t*>(base + (w << 2));
+}
+
+template <int TAIL, int BH>
 __global__ __launch_bounds__(BH * kLanesProp) void k_propagate(const FieldRec* __restrict__ table, int f0, int nf,
                                                                int lev, int qshift, int sx, int sy, uint32_t tag,
                                                                int32_t* __restrict__ ticket,
                                                                int32_t* __restrict__ status,
                                                                uint64_t timeout_ticks) {
   constexpr int L = kLanesProp, CH = kBatch;
-  constexpr int NS = 4 * FULL + TAIL;   // term slots per lane
-  static_assert(L == 16 && CH % 2 == 0 && CH % L == 0, "layout");
+  constexpr int NS = 4 + TAIL;   // term slots per lane
+  static_assert(L == 16 && CH % 2 == 0 && CH % L == 0 && TAIL <= 4, "layout");
   constexpr int kTileWords = (BH + 2 * kMaxRadius + 1) * ((kBatch + BH + 2 * kMaxRadius) | 1);
   __shared__ int32_t s_band, s_field;
   __shared__ int32_t bufF[2][BH], bufC[2][BH];
@@ -356,41 +372,48 @@ __global__ __launch_bounds__(BH * kLanesProp) void k_propagate(const FieldRec* _
   int32_t* Crow = C + (size_t)gy * Gw;
   auto gx_of = [&](int u) { return sx > 0 ? u : Gw - 1 - u; };
   auto gy_of = [&](int v) { return sy > 0 ? v : Gh - 1 - v; };
-  // slot table: group (0..3), offset index i (0..S-1), validity
-  int sg[NS], si[NS];
-  uint32_t sval = 0;
+  // target words: one scalar base (level plane 0), 32-bit word offsets; the
+  // transposed planes start dT words after the row-major ones
+  g_byte* const tgt = (g_byte*)(c.dst);
+  const uint32_t dT = (uint32_t)(c.dstT - c.dst);
+  const int nsx = sx * n, nsy = sy * n;
+  const int Wm = c.Wd - 1, Hm = c.Hd - 1;
+  const uint32_t Wd = (uint32_t)c.Wd, Hd = (uint32_t)c.Hd;
+  // lane constants: the full slots' offset along the group's free axis and
+  // validity; per tail slot its group (as selection masks), validity, sign
+  // and half of the packed sum; every slot's tile offset
+  const int offFull = lane - r;
+  const uint32_t fullMask = lane < S ? ~0u : 0u;
+  const int oxFull = nsx * offFull, oyFull = nsy * offFull;
+  int tOff[TAIL > 0 ? TAIL : 1], tGrp[TAIL > 0 ? TAIL : 1];
+  uint32_t tM0[TAIL > 0 ? TAIL : 1], tM1[TAIL > 0 ? TAIL : 1], tM2[TAIL > 0 ? TAIL : 1], tM3[TAIL > 0 ? TAIL : 1];
+  uint32_t tVal[TAIL > 0 ? TAIL : 1], tSh[TAIL > 0 ? TAIL : 1];
+  int32_t tNeg[TAIL > 0 ? TAIL : 1];
 #pragma unroll
-  for (int m = 0; m < FULL; ++m)
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      sg[4 * m + g] = g;
-      si[4 * m + g] = lane + 16 * m;
-      sval |= 1u << (4 * m + g);
-    }
-  {
-    const int tl = S - 16 * FULL;   // remaining offsets per group
-#pragma unroll
-    for (int q = 0; q < TAIL; ++q) {
-      const int e = lane + 16 * q;   // packed tail term
-      const int g = tl > 0 ? e / tl : 0;
-      sg[4 * FULL + q] = g < 4 ? g : 0;
-      si[4 * FULL + q] = 16 * FULL + (tl > 0 ? e % tl : 0);
-      if (g < 4) sval |= 1u << (4 * FULL + q);
-    }
+  for (int q = 0; q < TAIL; ++q) {
+    const int tl = S - 16;                   // remaining offsets per group
+    const int e = lane + 16 * q;             // packed tail term
+    const int g0 = e / tl;
+    const bool ok = g0 < 4;
+    const int g = ok ? g0 : 0;
+    tGrp[q] = g;
+    tOff[q] = 16 + (ok ? e % tl : 0) - r;
+    tM0[q] = g == 0 ? ~0u : 0u;
+    tM1[q] = g == 1 ? ~0u : 0u;
+    tM2[q] = g == 2 ? ~0u : 0u;
+    tM3[q] = g == 3 ? ~0u : 0u;
+    tVal[q] = ok ? ~0u : 0u;
+    tNeg[q] = (g & 1) ? 0 : -1;
+    tSh[q] = g >= 2 ? 16u : 0u;
   }
-  // per slot: transformed offsets (du, dv), and the LDS tile offset
-  int sdu[NS], sdv[NS], stoff[NS];
-  uint32_t shor = 0, sneg = 0;
+  int stoff[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    const int g = sg[k], o = si[k] - r;
+    const int g = k < 4 ? k : tGrp[k - 4 < TAIL ? k - 4 : 0];
+    const int o = k < 4 ? offFull : tOff[k - 4 < TAIL ? k - 4 : 0];
     const int du = g < 2 ? o : (g == 2 ? -r - 1 : r);
     const int dv = g < 2 ? (g == 0 ? -r - 1 : r) : o;
-    sdu[k] = du;
-    sdv[k] = dv;
     stoff[k] = (r + 1 + dv) * TW + (BH + r + du);
-    if (g >= 2) shor |= 1u << k;
-    if (g == 0 || g == 2) sneg |= 1u << k;
   }
   int32_t prevF = kEmpty, prevC = kInf;   // this row's result at u-1
   bool abandoned = false;
@@ -409,15 +432,14 @@ __global__ __launch_bounds__(BH * kLanesProp) void k_propagate(const FieldRec* _
     }
     return w;
   };
-  const uint32_t* dplane = c.dst;
-  const uint32_t* dplaneT = c.dstT;
+  const uint32_t maxMx = (uint32_t)(Wm * Q), maxMy = (uint32_t)(Hm * Q);
   // one step; `pw` holds the prefetched handoff word for this step (row 0),
   // `pn` receives the next one
   auto step = [&](int t, int tb, uint64_t pw, uint64_t& pn) {
     const int j = t - tb;
     const int u = t - row;
     const bool active = rowok && u >= 0 && u < Gw;
-    const int px = gx_of(clampi(u, 0, Gw - 1)) * n;
+    const int px = gx_of(med3i(u, 0, Gw - 1)) * n;
     const int32_t curF0 = inF[row][j], curC0 = inC[row][j];
     int32_t vF = bufF[(t - 1) & 1][row > 0 ? row - 1 : 0];
     int32_t vC = bufC[(t - 1) & 1][row > 0 ? row - 1 : 0];
@@ -432,53 +454,53 @@ __global__ __launch_bounds__(BH * kLanesProp) void k_propagate(const FieldRec* _
       }
     }
     const int32_t hF = u > 0 ? prevF : kEmpty, hC = u > 0 ? prevC : kInf;
-    const bool useV = active && vF != kEmpty && vF != curF0 && centre_valid(c, px, py, fx_of(vF), fy_of(vF));
-    const bool useH = active && hF != kEmpty && hF != curF0 && centre_valid(c, px, py, fx_of(hF), fy_of(hF));
-    int32_t dvs = 0, dhs = 0;
-    if (__any(useV || useH)) {
-      // target side: both candidates' centres, phase planes and the fixed
-      // row (vertical) / column (horizontal) of each group
-      const int mxv = px * Q + fx_of(vF), myv = py * Q + fy_of(vF);
-      const int mxh = px * Q + fx_of(hF), myh = py * Q + fy_of(hF);
-      const int Mxv = mxv >> c.qshift, Myv = myv >> c.qshift;
-      const int Mxh = mxh >> c.qshift, Myh = myh >> c.qshift;
-      const uint32_t phv = (uint32_t)c.pw * (uint32_t)(((myv & c.qmask) << c.qshift) + (mxv & c.qmask));
-      const uint32_t phh = (uint32_t)c.pw * (uint32_t)(((myh & c.qmask) << c.qshift) + (mxh & c.qmask));
-      const int nsx = sx * n, nsy = sy * n;
-      const uint32_t rb0 = phv + (uint32_t)clampi(Myv - nsy * (r + 1), 0, c.Hd - 1) * (uint32_t)c.Wd;
-      const uint32_t rb1 = phv + (uint32_t)clampi(Myv + nsy * r, 0, c.Hd - 1) * (uint32_t)c.Wd;
-      const uint32_t cb2 = phh + (uint32_t)clampi(Mxh - nsx * (r + 1), 0, c.Wd - 1) * (uint32_t)c.Hd;
-      const uint32_t cb3 = phh + (uint32_t)clampi(Mxh + nsx * r, 0, c.Wd - 1) * (uint32_t)c.Hd;
-      const int tbase = (row) * TW + (u - tb);   // tile index of (u, v) minus the slot offset base
-      uint32_t a[NS], b[NS];
+    // candidate centres in 1/Q px; EMPTY (-32768, -32768) always falls
+    // outside, so the validity test also rejects empty candidates
+    const int mxv = px * Q + fx_of(vF), myv = py * Q + fy_of(vF);
+    const int mxh = px * Q + fx_of(hF), myh = py * Q + fy_of(hF);
+    const bool useV = active && vF != curF0 && (uint32_t)mxv <= maxMx && (uint32_t)myv <= maxMy;
+    const bool useH = active && hF != curF0 && (uint32_t)mxh <= maxMx && (uint32_t)myh <= maxMy;
+    const int Mxv = mxv >> c.qshift, Myv = myv >> c.qshift;
+    const int Mxh = mxh >> c.qshift, Myh = myh >> c.qshift;
+    const uint32_t phv = c.pw * (uint32_t)(((myv & c.qmask) << c.qshift) + (mxv & c.qmask));
+    const uint32_t phh = dT + c.pw * (uint32_t)(((myh & c.qmask) << c.qshift) + (mxh & c.qmask));
+    const uint32_t base0 = phv + (uint32_t)med3i(Myv - nsy * (r + 1), 0, Hm) * Wd;
+    const uint32_t base1 = phv + (uint32_t)med3i(Myv + nsy * r, 0, Hm) * Wd;
+    const uint32_t base2 = phh + (uint32_t)med3i(Mxh - nsx * (r + 1), 0, Wm) * Hd;
+    const uint32_t base3 = phh + (uint32_t)med3i(Mxh + nsx * r, 0, Wm) * Hd;
+    const uint32_t xv = (uint32_t)med3i(Mxv + oxFull, 0, Wm);
+    const uint32_t yh = (uint32_t)med3i(Myh + oyFull, 0, Hm);
+    uint32_t bw[NS];
+    bw[0] = tword(tgt, base0 + xv);
+    bw[1] = tword(tgt, base1 + xv);
+    bw[2] = tword(tgt, base2 + yh);
+    bw[3] = tword(tgt, base3 + yh);
 #pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        // full slots have a compile-time group (k & 3); tail slots select
-        const int g = k < 4 * FULL ? (k & 3) : sg[k];
-        const uint32_t iv = (g == 0 ? rb0 : rb1) + (uint32_t)clampi(Mxv + nsx * sdu[k], 0, c.Wd - 1);
-        const uint32_t ih = (g == 2 ? cb2 : cb3) + (uint32_t)clampi(Myh + nsy * sdv[k], 0, c.Hd - 1);
-        if (k < 4 * FULL) {
-          b[k] = g < 2 ? ld32(dplane, iv) : ld32(dplaneT, ih);
-        } else {
-          const uint32_t bv = ld32(dplane, iv), bh = ld32(dplaneT, ih);
-          b[k] = ((sval >> k) & 1) ? (g < 2 ? bv : bh) : 0u;
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < NS; ++k) a[k] = tile[tbase + stoff[k]];
-      pn = poll ? __hip_atomic_load(&xin[clampi(u + 1, 0, Gw - 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        const int32_t pc = ((sval >> k) & 1) ? __popc(a[k] ^ b[k]) : 0;
-        const int32_t sgn = ((sneg >> k) & 1) ? -pc : pc;
-        if ((shor >> k) & 1) dhs += sgn;
-        else dvs += sgn;
-      }
-    } else {
-      pn = poll ? __hip_atomic_load(&xin[clampi(u + 1, 0, Gw - 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+    for (int q = 0; q < TAIL; ++q) {
+      const uint32_t xq = (uint32_t)med3i(Mxv + nsx * tOff[q], 0, Wm);
+      const uint32_t yq = (uint32_t)med3i(Myh + nsy * tOff[q], 0, Hm);
+      const uint32_t off = ((base0 + xq) & tM0[q]) | ((base1 + xq) & tM1[q]) | ((base2 + yq) & tM2[q]) |
+                           ((base3 + yq) & tM3[q]);
+      bw[4 + q] = tword(tgt, off);
     }
-    dvs = row16_sum(dvs);
-    dhs = row16_sum(dhs);
+    pn = poll ? __hip_atomic_load(&xin[med3i(u + 1, 0, Gw - 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+    const int tbase = row * TW + (u - tb);
+    uint32_t aw[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) aw[k] = tile[tbase + stoff[k]];
+    // entering minus leaving terms, vertical in the low half, horizontal in
+    // the high half of one word (|sums| < 2^15)
+    int32_t packed = (int32_t)__popc((aw[1] ^ bw[1]) & fullMask) - (int32_t)__popc((aw[0] ^ bw[0]) & fullMask);
+    packed += (int32_t)((uint32_t)((int32_t)__popc((aw[3] ^ bw[3]) & fullMask) -
+                                   (int32_t)__popc((aw[2] ^ bw[2]) & fullMask)) << 16);
+#pragma unroll
+    for (int q = 0; q < TAIL; ++q) {
+      const int32_t pc = (int32_t)__popc((aw[4 + q] ^ bw[4 + q]) & tVal[q]);
+      packed += (int32_t)((uint32_t)((pc ^ tNeg[q]) - tNeg[q]) << tSh[q]);   // leaving groups negated
+    }
+    const int32_t sum = row16_sum(packed);
+    const int32_t dvs = (int32_t)(int16_t)(uint16_t)((uint32_t)sum & 0xFFFFu);
+    const int32_t dhs = (sum - dvs) >> 16;
     // candidate order of Eq. 2: current, vertical, horizontal; strict <
     int32_t curF = curF0, curC = curC0;
     if (useV && vC + dvs < curC) { curF = vF; curC = vC + dvs; }
@@ -564,15 +586,13 @@ static void launch_propagate_bh(int r, int bands, hipStream_t stream, const Fiel
                                 int qshift, int sx, int sy, uint32_t tag, int32_t* ticket, int32_t* status,
                                 uint64_t timeout) {
   const dim3 grid(bands), block(BH * kLanesProp);
-  const int S = 2 * r + 1, full = S / 16, tl = S - 16 * full, tail = (4 * tl + 15) / 16;
-#define FF_PROP(FU, TA)                                                                                        \
-  if (full == FU && tail == TA) {                                                                            \
-    k_propagate<FU, TA, BH><<<grid, block, 0, stream>>>(table, f0, nf, lev, qshift, sx, sy, tag, ticket, status, \
-                                                       timeout);                                            \
-    return;                                                                                                  \
+  const int S = 2 * r + 1, tail = S > 16 ? (4 * (S - 16) + 15) / 16 : 0;
+#define FF_PROP(TA)                                                                                              \
+  if (tail == TA) {                                                                                              \
+    k_propagate<TA, BH><<<grid, block, 0, stream>>>(table, f0, nf, lev, qshift, sx, sy, tag, ticket, status, timeout); \
+    return;                                                                                                      \
   }
-  FF_PROP(0, 1) FF_PROP(0, 2) FF_PROP(0, 3) FF_PROP(0, 4)
-  FF_PROP(1, 1) FF_PROP(1, 2) FF_PROP(1, 3) FF_PROP(1, 4)
+  FF_PROP(0) FF_PROP(1) FF_PROP(2) FF_PROP(3) FF_PROP(4)
 #undef FF_PROP
 }
 
