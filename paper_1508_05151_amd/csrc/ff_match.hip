@@ -317,7 +317,7 @@ __device__ __forceinline__ uint32_t tword(g_byte* base, uint32_t w) {
 }
 
 template <int TAIL, int BH>
-__global__ __launch_bounds__(BH * kLanesProp) void k_propagate(const FieldRec* __restrict__ table, int f0, int nf,
+__global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldRec* __restrict__ table, int f0, int nf,
                                                                int lev, int qshift, int sx, int sy, uint32_t tag,
                                                                int32_t* __restrict__ ticket,
                                                                int32_t* __restrict__ status,
@@ -328,9 +328,14 @@ __global__ __launch_bounds__(BH * kLanesProp) void k_propagate(const FieldRec* _
   constexpr int kTileWords = (BH + 2 * kMaxRadius + 1) * ((kBatch + BH + 2 * kMaxRadius) | 1);
   __shared__ int32_t s_band, s_field;
   __shared__ int32_t bufF[2][BH], bufC[2][BH];
+  __shared__ int32_t topF[2], topC[2];   // row 0's vertical candidate, by step parity
   __shared__ int32_t inF[BH][CH], inC[BH][CH], outF[BH][CH], outC[BH][CH];
   __shared__ uint32_t tile[kTileWords];
-  const int row = threadIdx.x / L, lane = threadIdx.x % L;
+  // the band's rows run on BH / 4 wavefronts; one more wavefront waits for
+  // the band above and hands row 0 its vertical candidate through LDS, one
+  // step ahead, so that no compute wavefront polls global memory
+  const bool pollWave = __builtin_amdgcn_readfirstlane(threadIdx.x) >= BH * L;
+  const int row = pollWave ? 0 : threadIdx.x / L, lane = threadIdx.x % L;
   const int n = 1 << lev;
   if (threadIdx.x == 0) {
     // tickets are handed out in launch order; field-major, band-minor
@@ -360,12 +365,12 @@ __global__ __launch_bounds__(BH * kLanesProp) void k_propagate(const FieldRec* _
   const int r = c.r, S = 2 * r + 1, Q = c.Q;
   const int TH = BH + 2 * r + 1;          // tile rows: v0-r-1 .. v0+BH-1+r
   const int TW = (CH + BH + 2 * r) | 1;   // tile cols: tb-BH-r .. tb+CH-1+r; odd pitch (banks)
-  const bool rowok = row < rows;
+  const bool rowok = !pollWave && row < rows;
   const int rr = rowok ? row : rows - 1;  // inactive rows shadow a valid row
   const int gy = sy > 0 ? v0 + rr : Gh - 1 - (v0 + rr);
   const int py = gy * n;
   const bool publish = rowok && row == rows - 1 && v0 + rows < Gh;
-  const bool poll = rowok && row == 0 && v0 > 0;
+  const bool above = v0 > 0;              // a band above exists
   const uint64_t* xin = xch + (size_t)(band > 0 ? band - 1 : 0) * Gw;
   uint64_t* xout = xch + (size_t)band * Gw;
   int32_t* Frow = F + (size_t)gy * Gw;
@@ -433,26 +438,33 @@ __global__ __launch_bounds__(BH * kLanesProp) void k_propagate(const FieldRec* _
     return w;
   };
   const uint32_t maxMx = (uint32_t)(Wm * Q), maxMy = (uint32_t)(Hm * Q);
-  // one step; `pw` holds the prefetched handoff word for this step (row 0),
-  // `pn` receives the next one
-  auto step = [&](int t, int tb, uint64_t pw, uint64_t& pn) {
+  // the polling wavefront: before the barrier that ends step col - 1, the
+  // band above's result at column col for row 0 (EMPTY without a band
+  // above or past the row's end); `pw` holds the prefetched word for col
+  uint64_t pw = above ? __hip_atomic_load(&xin[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+  auto provide = [&](int col) {
+    int32_t f = kEmpty, cst = kInf;
+    if (above && col < Gw) {
+      const uint64_t w = wait_word(col, pw);
+      f = (int32_t)(uint32_t)w;
+      const uint32_t c16 = (uint32_t)(w >> 32) & 0xFFFFu;
+      cst = c16 == 0xFFFFu ? kInf : (int32_t)c16;
+      pw = __hip_atomic_load(&xin[med3i(col + 1, 0, Gw - 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      topF[col & 1] = f;
+      topC[col & 1] = cst;
+    }
+  };
+  // one step of the compute wavefronts
+  auto step = [&](int t, int tb) {
     const int j = t - tb;
     const int u = t - row;
     const bool active = rowok && u >= 0 && u < Gw;
     const int px = gx_of(med3i(u, 0, Gw - 1)) * n;
     const int32_t curF0 = inF[row][j], curC0 = inC[row][j];
-    int32_t vF = bufF[(t - 1) & 1][row > 0 ? row - 1 : 0];
-    int32_t vC = bufC[(t - 1) & 1][row > 0 ? row - 1 : 0];
-    if (row == 0) {
-      vF = kEmpty;
-      vC = kInf;
-      if (poll && active) {
-        const uint64_t w = wait_word(u, pw);
-        vF = (int32_t)(uint32_t)w;
-        const uint32_t c16 = (uint32_t)(w >> 32) & 0xFFFFu;
-        vC = c16 == 0xFFFFu ? kInf : (int32_t)c16;
-      }
-    }
+    int32_t vF = row > 0 ? bufF[(t - 1) & 1][row - 1] : topF[t & 1];
+    int32_t vC = row > 0 ? bufC[(t - 1) & 1][row - 1] : topC[t & 1];
     const int32_t hF = u > 0 ? prevF : kEmpty, hC = u > 0 ? prevC : kInf;
     // candidate centres in 1/Q px; EMPTY (-32768, -32768) always falls
     // outside, so the validity test also rejects empty candidates
@@ -483,7 +495,6 @@ __global__ __launch_bounds__(BH * kLanesProp) void k_propagate(const FieldRec* _
                            ((base3 + yq) & tM3[q]);
       bw[4 + q] = tword(tgt, off);
     }
-    pn = poll ? __hip_atomic_load(&xin[med3i(u + 1, 0, Gw - 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
     const int tbase = row * TW + (u - tb);
     uint32_t aw[NS];
 #pragma unroll
@@ -516,8 +527,8 @@ __global__ __launch_bounds__(BH * kLanesProp) void k_propagate(const FieldRec* _
         __hip_atomic_store(&xout[u], xch_pack(curF, curC, tag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   };
-  uint64_t w0 = poll ? __hip_atomic_load(&xin[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0, w1 = 0;
   const int TT = TH * TW;
+  constexpr int KPT = (kTileWords + BH * L - 1) / (BH * L);   // tile words per thread
   for (int tb = 0; tb < nsteps; tb += CH) {
     // stage this batch's own flows and costs (row r at step tb + j works on
     // u = tb + j - r) and the source tile: tile(y, x) is the source census
@@ -532,22 +543,30 @@ __global__ __launch_bounds__(BH * kLanesProp) void k_propagate(const FieldRec* _
         inC[row][j] = Crow[gx_of(u)];
       }
     }
-    for (int e = threadIdx.x; e < TT; e += BH * L) {
-      const int y = e / TW, x = e - y * TW;
-      const int gxp = gx_of(tb - BH - r + x) * n, gyp = gy_of(v0 - r - 1 + y) * n;
-      tile[e] = c.src[(size_t)clampi(gyp, 0, c.Hs - 1) * c.Ws + clampi(gxp, 0, c.Ws - 1)];
+    if (!pollWave) {
+      // all of a thread's tile loads are issued before its first LDS write
+      uint32_t tv[KPT];
+#pragma unroll
+      for (int k = 0; k < KPT; ++k) {
+        const int e = min((int)threadIdx.x + k * BH * L, TT - 1);
+        const int y = e / TW, x = e - y * TW;
+        const int gxp = gx_of(tb - BH - r + x) * n, gyp = gy_of(v0 - r - 1 + y) * n;
+        tv[k] = c.src[(size_t)clampi(gyp, 0, c.Hs - 1) * c.Ws + clampi(gxp, 0, c.Ws - 1)];
+      }
+#pragma unroll
+      for (int k = 0; k < KPT; ++k) {
+        const int e = (int)threadIdx.x + k * BH * L;
+        if (e < TT) tile[e] = tv[k];
+      }
+    } else if (tb == 0) {
+      provide(0);
     }
     __syncthreads();
     const int te = min(tb + CH, nsteps);
-    for (int t = tb; t < te; t += 2) {
-      step(t, tb, w0, w1);
+    for (int t = tb; t < te; ++t) {
+      if (pollWave) provide(t + 1);
+      else step(t, tb);
       __syncthreads();
-      if (t + 1 < te) {
-        step(t + 1, tb, w1, w0);
-        __syncthreads();
-      } else {
-        w0 = w1;
-      }
     }
     // write the batch's results back
 #pragma unroll
@@ -585,7 +604,7 @@ template <int BH>
 static void launch_propagate_bh(int r, int bands, hipStream_t stream, const FieldRec* table, int f0, int nf, int lev,
                                 int qshift, int sx, int sy, uint32_t tag, int32_t* ticket, int32_t* status,
                                 uint64_t timeout) {
-  const dim3 grid(bands), block(BH * kLanesProp);
+  const dim3 grid(bands), block(BH * kLanesProp + 64);
   const int S = 2 * r + 1, tail = S > 16 ? (4 * (S - 16) + 15) / 16 : 0;
 #define FF_PROP(TA)                                                                                              \
   if (tail == TA) {                                                                                              \
