@@ -27,6 +27,12 @@ HBM_PEAK_GBS = 8000.0
 CUS, LANES_PER_CU, CLOCK_GHZ = 256, 64, 2.4
 INT_PEAK_TOPS = CUS * LANES_PER_CU * CLOCK_GHZ / 1000.0   # 32-bit integer VALU ops, 39.3 T/s
 
+# HBM bytes per k_propagate launch (average over the 48 sweeps of one pair),
+# from FETCH_SIZE and WRITE_SIZE counter runs scaled by a plain-copy
+# calibration; profiles/hotpath_1024x436_hbm_counters.md holds the runs.
+# Valid for the current k_propagate only.
+PROPAGATE_HBM_BYTES_PER_LAUNCH = 24.34e6
+
 PROF_CLASS = {"descriptors": 1, "tree": 2, "seed": 3, "level_entry": 4, "propagate": 5, "random_search": 6,
               "filter": 7}
 
@@ -154,7 +160,8 @@ def main():
         ops_per_launch = propagate_ops_per_pair(W, H, k, (r, r, r2)) / launches_per_step
         achieved = ops_per_launch / (avg_launch_ms / 1000.0) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(INT_PEAK_TOPS, 2), "unit": "TOP/s",
-                "frac": round(achieved / INT_PEAK_TOPS, 5), "traffic": None,
+                "frac": round(achieved / INT_PEAK_TOPS, 5), "traffic": PROPAGATE_HBM_BYTES_PER_LAUNCH,
+                "traffic_GBps": round(PROPAGATE_HBM_BYTES_PER_LAUNCH / (avg_launch_ms / 1000.0) / 1e9, 2),
                 "kernel": "k_propagate", "avg_launch_ms": round(avg_launch_ms, 4), "launches": nl.value,
                 "ops_per_launch": int(ops_per_launch)}
 
