@@ -69,7 +69,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--crop", default="512x218", help="CPU baseline sample: crop WxH of the pair")
+    ap.add_argument("--crop", default="768x327", help="CPU baseline sample: crop WxH of the pair")
     ap.add_argument("--dominant", default="propagate", choices=sorted(PROF_CLASS))
     ap.add_argument("--mode", default="pair", choices=("pair", "batch"),
                     help="pair: one 1024x436 pair (headline); batch: 64 mixed-size pairs in one batched call")
