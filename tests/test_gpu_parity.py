@@ -193,3 +193,36 @@ def test_repeat_runs_identical(ff):
     o1, o2 = ffo.Desc(p.img1, k, Q, (r,)), ffo.Desc(p.img2, k, Q, (r,))
     oF, oC = ffo.match_field(o1, o2, r, k=k, seed=3)
     assert np.array_equal(base[0], oF) and np.array_equal(base[1], oC)
+
+
+@pytest.mark.parametrize("subpel", [1, 2, 8])
+def test_subpel_variants_bit_exact(ff, subpel):
+    """Whole pair at subpixel quanta other than the default 4: census phase
+    planes, flows in 1/Q px and the filter's eps_q all change with Q."""
+    p = _ragged_pair(40 + subpel, 90, 70, nlayers=3)
+    _say("subpel", subpel)
+    H, W = p.img1.shape[:2]
+    m = ff.PairMatcher(W, H, 3, r=8, r2=6, k=3, subpel=subpel, eps=5)
+    out = m.run(_dev(p.img1), _dev(p.img2), seed=99, pair_id=1)
+    torch.cuda.synchronize()
+    assert m.status() == [0, 0, 0]
+    ref = ffo.match_pair(p.img1, p.img2, r=8, r2=6, k=3, Q=subpel, eps=5, seed=99, pair_id=1)
+    for key in ("F", "CF", "B1", "CB1", "B2", "CB2", "keep", "filtered"):
+        assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
+
+
+@pytest.mark.parametrize("R,n_prop,n_rs,k,leaf", [(2, 4, 3, 3, 8), (1, 2, 1, 3, 8), (3, 6, 6, 2, 4),
+                                                  (1, 4, 0, 3, 16), (1, 1, 1, 0, 8)])
+def test_search_parameter_variants_bit_exact(ff, R, n_prop, n_rs, k, leaf):
+    """Random-search radius multiplier, number of propagation sweeps and
+    random searches per level, hierarchy depth (k = 0: no hierarchy) and
+    kd-tree leaf size: one field against the oracle."""
+    p = _ragged_pair(50 + R + n_prop, 96, 72, nlayers=3)
+    _say("params", R, n_prop, n_rs, k, leaf)
+    r = 8
+    d1, b1 = _gpu_desc(ff, p.img1, k, (r,))
+    d2, b2 = _gpu_desc(ff, p.img2, k, (r,))
+    gF, gC = _gpu_field(ff, d1, b1, d2, b2, r, k=k, R=R, n_prop=n_prop, n_rs=n_rs, leaf=leaf, seed=7)
+    o1, o2 = ffo.Desc(p.img1, k, Q, (r,)), ffo.Desc(p.img2, k, Q, (r,))
+    oF, oC = ffo.match_field(o1, o2, r, k=k, R=R, n_prop=n_prop, n_rs=n_rs, leaf=leaf, seed=7)
+    assert np.array_equal(gF, oF) and np.array_equal(gC, oC)
