@@ -26,7 +26,7 @@ typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kNetLayers = 6;
-constexpr int kWChunk = 4096;   // pixels per backward-weight partial
+constexpr int kWChunks = 512;   // most backward-weight partials per layer
 
 struct NetLayer {
   int cin, cout, stride, dil, relu;
@@ -224,19 +224,22 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t* __restric
 }
 
 // ---------------------------------------------------------------- backward-weight
-// Block = one fixed chunk of kWChunk output pixels; for every tap:
+// Block = one fixed chunk of `chunk` output pixels (a multiple of 64, chosen
+// per layer so that a launch has up to kWChunks blocks); for every tap:
 // part[chunk][tap][co][ci] = sum_p G[p][co] X[p_in(p, tap)][ci] on MFMA
 // (A = G^T from LDS, B = X_tap from LDS), bias partial sum_p G[p][co].
-// Wave w handles taps w, w + 4, w + 8.
+// Wave w handles taps w, w + 4, w + 8.  Staging reads 8 channels (16 bytes)
+// per load and transposes them into channel-major LDS rows.
 __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__ G, int Bn, int Ho, int Wo, int coutp,
                                                     const uint16_t* __restrict__ X, int H, int W, int cinp, int stride,
-                                                    int dil, float* __restrict__ part, float* __restrict__ partb) {
+                                                    int dil, int chunk, float* __restrict__ part,
+                                                    float* __restrict__ partb) {
   __shared__ __align__(16) uint16_t sG[32][64 + 4];      // [co][pixel]
   __shared__ __align__(16) uint16_t sX[9][32][64 + 4];   // [tap][ci][pixel]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m = lane & 15, g = lane >> 4;
   const size_t npx = (size_t)Bn * Ho * Wo;
-  const size_t c0 = (size_t)blockIdx.x * kWChunk;
+  const size_t c0 = (size_t)blockIdx.x * chunk;
   const int MT = (coutp + 15) / 16, NTt = (cinp + 15) / 16;
   f32x4 acc[3][2][2];
 #pragma unroll
@@ -247,30 +250,39 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__
       for (int c2 = 0; c2 < 2; ++c2) acc[a][b2][c2] = f32x4{0.f, 0.f, 0.f, 0.f};
   float bsum = 0.f;   // thread t < coutp: bias partial of channel t
   __shared__ int sPix[64][3];   // b, oy, ox of the 64 staged output pixels
-  for (size_t s0 = c0; s0 < c0 + kWChunk && s0 < npx; s0 += 64) {
+  // channel rows beyond the padded channel counts stay zero
+  for (int e = threadIdx.x; e < 32 * 68; e += 256) (&sG[0][0])[e] = 0;
+  for (int e = threadIdx.x; e < 9 * 32 * 68; e += 256) (&sX[0][0][0])[e] = 0;
+  const int gq = coutp / 8, xq = cinp / 8;   // 16-byte quads per pixel
+  for (size_t s0 = c0; s0 < c0 + chunk && s0 < npx; s0 += 64) {
     if (threadIdx.x < 64) {
       const size_t p = s0 + threadIdx.x;
       sPix[threadIdx.x][0] = p < npx ? (int)(p / ((size_t)Wo * Ho)) : -1;
       sPix[threadIdx.x][1] = (int)((p / Wo) % Ho);
       sPix[threadIdx.x][2] = (int)(p % Wo);
     }
-    // G (all co) and X for all 9 taps (all ci); channel fastest so that the
-    // global reads are contiguous runs of one pixel's channels
-    for (int e = threadIdx.x; e < 64 * 32; e += 256) {
-      const int ch = e & 31, px = e >> 5;
+    for (int e = threadIdx.x; e < 64 * gq; e += 256) {
+      const int q = e % gq, px = e / gq;
       const size_t p = s0 + px;
-      sG[ch][px] = (p < npx && ch < coutp) ? G[p * coutp + ch] : 0;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (p < npx) v = reinterpret_cast<const uint4*>(G + p * coutp)[q];
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int i = 0; i < 8; ++i) sG[8 * q + i][px] = (uint16_t)(w[i >> 1] >> (16 * (i & 1)));
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < 9 * 64 * 32; e += 256) {
-      const int ch = e & 31, px = (e >> 5) & 63, tap = e >> 11;
+    for (int e = threadIdx.x; e < 9 * 64 * xq; e += 256) {
+      const int q = e % xq, px = (e / xq) & 63, tap = e / (64 * xq);
       const int b = sPix[px][0];
-      uint16_t v = 0;
-      if (b >= 0 && ch < cinp) {
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (b >= 0) {
         const int iy = sPix[px][1] * stride - dil + (tap / 3) * dil, ix = sPix[px][2] * stride - dil + (tap % 3) * dil;
-        if (iy >= 0 && iy < H && ix >= 0 && ix < W) v = X[(((size_t)b * H + iy) * W + ix) * cinp + ch];
+        if (iy >= 0 && iy < H && ix >= 0 && ix < W)
+          v = reinterpret_cast<const uint4*>(X + (((size_t)b * H + iy) * W + ix) * cinp)[q];
       }
-      sX[tap][ch][px] = v;
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int i = 0; i < 8; ++i) sX[tap][8 * q + i][px] = (uint16_t)(w[i >> 1] >> (16 * (i & 1)));
     }
     __syncthreads();
     if (threadIdx.x < coutp)
@@ -446,7 +458,8 @@ static NetPlan net_plan(int Bn, int W, int H) {
     P.off_wbt[l] = take((size_t)chunks_of(kNet[l].coutp) * tiles_of(kNet[l].cin) * 256 * 2);
     maxpx = std::max(maxpx, (size_t)Bn * P.H[l + 1] * P.W[l + 1]);
   }
-  P.part_chunks = (maxpx + kWChunk - 1) / kWChunk;
+  (void)maxpx;
+  P.part_chunks = kWChunks;
   P.off_grad = take((size_t)param_total() * 4);
   P.off_part = take(P.part_chunks * 9 * 32 * 32 * 4);
   P.off_partb = take(P.part_chunks * 32 * 4);
@@ -559,9 +572,12 @@ ff_status ff_proposal_train_step(float* params, float* adam_m, float* adam_v, in
     const uint16_t* X = reinterpret_cast<const uint16_t*>(ws + P.off_x[l]);
     const int gch = l + 1 == kNetLayers ? 8 : L.coutp;
     const size_t npx = (size_t)batch * P.H[l + 1] * P.W[l + 1];
-    const int nchunk = (int)((npx + kWChunk - 1) / kWChunk);
+    // fixed chunking for a given size (run-to-run identical sums): chunks of
+    // a multiple of 64 pixels, at most kWChunks of them
+    const size_t chunk = std::max<size_t>(64, ((npx + kWChunks - 1) / kWChunks + 63) / 64 * 64);
+    const int nchunk = (int)((npx + chunk - 1) / chunk);
     k_conv_bwd_w<<<nchunk, 256, 0, stream>>>(G, batch, P.H[l + 1], P.W[l + 1], gch, X, P.H[l], P.W[l], L.cinp, L.stride,
-                                             L.dil, part, partb);
+                                             L.dil, (int)chunk, part, partb);
     k_reduce_w<<<64, 256, 0, stream>>>(part, partb, nchunk, L.cin, L.cout, param_offset(l), grad);
     if (l > 0) {
       const int nchb = chunks_of(gch), ntb = tiles_of(L.cin);
