@@ -309,6 +309,17 @@ constexpr int kBatch = 32;
 
 typedef __attribute__((address_space(1))) const char g_byte;
 
+// Workgroup barrier for LDS handoffs only: waits for this wavefront's LDS
+// operations, not for its outstanding global loads (the next step's
+// horizontal-candidate words stay in flight across it); the workgroup runs on
+// one CU, so completed LDS writes are visible to every wavefront after it.
+__device__ __forceinline__ void lds_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt and expcnt not waited
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 __device__ __forceinline__ int med3i(int v, int lo, int hi) { return min(max(v, lo), hi); }
 // target word at a 32-bit word offset from a uniform base: the byte offset is
 // formed in 32 bits so the load takes the scalar-base + 32-bit-offset form
@@ -420,7 +431,6 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
     const int dv = g < 2 ? (g == 0 ? -r - 1 : r) : o;
     stoff[k] = (r + 1 + dv) * TW + (BH + r + du);
   }
-  int32_t prevF = kEmpty, prevC = kInf;   // this row's result at u-1
   bool abandoned = false;
   auto wait_word = [&](int u, uint64_t w) -> uint64_t {
     if ((uint32_t)(w >> 48) != tag && !abandoned) {
@@ -457,6 +467,28 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
     }
   };
   // one step of the compute wavefronts
+  // The horizontal candidate of the next step is the row's own result, known
+  // before the barrier: its target geometry is prepared and its two full-slot
+  // words are loaded at the end of the step before, so those loads are in
+  // flight across the barrier (which waits for LDS operations only).
+  int32_t hFn = kEmpty, hCn = kInf;
+  int mxh = 0, myh = 0, Mxh = 0, Myh = 0;
+  uint32_t base2 = 0, base3 = 0, hb2 = 0, hb3 = 0;
+  auto prep_h = [&](int un, int32_t f, int32_t cst) {
+    hFn = un > 0 ? f : kEmpty;
+    hCn = un > 0 ? cst : kInf;
+    const int pxn = gx_of(med3i(un, 0, Gw - 1)) * n;
+    mxh = pxn * Q + fx_of(hFn);
+    myh = py * Q + fy_of(hFn);
+    Mxh = mxh >> c.qshift;
+    Myh = myh >> c.qshift;
+    const uint32_t phh = dT + c.pw * (uint32_t)(((myh & c.qmask) << c.qshift) + (mxh & c.qmask));
+    base2 = phh + (uint32_t)med3i(Mxh - nsx * (r + 1), 0, Wm) * Hd;
+    base3 = phh + (uint32_t)med3i(Mxh + nsx * r, 0, Wm) * Hd;
+    const uint32_t yh = (uint32_t)med3i(Myh + oyFull, 0, Hm);
+    hb2 = tword(tgt, base2 + yh);
+    hb3 = tword(tgt, base3 + yh);
+  };
   auto step = [&](int t, int tb) {
     const int j = t - tb;
     const int u = t - row;
@@ -465,28 +497,20 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
     const int32_t curF0 = inF[row][j], curC0 = inC[row][j];
     int32_t vF = row > 0 ? bufF[(t - 1) & 1][row - 1] : topF[t & 1];
     int32_t vC = row > 0 ? bufC[(t - 1) & 1][row - 1] : topC[t & 1];
-    const int32_t hF = u > 0 ? prevF : kEmpty, hC = u > 0 ? prevC : kInf;
+    const int32_t hF = hFn, hC = hCn;
     // candidate centres in 1/Q px; EMPTY (-32768, -32768) always falls
     // outside, so the validity test also rejects empty candidates
     const int mxv = px * Q + fx_of(vF), myv = py * Q + fy_of(vF);
-    const int mxh = px * Q + fx_of(hF), myh = py * Q + fy_of(hF);
     const bool useV = active && vF != curF0 && (uint32_t)mxv <= maxMx && (uint32_t)myv <= maxMy;
     const bool useH = active && hF != curF0 && (uint32_t)mxh <= maxMx && (uint32_t)myh <= maxMy;
     const int Mxv = mxv >> c.qshift, Myv = myv >> c.qshift;
-    const int Mxh = mxh >> c.qshift, Myh = myh >> c.qshift;
     const uint32_t phv = c.pw * (uint32_t)(((myv & c.qmask) << c.qshift) + (mxv & c.qmask));
-    const uint32_t phh = dT + c.pw * (uint32_t)(((myh & c.qmask) << c.qshift) + (mxh & c.qmask));
     const uint32_t base0 = phv + (uint32_t)med3i(Myv - nsy * (r + 1), 0, Hm) * Wd;
     const uint32_t base1 = phv + (uint32_t)med3i(Myv + nsy * r, 0, Hm) * Wd;
-    const uint32_t base2 = phh + (uint32_t)med3i(Mxh - nsx * (r + 1), 0, Wm) * Hd;
-    const uint32_t base3 = phh + (uint32_t)med3i(Mxh + nsx * r, 0, Wm) * Hd;
     const uint32_t xv = (uint32_t)med3i(Mxv + oxFull, 0, Wm);
-    const uint32_t yh = (uint32_t)med3i(Myh + oyFull, 0, Hm);
     uint32_t bw[NS];
     bw[0] = tword(tgt, base0 + xv);
     bw[1] = tword(tgt, base1 + xv);
-    bw[2] = tword(tgt, base2 + yh);
-    bw[3] = tword(tgt, base3 + yh);
 #pragma unroll
     for (int q = 0; q < TAIL; ++q) {
       const uint32_t xq = (uint32_t)med3i(Mxv + nsx * tOff[q], 0, Wm);
@@ -495,6 +519,8 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
                            ((base3 + yq) & tM3[q]);
       bw[4 + q] = tword(tgt, off);
     }
+    bw[2] = hb2;
+    bw[3] = hb3;
     const int tbase = row * TW + (u - tb);
     uint32_t aw[NS];
 #pragma unroll
@@ -516,8 +542,7 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
     int32_t curF = curF0, curC = curC0;
     if (useV && vC + dvs < curC) { curF = vF; curC = vC + dvs; }
     if (useH && hC + dhs < curC) { curF = hF; curC = hC + dhs; }
-    prevF = curF;
-    prevC = curC;
+    prep_h(u + 1, curF, curC);   // the next step's horizontal candidate
     if (lane == 0) {
       bufF[t & 1][row] = curF;
       bufC[t & 1][row] = curC;
@@ -527,6 +552,7 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
         __hip_atomic_store(&xout[u], xch_pack(curF, curC, tag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   };
+  if (!pollWave) prep_h(-row, kEmpty, kInf);
   const int TT = TH * TW;
   constexpr int KPT = (kTileWords + BH * L - 1) / (BH * L);   // tile words per thread
   for (int tb = 0; tb < nsteps; tb += CH) {
@@ -566,7 +592,7 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
     for (int t = tb; t < te; ++t) {
       if (pollWave) provide(t + 1);
       else step(t, tb);
-      __syncthreads();
+      lds_barrier();
     }
     // write the batch's results back
 #pragma unroll
