@@ -235,20 +235,36 @@ __global__ __launch_bounds__(256) void k_level_entry(const FieldRec* __restrict_
 // Section 3.1 / 3.2: one uniform offset per point, per axis an integer in
 // [-nRQ, nRQ] 1/Q px, from Philox keyed by the seed with counter (pixel, level,
 // step, field | pair << 2); replace only on a strictly lower cost.
+// One workgroup = 256 / L consecutive points of one grid row.  Their source
+// patches overlap: the union (S rows x S - 1 + 256 / L columns, grid-aligned
+// samples clamped to the image) is staged in LDS once, so only the target
+// side of each term is read from global memory.
 template <int L>
 __global__ __launch_bounds__(256) void k_random_search(const FieldRec* __restrict__ table, int lev, int qshift, int step,
                                                        int R) {
+  constexpr int PTS = 256 / L;
+  __shared__ uint32_t stile[(2 * kMaxRadius + 1) * (2 * kMaxRadius + PTS)];
   const FieldRec& f = table[blockIdx.y];
   const CostCtx c = ctx_of(f, lev, qshift);
   const int Gw = (f.Ws + c.n - 1) >> lev, Gh = (f.Hs + c.n - 1) >> lev;
-  const int pid = (blockIdx.x * blockDim.x + threadIdx.x) / L;
-  const int lane = threadIdx.x % L;
-  if (pid >= Gw * Gh) return;
+  const int tilesX = (Gw + PTS - 1) / PTS;
+  const int gy = blockIdx.x / tilesX, gx0 = (blockIdx.x % tilesX) * PTS;
+  if (gy >= Gh) return;   // whole workgroup
+  const int S = 2 * c.r + 1, TWs = S - 1 + PTS;
+  for (int e = threadIdx.x; e < S * TWs; e += 256) {
+    const int yy = e / TWs, xx = e - yy * TWs;
+    const int sy = clampi((gy + yy - c.r) * c.n, 0, c.Hs - 1), sx = clampi((gx0 + xx - c.r) * c.n, 0, c.Ws - 1);
+    stile[e] = c.src[(size_t)sy * c.Ws + sx];
+  }
+  __syncthreads();
+  const int i = threadIdx.x / L, lane = threadIdx.x % L;
+  const int gx = gx0 + i;
+  if (gx >= Gw) return;
+  const int pid = gy * Gw + gx;
   int32_t* F = grid_flow(f, lev);
   int32_t* C = grid_cost(f, lev, Gw * Gh);
   const int32_t fl = F[pid];
   if (fl == kEmpty) return;
-  const int gx = pid % Gw, gy = pid / Gw;
   const int px = gx * c.n, py = gy * c.n;
   const int rad = c.n * R * c.Q;
   uint32_t u0, u1;
@@ -258,7 +274,24 @@ __global__ __launch_bounds__(256) void k_random_search(const FieldRec* __restric
   const int oy = (int)((u1 * span) >> 32) - rad;
   const int fx = fx_of(fl) + ox, fy = fy_of(fl) + oy;
   if (!centre_valid(c, px, py, fx, fy)) return;
-  const int32_t e = group_sum<L>(patch_partial(c, px, py, fx, fy, lane, L));
+  // the patch sum, source terms from the tile
+  const int mx = px * c.Q + fx, my = py * c.Q + fy;
+  const int Mx = mx >> c.qshift, My = my >> c.qshift;
+  const uint32_t* D2 = c.dst + (size_t)c.pw * (size_t)(((my & c.qmask) << c.qshift) + (mx & c.qmask));
+  int dy = lane / S, dx = lane - dy * S;
+  const int stepy = L / S, stepx = L - stepy * S;
+  int32_t sum = 0;
+#pragma unroll 4
+  for (int t = lane; t < S * S; t += L) {
+    const uint32_t a = stile[dy * TWs + i + dx];
+    const uint32_t b = D2[(size_t)clampi(My + (dy - c.r) * c.n, 0, c.Hd - 1) * c.Wd +
+                          clampi(Mx + (dx - c.r) * c.n, 0, c.Wd - 1)];
+    sum += __popc(a ^ b);
+    dx += stepx;
+    dy += stepy;
+    if (dx >= S) { dx -= S; ++dy; }
+  }
+  const int32_t e = group_sum<L>(sum);
   if (lane == 0 && e < C[pid]) {
     F[pid] = packf(fx, fy);
     C[pid] = e;
@@ -830,6 +863,11 @@ static ff_status run_batch(const ff_field_job* jobs, int n, const ff_match_param
     if (st != FF_OK) return st;
   }
   auto pts = [&](int lev) { return ((maxW + (1 << lev) - 1) >> lev) * ((maxH + (1 << lev) - 1) >> lev); };
+  // random search: one workgroup per 256 / kLanesPt consecutive points of a grid row
+  auto rs_blocks = [&](int lev) {
+    const int pt = 256 / kLanesPt;
+    return (unsigned)((((maxW + (1 << lev) - 1) >> lev) + pt - 1) / pt * ((maxH + (1 << lev) - 1) >> lev));
+  };
   int steps = 0, cur_lev = k;
   auto stop = [&]() { return p->max_steps >= 0 && steps >= p->max_steps; };
   auto finish = [&]() -> ff_status {
@@ -877,7 +915,7 @@ static ff_status run_batch(const ff_field_job* jobs, int n, const ff_match_param
       if (stop()) return finish();
       if (i < p->n_rs) {
         prof_mark(FF_PROF_RANDOM_SEARCH, stream, true);
-        k_random_search<kLanesPt><<<dim3(gpts, n), 256, 0, stream>>>(table, lev, qshift, i, p->R);
+        k_random_search<kLanesPt><<<dim3(rs_blocks(lev), n), 256, 0, stream>>>(table, lev, qshift, i, p->R);
         prof_mark(FF_PROF_RANDOM_SEARCH, stream, false);
         ++steps;
         if (stop()) return finish();
