@@ -40,6 +40,9 @@ def test_struct_layouts_match_header(ff):
     assert C.sizeof(ff.ff_desc) == 12 * 4 + 7 * 8
     assert C.sizeof(ff.ff_match_params) == 10 * 4 + 8
     assert ff.ff_match_params.seed.offset == 40
+    # ff_field_job: 4 pointers, 4 x 4-byte fields, uint64 seed, 3 pointers
+    assert C.sizeof(ff.ff_field_job) == 4 * 8 + 4 * 4 + 8 + 3 * 8
+    assert ff.ff_field_job.seed.offset == 48 and ff.ff_field_job.cost.offset == 72
 
 
 def test_desc_init_validation(ff):
@@ -85,3 +88,23 @@ def test_network_entry_points_validate(ff):
     assert L.ff_proposal_forward(None, None, None, 1, 64, 64, 4, None, None, None, 0, None) == -1
     assert L.ff_proposal_train_step(None, None, None, 1, 1e-3, None, None, None, 1, 64, 64, 4, None, None, None, 0,
                                     None) == -1
+
+
+def test_batch_entry_points_validate(ff):
+    L = ff.lib()
+    p = ff.ff_default_params()
+    assert L.ff_match_batch_workspace_bytes(None, 1, C.byref(p)) == 0
+    assert L.ff_match_batch(None, 1, C.byref(p), None, 0, None) == -1
+    d = ff.ff_desc_init(64, 48, 3, 3, 4, (8,))
+    jobs = (ff.ff_field_job * 1)()
+    jobs[0].src = C.pointer(d)
+    jobs[0].dst = C.pointer(d)
+    jobs[0].radius = 8
+    # sizing needs only descriptors and radius; a radius without WHT vectors
+    # is refused; launching with null blobs, outputs or workspace is refused
+    assert L.ff_match_batch_workspace_bytes(jobs, 1, C.byref(p)) > 0
+    jobs[0].radius = 6
+    assert L.ff_match_batch_workspace_bytes(jobs, 1, C.byref(p)) == 0
+    jobs[0].radius = 8
+    assert L.ff_match_batch(jobs, 1, C.byref(p), None, 0, None) == -1
+    assert L.ff_match_batch(jobs, 0, C.byref(p), None, 0, None) == -1
