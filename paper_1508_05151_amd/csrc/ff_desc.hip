@@ -200,37 +200,67 @@ __global__ void k_lanczos_v(const int32_t* __restrict__ T, int W, int H, int n, 
 // the 2x2 neighbourhoods of the centre and of the 8 neighbours at stride n
 // are loaded once per channel; each phase mixes them with exact integer
 // bilinear weights.
+// One workgroup = a 64 x 4 tile of output pixels.  The smoothed input it
+// reads (the tile grown by n + 1, clamped to the image) is staged in LDS per
+// channel; the bilinear phase shift is done separably (horizontal phase a,
+// then vertical phase b), which gives the same integers as the 4-tap form.
+constexpr int kCensusTW = 64, kCensusTH = 4;
+
 template <int Q>
-__global__ void k_census(const int16_t* __restrict__ S, int W, int H, int C, int n, uint32_t* __restrict__ out,
-                         size_t plane_words) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y;
-  if (x >= W) return;
+__global__ __launch_bounds__(256) void k_census(const int16_t* __restrict__ S, int W, int H, int C, int n,
+                                                uint32_t* __restrict__ out, size_t plane_words) {
+  constexpr int kMaxN = 16;   // largest level stride (k <= 4)
+  constexpr int LWmax = kCensusTW + 2 * kMaxN + 2, LHmax = kCensusTH + 2 * kMaxN + 2;
+  __shared__ int16_t tileS[LHmax * LWmax];
+  const int x0 = blockIdx.x * kCensusTW, y0 = blockIdx.y * kCensusTH;
+  const int tx = threadIdx.x % kCensusTW, ty = threadIdx.x / kCensusTW;
+  const int x = x0 + tx, y = y0 + ty;
+  // staged image window (already clamped coordinates)
+  const int sx0 = max(x0 - n, 0), sx1 = min(x0 + kCensusTW + n, W - 1);
+  const int sy0 = max(y0 - n, 0), sy1 = min(y0 + kCensusTH + n, H - 1);
+  const int LW = sx1 - sx0 + 1, LH = sy1 - sy0 + 1;
+  const int xc = min(x, W - 1), yc = min(y, H - 1);   // lanes past the edge compute a valid pixel, store nothing
   uint32_t word[Q * Q];
 #pragma unroll
   for (int i = 0; i < Q * Q; ++i) word[i] = 0;
   const size_t N = (size_t)W * H;
+  // LDS offsets of the 9 taps' top-left samples and their right/down steps
+  int o00[9], dxs[9], dys[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int dx = t % 3 - 1, dy = t / 3 - 1;
+    const int X = clampi(xc + n * dx, 0, W - 1), Y = clampi(yc + n * dy, 0, H - 1);
+    o00[t] = (Y - sy0) * LW + (X - sx0);
+    dxs[t] = X + 1 <= W - 1 ? 1 : 0;
+    dys[t] = Y + 1 <= H - 1 ? LW : 0;
+  }
   for (int c = 0; c < C; ++c) {
     const int16_t* P = S + c * N;
-    int32_t s00[9], s01[9], s10[9], s11[9];
+    __syncthreads();
+    for (int e = threadIdx.x; e < LW * LH; e += 256) {
+      const int yy = e / LW, xx = e - yy * LW;
+      tileS[e] = P[(size_t)(sy0 + yy) * W + sx0 + xx];
+    }
+    __syncthreads();
+    // horizontal phase first: h0[t][a] (row Y), h1[t][a] (row Y + 1)
+    int32_t h0[9][Q], h1[9][Q];
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-      const int dx = t % 3 - 1, dy = t / 3 - 1;
-      const int X = clampi(x + n * dx, 0, W - 1), Y = clampi(y + n * dy, 0, H - 1);
-      const int X1 = min(X + 1, W - 1), Y1 = min(Y + 1, H - 1);
-      s00[t] = P[(size_t)Y * W + X];
-      s01[t] = P[(size_t)Y * W + X1];
-      s10[t] = P[(size_t)Y1 * W + X];
-      s11[t] = P[(size_t)Y1 * W + X1];
+      const int32_t s00 = tileS[o00[t]], s01 = tileS[o00[t] + dxs[t]];
+      const int32_t s10 = tileS[o00[t] + dys[t]], s11 = tileS[o00[t] + dys[t] + dxs[t]];
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        h0[t][a] = (Q - a) * s00 + a * s01;
+        h1[t][a] = (Q - a) * s10 + a * s11;
+      }
     }
 #pragma unroll
     for (int b = 0; b < Q; ++b)
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
-        const int w00 = (Q - a) * (Q - b), w01 = a * (Q - b), w10 = (Q - a) * b, w11 = a * b;
         int32_t B[9];
 #pragma unroll
-        for (int t = 0; t < 9; ++t) B[t] = w00 * s00[t] + w01 * s01[t] + w10 * s10[t] + w11 * s11[t];
+        for (int t = 0; t < 9; ++t) B[t] = (Q - b) * h0[t][a] + b * h1[t][a];
         // neighbours in raster order, skipping the centre (t = 4); bit i
         // set when the neighbour is darker than the centre
         uint32_t bits = 0;
@@ -244,6 +274,7 @@ __global__ void k_census(const int16_t* __restrict__ S, int W, int H, int C, int
         word[b * Q + a] |= bits << (8 * c);
       }
   }
+  if (x >= W || y >= H) return;
   const size_t o = (size_t)y * W + x;
 #pragma unroll
   for (int i = 0; i < Q * Q; ++i) out[i * plane_words + o] = word[i];
@@ -424,11 +455,12 @@ ff_status ff_compute_descriptors(const ff_desc* d, const ff_image* img, const ui
     uint32_t* out = reinterpret_cast<uint32_t*>(base + d->off_census) + (size_t)lev * d->subpel * d->subpel * pw;
     const int16_t* S = smooth + (size_t)lev * C * N;
     const int n = 1 << lev;
+    const dim3 cg((W + kCensusTW - 1) / kCensusTW, (H + kCensusTH - 1) / kCensusTH);
     switch (d->subpel) {
-      case 1: k_census<1><<<dim3(gx, H), tb, 0, stream>>>(S, W, H, C, n, out, pw); break;
-      case 2: k_census<2><<<dim3(gx, H), tb, 0, stream>>>(S, W, H, C, n, out, pw); break;
-      case 4: k_census<4><<<dim3(gx, H), tb, 0, stream>>>(S, W, H, C, n, out, pw); break;
-      default: k_census<8><<<dim3(gx, H), tb, 0, stream>>>(S, W, H, C, n, out, pw); break;
+      case 1: k_census<1><<<cg, tb, 0, stream>>>(S, W, H, C, n, out, pw); break;
+      case 2: k_census<2><<<cg, tb, 0, stream>>>(S, W, H, C, n, out, pw); break;
+      case 4: k_census<4><<<cg, tb, 0, stream>>>(S, W, H, C, n, out, pw); break;
+      default: k_census<8><<<cg, tb, 0, stream>>>(S, W, H, C, n, out, pw); break;
     }
   }
   {
