@@ -55,7 +55,8 @@ def _ragged_pair(seed, W, H, C=3, nlayers=2):
 CASES = [("square", lambda: pairs.square_pair(0), 3, (8, 6)),
          ("ragged97x61", lambda: _ragged_pair(5, 97, 61), 3, (8, 6)),
          ("gray75x50", lambda: _ragged_pair(6, 75, 50, C=1), 2, (5,)),
-         ("tiny13x9", lambda: _ragged_pair(7, 13, 9), 1, (3,))]
+         ("tiny13x9", lambda: _ragged_pair(7, 13, 9), 1, (3,)),
+         ("k4_200x120", lambda: _ragged_pair(8, 200, 120, nlayers=3), 4, (8, 6))]
 
 
 @pytest.mark.parametrize("name,make,k,radii", CASES, ids=[c[0] for c in CASES])
