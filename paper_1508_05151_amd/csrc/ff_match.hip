@@ -128,6 +128,43 @@ __device__ __forceinline__ int32_t group_sum(int32_t v) {
   return v;
 }
 
+// Patch sum at level stride 1 with whole rows per lane (16 lanes per point):
+// lane l < min(S, 16) sums patch row l, S consecutive words on each side,
+// read with 16-byte loads where the alignment allows; rows 16..S-1 spread
+// their words over the lanes.  Each side is given as the address of the
+// patch's column 0 in plane row 0 (sb, tb), its row pitch in words and the
+// plane row of patch row 0 (sy0, ty0); rows clamp to [0, ymax], columns are
+// not clamped, so the caller guarantees that both S-word row segments lie
+// inside their planes.
+typedef __attribute__((address_space(1))) const uint32_t g_u32;
+typedef uint32_t v4u_t __attribute__((ext_vector_type(4)));
+typedef v4u_t v4u_a4 __attribute__((aligned(4)));   // four words at a word-aligned address
+
+template <int S, typename SP>
+__device__ __forceinline__ int32_t rows_sum_n1(SP sb, int spw, int sy0, int symax, g_u32* tb, int tpw, int ty0,
+                                               int tymax, int lane) {
+  int32_t sum = 0;
+  if (lane < S) {
+    const SP a = sb + (size_t)clampi(sy0 + lane, 0, symax) * spw;
+    g_u32* t = tb + (size_t)clampi(ty0 + lane, 0, tymax) * tpw;
+#pragma unroll
+    for (int q = 0; q + 4 <= S; q += 4) {
+      const v4u_a4 u = *(const v4u_a4*)(a + q);
+      const v4u_a4 v = *(__attribute__((address_space(1))) const v4u_a4*)(t + q);
+      sum += __popc(u.x ^ v.x) + __popc(u.y ^ v.y) + __popc(u.z ^ v.z) + __popc(u.w ^ v.w);
+    }
+#pragma unroll
+    for (int q = S & ~3; q < S; ++q) sum += __popc(a[q] ^ t[q]);
+  }
+#pragma unroll
+  for (int row = 16; row < S; ++row) {
+    const SP a = sb + (size_t)clampi(sy0 + row, 0, symax) * spw;
+    g_u32* t = tb + (size_t)clampi(ty0 + row, 0, tymax) * tpw;
+    for (int w = lane; w < S; w += 16) sum += __popc(a[w] ^ t[w]);
+  }
+  return sum;
+}
+
 // sum over a 16-lane DPP row, left in every lane of the row: swap adjacent
 // lanes, swap lane pairs, mirror within half-rows (quad 0 <-> quad 1), mirror
 // within the row (half 0 <-> half 1)
@@ -207,28 +244,50 @@ __global__ __launch_bounds__(256) void k_seed(const FieldRec* __restrict__ table
 
 // ---------------------------------------------------------------- level entry
 // Section 3.2: points of the coarser grid keep their flow and are re-costed
-// with this level's patch; new points start empty.  grid: (pts L / 256, fields)
+// with this level's patch; new points start empty.  One group of L lanes per
+// coarse point (the fine points of even coordinates), which also writes the
+// three new points it covers.  grid: (coarse pts L / 256, fields)
 template <int L>
 __global__ __launch_bounds__(256) void k_level_entry(const FieldRec* __restrict__ table, int lev, int qshift) {
+  static_assert(L == 16, "the row path assumes 16 lanes per point");
   const FieldRec& f = table[blockIdx.y];
   const CostCtx c = ctx_of(f, lev, qshift);
   const int Gw = (f.Ws + c.n - 1) >> lev, Gh = (f.Hs + c.n - 1) >> lev;
-  const int pid = (blockIdx.x * blockDim.x + threadIdx.x) / L;
-  const int lane = threadIdx.x % L;
-  if (pid >= Gw * Gh) return;
   const int Gwc = (f.Ws + 2 * c.n - 1) >> (lev + 1), Ghc = (f.Hs + 2 * c.n - 1) >> (lev + 1);
-  const int32_t* Fc = grid_flow(f, lev + 1);
-  const int gx = pid % Gw, gy = pid / Gw;
-  int32_t fl = kEmpty, e = kInf;
-  if (!(gx & 1) && !(gy & 1)) {
-    fl = Fc[(size_t)(gy >> 1) * Gwc + (gx >> 1)];
-    if (fl != kEmpty) e = group_sum<L>(patch_partial(c, gx * c.n, gy * c.n, fx_of(fl), fy_of(fl), lane, L));
+  const int cid = (blockIdx.x * blockDim.x + threadIdx.x) / L;
+  const int lane = threadIdx.x % L;
+  if (cid >= Gwc * Ghc) return;
+  const int cx = cid % Gwc, cy = cid / Gwc;
+  const int gx = 2 * cx, gy = 2 * cy;
+  const int32_t fl = grid_flow(f, lev + 1)[cid];
+  int32_t e = kInf;
+  if (fl != kEmpty) {
+    const int px = gx * c.n, py = gy * c.n, fx = fx_of(fl), fy = fy_of(fl);
+    const int mx = px * c.Q + fx, my = py * c.Q + fy;
+    const int Mx = mx >> c.qshift, My = my >> c.qshift;
+    int32_t part;
+    if (lev == 0 && (c.r == 8 || c.r == 6) && px >= c.r && px + c.r < c.Ws && Mx >= c.r && Mx + c.r < c.Wd) {
+      // stride 1, no column clamp on either side: whole rows per lane
+      const uint32_t* D2 = c.dst + (size_t)c.pw * (size_t)(((my & c.qmask) << c.qshift) + (mx & c.qmask));
+      g_u32* sb = (g_u32*)(c.src + (px - c.r));
+      g_u32* tb = (g_u32*)(D2 + (Mx - c.r));
+      part = c.r == 8 ? rows_sum_n1<17>(sb, c.Ws, py - 8, c.Hs - 1, tb, c.Wd, My - 8, c.Hd - 1, lane)
+                      : rows_sum_n1<13>(sb, c.Ws, py - 6, c.Hs - 1, tb, c.Wd, My - 6, c.Hd - 1, lane);
+    } else {
+      part = patch_partial(c, px, py, fx, fy, lane, L);
+    }
+    e = group_sum<L>(part);
+  }
+  int32_t* F = grid_flow(f, lev);
+  int32_t* C = grid_cost(f, lev, Gw * Gh);
+  if (lane < 4) {
+    const int x = gx + (lane & 1), y = gy + (lane >> 1);
+    if (x < Gw && y < Gh) {
+      F[(size_t)y * Gw + x] = lane == 0 ? fl : kEmpty;
+      C[(size_t)y * Gw + x] = lane == 0 ? e : kInf;
+    }
   }
   (void)Ghc;
-  if (lane == 0) {
-    grid_flow(f, lev)[pid] = fl;
-    grid_cost(f, lev, Gw * Gh)[pid] = e;
-  }
 }
 
 // ---------------------------------------------------------------- random search
@@ -243,18 +302,20 @@ template <int L>
 __global__ __launch_bounds__(256) void k_random_search(const FieldRec* __restrict__ table, int lev, int qshift, int step,
                                                        int R) {
   constexpr int PTS = 256 / L;
-  __shared__ uint32_t stile[(2 * kMaxRadius + 1) * (2 * kMaxRadius + PTS)];
+  __shared__ uint32_t stile[(2 * kMaxRadius + 1) * (2 * kMaxRadius + PTS + 1)];
   const FieldRec& f = table[blockIdx.y];
   const CostCtx c = ctx_of(f, lev, qshift);
   const int Gw = (f.Ws + c.n - 1) >> lev, Gh = (f.Hs + c.n - 1) >> lev;
   const int tilesX = (Gw + PTS - 1) / PTS;
   const int gy = blockIdx.x / tilesX, gx0 = (blockIdx.x % tilesX) * PTS;
   if (gy >= Gh) return;   // whole workgroup
-  const int S = 2 * c.r + 1, TWs = S - 1 + PTS;
+  // tile rows: S patch rows; pitch odd, so that the row-per-lane path's 16
+  // lanes of a point fall in different banks
+  const int S = 2 * c.r + 1, TWs = S - 1 + PTS, TP = TWs | 1;
   for (int e = threadIdx.x; e < S * TWs; e += 256) {
     const int yy = e / TWs, xx = e - yy * TWs;
     const int sy = clampi((gy + yy - c.r) * c.n, 0, c.Hs - 1), sx = clampi((gx0 + xx - c.r) * c.n, 0, c.Ws - 1);
-    stile[e] = c.src[(size_t)sy * c.Ws + sx];
+    stile[yy * TP + xx] = c.src[(size_t)sy * c.Ws + sx];
   }
   __syncthreads();
   const int i = threadIdx.x / L, lane = threadIdx.x % L;
@@ -278,18 +339,27 @@ __global__ __launch_bounds__(256) void k_random_search(const FieldRec* __restric
   const int mx = px * c.Q + fx, my = py * c.Q + fy;
   const int Mx = mx >> c.qshift, My = my >> c.qshift;
   const uint32_t* D2 = c.dst + (size_t)c.pw * (size_t)(((my & c.qmask) << c.qshift) + (mx & c.qmask));
-  int dy = lane / S, dx = lane - dy * S;
-  const int stepy = L / S, stepx = L - stepy * S;
   int32_t sum = 0;
+  if (L == 16 && lev == 0 && (c.r == 8 || c.r == 6) && Mx >= c.r && Mx + c.r < c.Wd) {
+    // stride 1 and no column clamp on the target side: whole rows per lane
+    // (the tile's rows are already clamped)
+    g_u32* tb = (g_u32*)(D2 + (Mx - c.r));
+    const uint32_t* sb = stile + i;
+    sum = c.r == 8 ? rows_sum_n1<17>(sb, TP, 0, S - 1, tb, c.Wd, My - 8, c.Hd - 1, lane)
+                   : rows_sum_n1<13>(sb, TP, 0, S - 1, tb, c.Wd, My - 6, c.Hd - 1, lane);
+  } else {
+    int dy = lane / S, dx = lane - dy * S;
+    const int stepy = L / S, stepx = L - stepy * S;
 #pragma unroll 4
-  for (int t = lane; t < S * S; t += L) {
-    const uint32_t a = stile[dy * TWs + i + dx];
-    const uint32_t b = D2[(size_t)clampi(My + (dy - c.r) * c.n, 0, c.Hd - 1) * c.Wd +
-                          clampi(Mx + (dx - c.r) * c.n, 0, c.Wd - 1)];
-    sum += __popc(a ^ b);
-    dx += stepx;
-    dy += stepy;
-    if (dx >= S) { dx -= S; ++dy; }
+    for (int t = lane; t < S * S; t += L) {
+      const uint32_t a = stile[dy * TP + i + dx];
+      const uint32_t b = D2[(size_t)clampi(My + (dy - c.r) * c.n, 0, c.Hd - 1) * c.Wd +
+                            clampi(Mx + (dx - c.r) * c.n, 0, c.Wd - 1)];
+      sum += __popc(a ^ b);
+      dx += stepx;
+      dy += stepy;
+      if (dx >= S) { dx -= S; ++dy; }
+    }
   }
   const int32_t e = group_sum<L>(sum);
   if (lane == 0 && e < C[pid]) {
@@ -884,8 +954,9 @@ static ff_status run_batch(const ff_field_job* jobs, int n, const ff_match_param
   int launch = 0;
   for (int lev = k; lev >= 0; --lev) {
     cur_lev = lev;
-    const unsigned gpts = (unsigned)((pts(lev) * kLanesPt + 255) / 256);
     if (lev < k) {
+      // one group of lanes per point of the coarser grid
+      const unsigned gpts = (unsigned)(((size_t)pts(lev + 1) * kLanesPt + 255) / 256);
       prof_mark(FF_PROF_LEVEL_ENTRY, stream, true);
       k_level_entry<kLanesPt><<<dim3(gpts, n), 256, 0, stream>>>(table, lev, qshift);
       prof_mark(FF_PROF_LEVEL_ENTRY, stream, false);

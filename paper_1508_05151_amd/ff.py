@@ -271,14 +271,24 @@ class PairMatcher:
             self.cost[name] = torch.empty((height, width), dtype=torch.int32, device=device)
         self.keep = torch.empty((height, width), dtype=torch.uint8, device=device)
         self.filtered = torch.empty((height, width), dtype=torch.int32, device=device)
+        # four streams in all (the caller's and three field streams): HIP gives
+        # a process four hardware queues by default, and a fifth stream would
+        # share one with a field and serialise behind it
         self.streams = [torch.cuda.Stream(device=device) for _ in range(3)]
 
     def run(self, img1: torch.Tensor, img2: torch.Tensor, seed: int = 0, pair_id: int = 0, proposal=None):
         """proposal: None, a seed-grid tensor for F, or (forward, backward)
         where the backward proposal serves B1 and B2."""
         main = torch.cuda.current_stream()
+        # the two images' descriptors run concurrently (each is a chain of
+        # small kernels that leaves most of the chip idle); the second image's
+        # go to the last field stream, which waits for both anyway
+        ds = self.streams[len(self.fields) - 1]
+        ds.wait_stream(main)
+        ff_compute_descriptors(self.desc, img2, self.blob2, ds)
+        img2.record_stream(ds)
         ff_compute_descriptors(self.desc, img1, self.blob1, main)
-        ff_compute_descriptors(self.desc, img2, self.blob2, main)
+        main.wait_stream(ds)
         ev = torch.cuda.Event()
         ev.record(main)
         for (name, rad, fid), ws, s in zip(self.fields, self.ws, self.streams):
