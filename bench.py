@@ -27,11 +27,12 @@ HBM_PEAK_GBS = 8000.0
 CUS, LANES_PER_CU, CLOCK_GHZ = 256, 64, 2.4
 INT_PEAK_TOPS = CUS * LANES_PER_CU * CLOCK_GHZ / 1000.0   # 32-bit integer VALU ops, 39.3 T/s
 
-# HBM bytes per k_propagate launch (average over the 48 sweeps of one pair),
+# HBM bytes per k_propagate launch (average over the 36 launches of one pair:
+# single sweeps and pipelined sweep pairs),
 # from FETCH_SIZE and WRITE_SIZE counter runs scaled by a plain-copy
 # calibration; profiles/hotpath_1024x436_hbm_counters.md holds the runs.
 # Valid for the current k_propagate only.
-PROPAGATE_HBM_BYTES_PER_LAUNCH = 24.42e6
+PROPAGATE_HBM_BYTES_PER_LAUNCH = 47.26e6
 
 PROF_CLASS = {"descriptors": 1, "tree": 2, "seed": 3, "level_entry": 4, "propagate": 5, "random_search": 6,
               "filter": 7}
@@ -47,6 +48,23 @@ def propagate_ops_per_pair(W, H, k, radii, n_prop=4):
     census terms of one XOR and one popcount-accumulate (2 ops)."""
     pts = sum(grid_points(W, H, k))
     return sum(n_prop * pts * 2 * 2 * (2 * r + 1) * 2 for r in radii)
+
+
+def search_ops_in_sweep_launches(W, H, k, radii, n_prop=4, n_rs=3):
+    """Algorithmic integer ops of the random searches that run inside
+    pipelined sweep-pair launches (sweeps i, i + 1 with the same horizontal
+    direction: with four sweeps per level, the search after sweep 2): per
+    grid point (2r+1)^2 census terms of 2 ops."""
+    sx = lambda i: 1 if (i & 3) in (0, 3) else -1
+    inside, i = 0, 0
+    while i < n_prop:
+        if i + 1 < n_prop and sx(i + 1) == sx(i):
+            inside += 1 if i < n_rs else 0
+            i += 2
+        else:
+            i += 1
+    pts = sum(grid_points(W, H, k))
+    return sum(inside * pts * (2 * r + 1) ** 2 * 2 for r in radii)
 
 
 def cpu_sample(crop_w, crop_h):
@@ -157,7 +175,9 @@ def main():
     avg_launch_ms = tot.value / max(nl.value, 1)
     roof = None
     if args.dominant == "propagate":
-        ops_per_launch = propagate_ops_per_pair(W, H, k, (r, r, r2)) / launches_per_step
+        # launches per step as measured (a pipelined sweep pair is one launch)
+        ops_per_launch = (propagate_ops_per_pair(W, H, k, (r, r, r2)) +
+                          search_ops_in_sweep_launches(W, H, k, (r, r, r2))) / (nl.value / args.steps)
         achieved = ops_per_launch / (avg_launch_ms / 1000.0) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(INT_PEAK_TOPS, 2), "unit": "TOP/s",
                 "frac": round(achieved / INT_PEAK_TOPS, 5), "traffic": PROPAGATE_HBM_BYTES_PER_LAUNCH,
@@ -255,7 +275,7 @@ def bench_batch(args, ff, prs, torch, dev):
     m = ff.BatchMatcher(shapes)
     m.run(i1, i2, seeds=seeds)
     torch.cuda.synchronize()
-    best_bh, tune_ms = m.autotune(i1, i2)
+    best_bh, best_pipe, tune_ms = m.autotune(i1, i2)
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
@@ -298,7 +318,7 @@ def bench_batch(args, ff, prs, torch, dev):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": f"{len(prs)} layered pairs of mixed sizes (320x240 to 1242x375, 2-8 layers), "
                                f"{total_px} px per batch; whole batch replayed from one HIP graph",
-                   "band_rows": best_bh},
+                   "band_rows": best_bh, "pipelined_sweep_pairs": bool(best_pipe)},
         "one_pair_per_launch": {"ms_per_batch": round(ms_single, 3),
                                 "Mpixel_per_s": round(total_px / (ms_single / 1000.0) / 1e6, 3),
                                 "pairs_per_s": round(len(prs) / (ms_single / 1000.0), 2)},

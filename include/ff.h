@@ -97,6 +97,13 @@ typedef struct {
   uint32_t pair_id;   /* part of the random-search counter */
   int32_t band_rows;  /* propagation band height: 8, 16 (default) or 32 rows per
                          workgroup; results are identical for every value */
+  int32_t pipeline;   /* 1 (default): two consecutive sweeps with the same
+                         horizontal direction (and the random search between
+                         them) run as one launch, the second sweep starting on
+                         columns that the first and the search have finished;
+                         0: one launch per sweep and per search.  Results are
+                         identical; max_steps >= 0 implies 0 */
+  int32_t reserved;   /* must be 0 */
   uint64_t seed;      /* Philox key */
 } ff_match_params;
 

@@ -63,10 +63,12 @@ struct FieldRec {
   // kd-tree over the target (offsets into ws)
   int32_t t_nodes, t_top, pad2, pad3;
   uint32_t o_dim, o_split, o_perm, o_perm2, o_mm, o_hist, o_cnt, o_key;
-  // level grids n = 2..2^k (flow then cost) and the band handoff words
+  // level grids n = 2..2^k (flow then cost), the band handoff words of the
+  // first and of the second sweep of a launch, and the column-progress words
+  // of a pipelined sweep pair (two arrays)
   uint32_t o_grid[5];
   uint32_t o_xch;
-  uint32_t pad5[2];
+  uint32_t o_xch2, o_prog;
 };
 
 // Enqueue the kd-tree builds of `nf` fields whose records are in `table`

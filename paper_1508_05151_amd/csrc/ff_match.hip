@@ -28,6 +28,9 @@ constexpr int kLanesPt = 16;      // lanes per point in recost / random search
 constexpr int kStatusBytes = 256;
 constexpr int kMinBandRows = 8;   // smallest band height (sizes the handoff buffer)
 constexpr int kRecsPerWrite = 16; // table records per writer launch (kernel argument size)
+// words per pipelined-progress array: covers ceil(Gh / BH) * BH / 4 random-
+// search workgroups of any band height up to 32 at any level
+__host__ __device__ __forceinline__ int prog_words(int Hs) { return (Hs + 31) / 4 + 8; }
 
 // ---------------------------------------------------------------- per-field cost context
 struct CostCtx {
@@ -185,12 +188,22 @@ __global__ void k_write_table(RecChunk chunk, int n, FieldRec* __restrict__ out)
   if ((int)threadIdx.x < n) out[threadIdx.x] = chunk.r[threadIdx.x];
 }
 
-// zero every field's band handoff words (grid: chunks x fields)
+// zero every field's band handoff words and progress words (grid: chunks x
+// fields)
 __global__ void k_clear_xch(const FieldRec* __restrict__ table, int bands_rows) {
   const FieldRec& f = table[blockIdx.y];
   uint64_t* x = reinterpret_cast<uint64_t*>(f.ws + f.o_xch);
-  const size_t nw = (size_t)((f.Hs + bands_rows - 1) / bands_rows) * f.Ws;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += (size_t)gridDim.x * blockDim.x) x[i] = 0;
+  uint64_t* x2 = reinterpret_cast<uint64_t*>(f.ws + f.o_xch2);
+  int32_t* pg = reinterpret_cast<int32_t*>(f.ws + f.o_prog);
+  const size_t nb = (size_t)((f.Hs + bands_rows - 1) / bands_rows);
+  const size_t nw = nb * f.Ws;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += (size_t)gridDim.x * blockDim.x) {
+    x[i] = 0;
+    x2[i] = 0;
+  }
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * (size_t)prog_words(f.Hs);
+       i += (size_t)gridDim.x * blockDim.x)
+    pg[i] = 0;
 }
 
 // ---------------------------------------------------------------- seeds (Eq. 1 / Eq. 4)
@@ -430,17 +443,154 @@ __device__ __forceinline__ uint32_t tword(g_byte* base, uint32_t w) {
   return *reinterpret_cast<__attribute__((address_space(1))) const uint32_t*>(base + (w << 2));
 }
 
+// ---------------------------------------------------------------- pipelined sweep pairs
+// Two consecutive sweeps that share the horizontal direction (and so run in
+// opposite vertical directions) can overlap: a point's value after the first
+// sweep and the random search between them is all the second one needs, so
+// the second sweep may start on columns the first has finished.  Such a pair
+// is one launch with three roles, claimed in this order by the launch's
+// ticket: A (the first sweep, one workgroup per band), X (the random search
+// after A, kXRows grid rows of the second sweep's bands per workgroup, run
+// behind A's progress) and B (the second sweep, one workgroup per band,
+// starting a batch once X has finished the columns it stages).  Every wait is
+// on a workgroup with a lower ticket, which is already running.  The random
+// search of a point depends on that point alone, so every result equals the
+// one-launch-per-stage order.  Workgroups of one launch may sit on different
+// XCDs, whose L2 caches are not coherent: flows and costs that cross roles
+// are read and written with device-coherent (agent-scope) accesses, and A and
+// X publish how many columns of a band are final in a progress word (launch
+// tag << 20 | columns) after their stores have completed.
+constexpr int kRoleA = 0, kRoleX = 1, kRoleB = 2;
+constexpr int kXRows = 4;
+
+__device__ __forceinline__ int32_t ld_coh(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coh(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t prog_word(uint32_t tag, int cols) {
+  return (int32_t)(((tag & 0xFFFu) << 20) | (uint32_t)cols);
+}
+__device__ __forceinline__ int prog_cols(int32_t w, uint32_t tag) {
+  return ((uint32_t)w >> 20) == (tag & 0xFFFu) ? (int)((uint32_t)w & 0xFFFFFu) : 0;
+}
+// one thread: wait until a progress word reaches `need` columns; on the
+// watchdog the launch reports FF_ERR_DEVICE and the wait gives up, and once
+// an error is reported no later wait of the call waits at all
+__device__ bool wait_prog(const int32_t* w, uint32_t tag, int need, int32_t* status, uint64_t timeout) {
+  if (prog_cols(ld_coh(w), tag) >= need) return true;
+  const uint64_t t0 = rt_clock();
+  for (;;) {
+    __builtin_amdgcn_s_sleep(2);
+    if (prog_cols(ld_coh(w), tag) >= need) return true;
+    if (ld_coh(status) != 0) return false;
+    if (rt_clock() - t0 > timeout) {
+      __hip_atomic_store(status, (int32_t)FF_ERR_DEVICE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+  }
+}
+// all of this workgroup's global stores complete, then one word published
+__device__ __forceinline__ void publish_prog(int32_t* w, uint32_t tag, int cols) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) st_coh(w, prog_word(tag, cols));
+}
+
+// The random search of one grid point by a group of L = 16 lanes, as in
+// k_random_search, with device-coherent flow/cost accesses and the source
+// patch read from the plane.
+__device__ __forceinline__ void rs_point(const FieldRec& f, const CostCtx& c, int lev, int step, int R, int gx, int gy,
+                                         int Gw, int Gh, int lane) {
+  const int pid = gy * Gw + gx;
+  int32_t* F = grid_flow(f, lev);
+  int32_t* C = grid_cost(f, lev, Gw * Gh);
+  const int32_t fl = ld_coh(F + pid), cst = ld_coh(C + pid);
+  if (fl == kEmpty) return;
+  const int px = gx * c.n, py = gy * c.n;
+  const int rad = c.n * R * c.Q;
+  uint32_t u0, u1;
+  philox2((uint32_t)(py * c.Ws + px), (uint32_t)lev, (uint32_t)step, f.c3, f.k0, f.k1, u0, u1);
+  const uint64_t span = (uint64_t)(2 * rad + 1);
+  const int ox = (int)((u0 * span) >> 32) - rad;
+  const int oy = (int)((u1 * span) >> 32) - rad;
+  const int fx = fx_of(fl) + ox, fy = fy_of(fl) + oy;
+  if (!centre_valid(c, px, py, fx, fy)) return;
+  const int mx = px * c.Q + fx, my = py * c.Q + fy;
+  const int Mx = mx >> c.qshift, My = my >> c.qshift;
+  int32_t part;
+  if (lev == 0 && (c.r == 8 || c.r == 6) && px >= c.r && px + c.r < c.Ws && Mx >= c.r && Mx + c.r < c.Wd) {
+    const uint32_t* D2 = c.dst + (size_t)c.pw * (size_t)(((my & c.qmask) << c.qshift) + (mx & c.qmask));
+    g_u32* sb = (g_u32*)(c.src + (px - c.r));
+    g_u32* tb = (g_u32*)(D2 + (Mx - c.r));
+    part = c.r == 8 ? rows_sum_n1<17>(sb, c.Ws, py - 8, c.Hs - 1, tb, c.Wd, My - 8, c.Hd - 1, lane)
+                    : rows_sum_n1<13>(sb, c.Ws, py - 6, c.Hs - 1, tb, c.Wd, My - 6, c.Hd - 1, lane);
+  } else {
+    part = patch_partial(c, px, py, fx, fy, lane, 16);
+  }
+  const int32_t e = group_sum<16>(part);
+  if (lane == 0 && e < cst) {
+    st_coh(F + pid, packf(fx, fy));
+    st_coh(C + pid, e);
+  }
+}
+
+// An X workgroup: rows kXRows m .. kXRows m + kXRows - 1 of band k of the
+// second sweep (direction syX), columns in chunks of 32 as the first sweep's
+// bands (direction -syX, progress words progA) finish them; random search
+// step rs (< 0: none, progress is only passed on); publishes its progress in
+// progX[k * BH / kXRows + m].
+template <int BH>
+__device__ __forceinline__ void x_worker(const FieldRec& fr, const CostCtx& c, int lev, int k, int m, int sx,
+                                         int syX, const int32_t* progA, int32_t* progX, int rs, int R, uint32_t tag,
+                                         int32_t* status, uint64_t timeout) {
+  constexpr int CH = kBatch;
+  const int n = c.n;
+  const int Gw = (fr.Ws + n - 1) >> lev, Gh = (fr.Hs + n - 1) >> lev;
+  const int b0 = k * BH;
+  const int v0 = b0 + m * kXRows;
+  const int rows = min(kXRows, min(BH, Gh - b0) - m * kXRows);
+  int32_t* const pw = progX + k * (BH / kXRows) + m;
+  if (rows <= 0) {
+    publish_prog(pw, tag, Gw);
+    return;
+  }
+  // the first sweep's bands holding these grid rows (its rows run the other
+  // way: transformed row v here is Gh - 1 - v there)
+  const int blo = (Gh - 1 - (v0 + rows - 1)) / BH, bhi = (Gh - 1 - v0) / BH;
+  const int lane = threadIdx.x % 16, group = threadIdx.x / 16, ngroups = blockDim.x / 16;
+  for (int c0 = 0; c0 < Gw; c0 += CH) {
+    const int c1 = min(c0 + CH, Gw), cw = c1 - c0;
+    if (threadIdx.x == 0)
+      for (int b = blo; b <= bhi; ++b) wait_prog(progA + b, tag, c1, status, timeout);
+    __syncthreads();
+    if (rs >= 0) {
+      for (int i = group; i < rows * cw; i += ngroups) {
+        const int v = v0 + i / cw, u = c0 + i % cw;
+        const int gx = sx > 0 ? u : Gw - 1 - u, gy = syX > 0 ? v : Gh - 1 - v;
+        rs_point(fr, c, lev, rs, R, gx, gy, Gw, Gh, lane);
+      }
+    }
+    publish_prog(pw, tag, c1);
+  }
+}
+
+// pair = 0: one sweep (sx, sy), one workgroup per band; pair = 1: the sweep
+// pair (sx, sy) then (sx, -sy) with the random search step rs (< 0: none)
+// between them.  na: bands over the launch's fields.
 template <int TAIL, int BH>
 __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldRec* __restrict__ table, int f0, int nf,
                                                                int lev, int qshift, int sx, int sy, uint32_t tag,
                                                                int32_t* __restrict__ ticket,
                                                                int32_t* __restrict__ status,
-                                                               uint64_t timeout_ticks) {
+                                                               uint64_t timeout_ticks, int pair, int na, int rs,
+                                                               int R) {
   constexpr int L = kLanesProp, CH = kBatch;
   constexpr int NS = 4 + TAIL;   // term slots per lane
   static_assert(L == 16 && CH % 2 == 0 && CH % L == 0 && TAIL <= 4, "layout");
   constexpr int kTileWords = (BH + 2 * kMaxRadius + 1) * ((kBatch + BH + 2 * kMaxRadius) | 1);
-  __shared__ int32_t s_band, s_field;
+  __shared__ int32_t s_band, s_field, s_role, s_sub;
   __shared__ int32_t bufF[2][BH], bufC[2][BH];
   __shared__ int32_t topF[2], topC[2];   // row 0's vertical candidate, by step parity
   __shared__ int32_t inF[BH][CH], inC[BH][CH], outF[BH][CH], outC[BH][CH];
@@ -452,8 +602,23 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
   const int row = pollWave ? 0 : threadIdx.x / L, lane = threadIdx.x % L;
   const int n = 1 << lev;
   if (threadIdx.x == 0) {
-    // tickets are handed out in launch order; field-major, band-minor
+    // tickets are handed out in launch order; role-major, then field-major,
+    // band-minor
+    // role sizes: A and B one workgroup per band, X BH / kXRows
     int tk = atomicAdd(ticket, 1), fi = f0;
+    int role = -1, sub = 0;
+    for (int rb = 0; rb < (pair ? 3 : 1); ++rb) {
+      const int per = rb == kRoleX ? BH / kXRows : 1;
+      if (tk < na * per) {
+        role = rb;
+        sub = tk % per;
+        tk /= per;
+        break;
+      }
+      tk -= na * per;
+    }
+    s_role = role;
+    s_sub = sub;
     for (; fi < f0 + nf; ++fi) {
       const int gh = (table[fi].Hs + n - 1) >> lev;
       const int nb = (gh + BH - 1) / BH;
@@ -464,13 +629,25 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
     s_field = fi;
   }
   __syncthreads();
-  if (s_field >= f0 + nf) return;
+  if (s_field >= f0 + nf || s_role < 0) return;
   const FieldRec& fr = table[s_field];
   const CostCtx c = ctx_of(fr, lev, qshift);
   const int Gw = (fr.Ws + n - 1) >> lev, Gh = (fr.Hs + n - 1) >> lev;
   int32_t* const F = grid_flow(fr, lev);
   int32_t* const C = grid_cost(fr, lev, Gw * Gh);
-  uint64_t* const xch = reinterpret_cast<uint64_t*>(fr.ws + fr.o_xch);
+  const int role = s_role;
+  // progress words: A's bands, then X's workgroups
+  int32_t* const progA = reinterpret_cast<int32_t*>(fr.ws + fr.o_prog);
+  int32_t* const progX = progA + prog_words(fr.Hs);
+  if (role == kRoleX) {
+    x_worker<BH>(fr, c, lev, s_band, s_sub, sx, -sy, progA, progX, rs, R, tag, status, timeout_ticks);
+    return;
+  }
+  if (role == kRoleB) sy = -sy;
+  const bool coherent = pair != 0;   // flows/costs cross roles of this launch
+  const int32_t* const waitProg = role == kRoleB ? progX : nullptr;
+  int32_t* const pubProg = role == kRoleA && pair ? progA : nullptr;
+  uint64_t* const xch = reinterpret_cast<uint64_t*>(fr.ws + (role == kRoleB ? fr.o_xch2 : fr.o_xch));
   const int band = s_band;
   const int v0 = band * BH;
   if (v0 >= Gh) return;
@@ -659,6 +836,13 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
   const int TT = TH * TW;
   constexpr int KPT = (kTileWords + BH * L - 1) / (BH * L);   // tile words per thread
   for (int tb = 0; tb < nsteps; tb += CH) {
+    // a trailing sweep starts a batch once the columns it stages are final
+    if (waitProg) {
+      if (threadIdx.x == 0)
+        for (int m = 0; m < BH / kXRows; ++m)
+          wait_prog(waitProg + band * (BH / kXRows) + m, tag, min(tb + CH, Gw), status, timeout_ticks);
+      __syncthreads();
+    }
     // stage this batch's own flows and costs (row r at step tb + j works on
     // u = tb + j - r) and the source tile: tile(y, x) is the source census
     // at transformed grid (u, v) = (tb - BH - r + x, v0 - r - 1 + y),
@@ -668,8 +852,13 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
       const int j = lane + jj * L;
       const int u = tb + j - row;
       if (rowok && u >= 0 && u < Gw) {
-        inF[row][j] = Frow[gx_of(u)];
-        inC[row][j] = Crow[gx_of(u)];
+        if (coherent) {
+          inF[row][j] = ld_coh(Frow + gx_of(u));
+          inC[row][j] = ld_coh(Crow + gx_of(u));
+        } else {
+          inF[row][j] = Frow[gx_of(u)];
+          inC[row][j] = Crow[gx_of(u)];
+        }
       }
     }
     if (!pollWave) {
@@ -703,10 +892,17 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
       const int j = lane + jj * L;
       const int u = tb + j - row;
       if (rowok && u >= 0 && u < Gw && tb + j < te) {
-        Frow[gx_of(u)] = outF[row][j];
-        Crow[gx_of(u)] = outC[row][j];
+        if (coherent) {
+          st_coh(Frow + gx_of(u), outF[row][j]);
+          st_coh(Crow + gx_of(u), outC[row][j]);
+        } else {
+          Frow[gx_of(u)] = outF[row][j];
+          Crow[gx_of(u)] = outC[row][j];
+        }
       }
     }
+    // after steps < te every row has finished columns u <= te - rows
+    if (pubProg) publish_prog(pubProg + band, tag, min(max(te - rows + 1, 0), Gw));
   }
 }
 
@@ -729,30 +925,40 @@ __global__ void k_write_grid(const FieldRec* __restrict__ table, int lev) {
   }
 }
 
+// One propagation launch: a sweep, or a sweep pair (A, X, B workgroups).
+struct PropLaunch {
+  int lev, qshift, sx, sy;
+  uint32_t tag;
+  int32_t* ticket;
+  int32_t* status;
+  uint64_t timeout;
+  int pair, rs, R;
+};
+
 template <int BH>
-static void launch_propagate_bh(int r, int bands, hipStream_t stream, const FieldRec* table, int f0, int nf, int lev,
-                                int qshift, int sx, int sy, uint32_t tag, int32_t* ticket, int32_t* status,
-                                uint64_t timeout) {
-  const dim3 grid(bands), block(BH * kLanesProp + 64);
+static void launch_propagate_bh(int r, int bands, hipStream_t stream, const FieldRec* table, int f0, int nf,
+                                const PropLaunch& L) {
+  const int per = L.pair ? 2 + BH / kXRows : 1;
+  const dim3 grid(bands * per), block(BH * kLanesProp + 64);
   const int S = 2 * r + 1, tail = S > 16 ? (4 * (S - 16) + 15) / 16 : 0;
-#define FF_PROP(TA)                                                                                              \
-  if (tail == TA) {                                                                                              \
-    k_propagate<TA, BH><<<grid, block, 0, stream>>>(table, f0, nf, lev, qshift, sx, sy, tag, ticket, status, timeout); \
-    return;                                                                                                      \
+#define FF_PROP(TA)                                                                                                \
+  if (tail == TA) {                                                                                                \
+    k_propagate<TA, BH><<<grid, block, 0, stream>>>(table, f0, nf, L.lev, L.qshift, L.sx, L.sy, L.tag, L.ticket,    \
+                                                    L.status, L.timeout, L.pair, bands, L.rs, L.R);                \
+    return;                                                                                                        \
   }
   FF_PROP(0) FF_PROP(1) FF_PROP(2) FF_PROP(3) FF_PROP(4)
 #undef FF_PROP
 }
 
 static void launch_propagate(int bh, int r, int bands, hipStream_t stream, const FieldRec* table, int f0, int nf,
-                             int lev, int qshift, int sx, int sy, uint32_t tag, int32_t* ticket, int32_t* status,
-                             uint64_t timeout) {
+                             const PropLaunch& L) {
   if (bh == 8)
-    launch_propagate_bh<8>(r, bands, stream, table, f0, nf, lev, qshift, sx, sy, tag, ticket, status, timeout);
+    launch_propagate_bh<8>(r, bands, stream, table, f0, nf, L);
   else if (bh == 32)
-    launch_propagate_bh<32>(r, bands, stream, table, f0, nf, lev, qshift, sx, sy, tag, ticket, status, timeout);
+    launch_propagate_bh<32>(r, bands, stream, table, f0, nf, L);
   else
-    launch_propagate_bh<16>(r, bands, stream, table, f0, nf, lev, qshift, sx, sy, tag, ticket, status, timeout);
+    launch_propagate_bh<16>(r, bands, stream, table, f0, nf, L);
 }
 
 // ---------------------------------------------------------------- host plans
@@ -760,7 +966,7 @@ struct FieldPlan {
   bool has_tree;
   TreeLayout tree;        // offsets relative to the field region
   size_t off_grid[5];
-  size_t off_xch;
+  size_t off_xch, off_xch2, off_prog;
   size_t bytes;
 };
 
@@ -779,9 +985,14 @@ static FieldPlan field_plan(const ff_desc* src, const ff_desc* dst, const ff_mat
     P.off_grid[lev] = off;
     off += G * 8;
   }
+  const size_t nb = (size_t)((src->height + kMinBandRows - 1) / kMinBandRows);
   off = align_up(off, 256);
   P.off_xch = off;
-  off += (size_t)((src->height + kMinBandRows - 1) / kMinBandRows) * src->width * 8;
+  off = align_up(off + nb * src->width * 8, 256);
+  P.off_xch2 = off;
+  off = align_up(off + nb * src->width * 8, 256);
+  P.off_prog = off;
+  off += 2 * (size_t)prog_words(src->height) * 4;
   P.bytes = align_up(off, 256);
   return P;
 }
@@ -796,6 +1007,8 @@ static ff_status check_params(const ff_desc* src, const ff_desc* dst, int radius
   if (p->R < 0 || p->R > 64 || p->n_prop < 0 || p->n_prop > 64 || p->n_rs < 0 || p->n_rs > p->n_prop) return FF_ERR_ARG;
   if (p->field_id > 3) return FF_ERR_ARG;
   if (p->band_rows != 0 && p->band_rows != 8 && p->band_rows != 16 && p->band_rows != 32) return FF_ERR_ARG;
+  if (p->pipeline != 0 && p->pipeline != 1) return FF_ERR_ARG;
+  if (p->reserved != 0) return FF_ERR_ARG;
   if (p->use_kdtree) {
     if (p->leaf < 2 || p->leaf > kMaxLeaf) return FF_ERR_ARG;
     bool hs = false, hd = false;
@@ -889,6 +1102,8 @@ static FieldRec make_rec(const ff_field_job& j, const ff_match_params* p, char* 
   }
   for (int l = 0; l < 5; ++l) r.o_grid[l] = (uint32_t)P.off_grid[l];
   r.o_xch = (uint32_t)P.off_xch;
+  r.o_xch2 = (uint32_t)P.off_xch2;
+  r.o_prog = (uint32_t)P.off_prog;
   return r;
 }
 
@@ -938,6 +1153,9 @@ static ff_status run_batch(const ff_field_job* jobs, int n, const ff_match_param
     const int pt = 256 / kLanesPt;
     return (unsigned)((((maxW + (1 << lev) - 1) >> lev) + pt - 1) / pt * ((maxH + (1 << lev) - 1) >> lev));
   };
+  // pipelined launches need tags below 2^12 (progress words) and no
+  // inspection stops between their stages
+  const bool pipe = p->pipeline == 1 && p->max_steps < 0 && B.launches < 4096;
   int steps = 0, cur_lev = k;
   auto stop = [&]() { return p->max_steps >= 0 && steps >= p->max_steps; };
   auto finish = [&]() -> ff_status {
@@ -963,11 +1181,10 @@ static ff_status run_batch(const ff_field_job* jobs, int n, const ff_match_param
       ++steps;
       if (stop()) return finish();
     }
-    for (int i = 0; i < p->n_prop; ++i) {
-      const int dir = i & 3;
-      const int sx = (dir == 0 || dir == 3) ? 1 : -1;
-      const int sy = (dir == 0 || dir == 2) ? 1 : -1;
-      prof_mark(FF_PROF_PROPAGATE, stream, true);
+    auto sx_of = [](int i) { return ((i & 3) == 0 || (i & 3) == 3) ? 1 : -1; };
+    auto sy_of = [](int i) { return ((i & 3) == 0 || (i & 3) == 2) ? 1 : -1; };
+    // one launch per patch radius group; `L` names the launch's roles
+    auto propagate = [&](PropLaunch L) {
       for (int g0 = 0; g0 < n;) {
         int g1 = g0;
         int bands = 0;
@@ -976,11 +1193,33 @@ static ff_status run_batch(const ff_field_job* jobs, int n, const ff_match_param
           bands += (gh + bh - 1) / bh;
           ++g1;
         }
-        launch_propagate(bh, recs[g0].r, bands, stream, table, g0, g1 - g0, lev, qshift, sx, sy,
-                         (uint32_t)(launch + 1), tickets + launch, status, timeout);
+        L.tag = (uint32_t)(launch + 1);
+        L.ticket = tickets + launch;
+        launch_propagate(bh, recs[g0].r, bands, stream, table, g0, g1 - g0, L);
         ++launch;
         g0 = g1;
       }
+    };
+    for (int i = 0; i < p->n_prop;) {
+      PropLaunch L{lev, qshift, sx_of(i), sy_of(i), 0, nullptr, status, timeout, 0, -1, p->R};
+      if (pipe && i + 1 < p->n_prop && sx_of(i + 1) == sx_of(i)) {
+        // sweeps i and i + 1 as one pipelined launch with the random search
+        // between them; the search after sweep i + 1 follows on its own
+        L.pair = 1;
+        L.rs = i < p->n_rs ? i : -1;
+        prof_mark(FF_PROF_PROPAGATE, stream, true);
+        propagate(L);
+        prof_mark(FF_PROF_PROPAGATE, stream, false);
+        if (i + 1 < p->n_rs) {
+          prof_mark(FF_PROF_RANDOM_SEARCH, stream, true);
+          k_random_search<kLanesPt><<<dim3(rs_blocks(lev), n), 256, 0, stream>>>(table, lev, qshift, i + 1, p->R);
+          prof_mark(FF_PROF_RANDOM_SEARCH, stream, false);
+        }
+        i += 2;
+        continue;
+      }
+      prof_mark(FF_PROF_PROPAGATE, stream, true);
+      propagate(L);
       prof_mark(FF_PROF_PROPAGATE, stream, false);
       ++steps;
       if (stop()) return finish();
@@ -991,6 +1230,7 @@ static ff_status run_batch(const ff_field_job* jobs, int n, const ff_match_param
         ++steps;
         if (stop()) return finish();
       }
+      ++i;
     }
   }
   (void)maxG;
@@ -1015,6 +1255,7 @@ void ff_default_params(ff_match_params* p) {
   p->use_kdtree = 1;
   p->max_steps = -1;
   p->band_rows = 16;
+  p->pipeline = 1;
 }
 
 size_t ff_match_batch_workspace_bytes(const ff_field_job* jobs, int32_t n_jobs, const ff_match_params* p) {

@@ -47,7 +47,7 @@ class ff_match_params(C.Structure):
     _fields_ = [("k", C.c_int32), ("R", C.c_int32), ("leaf", C.c_int32), ("n_prop", C.c_int32),
                 ("n_rs", C.c_int32), ("use_kdtree", C.c_int32), ("max_steps", C.c_int32),
                 ("field_id", C.c_uint32), ("pair_id", C.c_uint32), ("band_rows", C.c_int32),
-                ("seed", C.c_uint64)]
+                ("pipeline", C.c_int32), ("reserved", C.c_int32), ("seed", C.c_uint64)]
 
 
 class ff_field_job(C.Structure):
@@ -384,25 +384,28 @@ class BatchMatcher:
     def status(self):
         return ff_read_status(self.ws)
 
-    def autotune(self, imgs1, imgs2, candidates=(8, 16, 32), reps=2):
-        """Time the propagation band height on this batch; keep the fastest
-        (every candidate gives identical bytes)."""
+    def autotune(self, imgs1, imgs2, band_rows=(8, 16, 32), pipeline=(1, 0), reps=2):
+        """Time every (band height, sweep-pair pipelining) combination on this
+        batch and keep the fastest (all give identical bytes).  Returns
+        (band_rows, pipeline, ms)."""
         best = None
-        for bh in candidates:
-            self.params.band_rows = bh
-            self.run(imgs1, imgs2)
-            torch.cuda.synchronize()
-            t0 = torch.cuda.Event(enable_timing=True)
-            t1 = torch.cuda.Event(enable_timing=True)
-            t0.record()
-            for _ in range(reps):
+        for bh in band_rows:
+            for pipe in pipeline:
+                self.params.band_rows = bh
+                self.params.pipeline = pipe
                 self.run(imgs1, imgs2)
-            t1.record()
-            torch.cuda.synchronize()
-            ms = t0.elapsed_time(t1) / reps
-            if best is None or ms < best[1]:
-                best = (bh, ms)
-        self.params.band_rows = best[0]
+                torch.cuda.synchronize()
+                t0 = torch.cuda.Event(enable_timing=True)
+                t1 = torch.cuda.Event(enable_timing=True)
+                t0.record()
+                for _ in range(reps):
+                    self.run(imgs1, imgs2)
+                t1.record()
+                torch.cuda.synchronize()
+                ms = t0.elapsed_time(t1) / reps
+                if best is None or ms < best[2]:
+                    best = (bh, pipe, ms)
+        self.params.band_rows, self.params.pipeline = best[0], best[1]
         return best
 
 

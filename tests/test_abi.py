@@ -38,8 +38,8 @@ def test_every_declared_symbol_is_exported(ff):
 def test_struct_layouts_match_header(ff):
     # ff_desc: 12 int32 then 7 size_t; ff_match_params: 10 x 4-byte fields then uint64
     assert C.sizeof(ff.ff_desc) == 12 * 4 + 7 * 8
-    assert C.sizeof(ff.ff_match_params) == 10 * 4 + 8
-    assert ff.ff_match_params.seed.offset == 40
+    assert C.sizeof(ff.ff_match_params) == 12 * 4 + 8
+    assert ff.ff_match_params.seed.offset == 48
     # ff_field_job: 4 pointers, 4 x 4-byte fields, uint64 seed, 3 pointers
     assert C.sizeof(ff.ff_field_job) == 4 * 8 + 4 * 4 + 8 + 3 * 8
     assert ff.ff_field_job.seed.offset == 48 and ff.ff_field_job.cost.offset == 72
@@ -65,10 +65,13 @@ def test_match_argument_checks_before_any_launch(ff):
     d = ff.ff_desc_init(64, 48, 3, 3, 4, (8,))
     p = ff.ff_default_params()
     assert (p.k, p.R, p.leaf, p.n_prop, p.n_rs, p.use_kdtree, p.max_steps) == (3, 1, 8, 4, 3, 1, -1)
+    assert (p.band_rows, p.pipeline, p.reserved) == (16, 1, 0)
     assert ff.ff_match_workspace_bytes(d, d, 8, p) > 0
     L = ff.lib()
     # radius without WHT vectors, leaf out of range, k above the descriptors'
-    for r, kw in [(6, {}), (8, dict(leaf=1)), (8, dict(k=4)), (8, dict(n_rs=5)), (8, dict(field_id=4))]:
+    # pipeline flag 0/1 only, reserved word zero
+    for r, kw in [(6, {}), (8, dict(leaf=1)), (8, dict(k=4)), (8, dict(n_rs=5)), (8, dict(field_id=4)),
+                  (8, dict(pipeline=2)), (8, dict(reserved=1))]:
         q = ff.ff_default_params(**kw)
         assert L.ff_match_workspace_bytes(C.byref(d), C.byref(d), r, C.byref(q)) == 0
     # null buffers are rejected before anything is enqueued

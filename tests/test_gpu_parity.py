@@ -227,3 +227,23 @@ def test_search_parameter_variants_bit_exact(ff, R, n_prop, n_rs, k, leaf):
     o1, o2 = ffo.Desc(p.img1, k, Q, (r,)), ffo.Desc(p.img2, k, Q, (r,))
     oF, oC = ffo.match_field(o1, o2, r, k=k, R=R, n_prop=n_prop, n_rs=n_rs, leaf=leaf, seed=7)
     assert np.array_equal(gF, oF) and np.array_equal(gC, oC)
+
+
+@pytest.mark.parametrize("band_rows", [8, 16, 32])
+def test_pipelined_sweeps_equal_one_launch_per_stage(ff, band_rows):
+    """The pipelined launches (random search behind its sweep, the next sweep
+    of the same horizontal direction trailing it) give the same field as one
+    launch per sweep and per search, at every band height; a ragged size so
+    that the two sweeps' bands do not align."""
+    p = _ragged_pair(77 + band_rows, 150, 101, nlayers=4)
+    _say("pipeline", band_rows)
+    k, r = 3, 8
+    d1, b1 = _gpu_desc(ff, p.img1, k, (r,))
+    d2, b2 = _gpu_desc(ff, p.img2, k, (r,))
+    on = _gpu_field(ff, d1, b1, d2, b2, r, k=k, band_rows=band_rows, pipeline=1, seed=21)
+    off = _gpu_field(ff, d1, b1, d2, b2, r, k=k, band_rows=band_rows, pipeline=0, seed=21)
+    assert np.array_equal(on[0], off[0]) and np.array_equal(on[1], off[1])
+    if band_rows == 16:
+        o1, o2 = ffo.Desc(p.img1, k, Q, (r,)), ffo.Desc(p.img2, k, Q, (r,))
+        oF, oC = ffo.match_field(o1, o2, r, k=k, seed=21)
+        assert np.array_equal(on[0], oF) and np.array_equal(on[1], oC)
