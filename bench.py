@@ -27,12 +27,12 @@ HBM_PEAK_GBS = 8000.0
 CUS, LANES_PER_CU, CLOCK_GHZ = 256, 64, 2.4
 INT_PEAK_TOPS = CUS * LANES_PER_CU * CLOCK_GHZ / 1000.0   # 32-bit integer VALU ops, 39.3 T/s
 
-# HBM bytes per k_propagate launch (average over the 36 launches of one pair:
+# HBM bytes per k_propagate launch (average over the 27 launches of one pair:
 # single sweeps and pipelined sweep pairs),
 # from FETCH_SIZE and WRITE_SIZE counter runs scaled by a plain-copy
 # calibration; profiles/hotpath_1024x436_hbm_counters.md holds the runs.
 # Valid for the current k_propagate only.
-PROPAGATE_HBM_BYTES_PER_LAUNCH = 47.26e6
+PROPAGATE_HBM_BYTES_PER_LAUNCH = 69.57e6
 
 PROF_CLASS = {"descriptors": 1, "tree": 2, "seed": 3, "level_entry": 4, "propagate": 5, "random_search": 6,
               "filter": 7}
@@ -50,21 +50,33 @@ def propagate_ops_per_pair(W, H, k, radii, n_prop=4):
     return sum(n_prop * pts * 2 * 2 * (2 * r + 1) * 2 for r in radii)
 
 
-def search_ops_in_sweep_launches(W, H, k, radii, n_prop=4, n_rs=3):
-    """Algorithmic integer ops of the random searches that run inside
-    pipelined sweep-pair launches (sweeps i, i + 1 with the same horizontal
-    direction: with four sweeps per level, the search after sweep 2): per
-    grid point (2r+1)^2 census terms of 2 ops."""
+def per_point_ops_in_sweep_launches(W, H, k, radii, n_prop=4, n_rs=3):
+    """Algorithmic integer ops of the per-point stages that run inside
+    pipelined sweep-pair launches, following the library's pairing: two
+    sweeps of one level with the same horizontal direction hold the random
+    search between them (all grid points), and a level's last sweep paired
+    with the next level's first holds that level's entry (the carried points,
+    one per point of the coarser grid); each point costs (2r+1)^2 census
+    terms of 2 ops."""
     sx = lambda i: 1 if (i & 3) in (0, 3) else -1
-    inside, i = 0, 0
-    while i < n_prop:
-        if i + 1 < n_prop and sx(i + 1) == sx(i):
-            inside += 1 if i < n_rs else 0
-            i += 2
-        else:
-            i += 1
-    pts = sum(grid_points(W, H, k))
-    return sum(inside * pts * (2 * r + 1) ** 2 * 2 for r in radii)
+    sy = lambda i: 1 if (i & 3) in (0, 2) else -1
+    pts = grid_points(W, H, k)
+    terms = 0          # grid points costed inside launches, per field
+    entered = False
+    for lev in range(k, -1, -1):
+        i = 1 if entered else 0
+        entered = False
+        while i < n_prop:
+            if i + 1 < n_prop and sx(i + 1) == sx(i):
+                terms += pts[lev] if i < n_rs else 0
+                i += 2
+            elif (i == n_prop - 1 and i >= n_rs and lev > 0 and sx(0) == sx(i) and sy(0) == -sy(i)):
+                terms += pts[lev]       # points of level lev = the carried points of level lev - 1
+                entered = True
+                i += 1
+            else:
+                i += 1
+    return sum(terms * (2 * r + 1) ** 2 * 2 for r in radii)
 
 
 def cpu_sample(crop_w, crop_h):
@@ -177,7 +189,7 @@ def main():
     if args.dominant == "propagate":
         # launches per step as measured (a pipelined sweep pair is one launch)
         ops_per_launch = (propagate_ops_per_pair(W, H, k, (r, r, r2)) +
-                          search_ops_in_sweep_launches(W, H, k, (r, r, r2))) / (nl.value / args.steps)
+                          per_point_ops_in_sweep_launches(W, H, k, (r, r, r2))) / (nl.value / args.steps)
         achieved = ops_per_launch / (avg_launch_ms / 1000.0) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(INT_PEAK_TOPS, 2), "unit": "TOP/s",
                 "frac": round(achieved / INT_PEAK_TOPS, 5), "traffic": PROPAGATE_HBM_BYTES_PER_LAUNCH,

@@ -460,8 +460,14 @@ __device__ __forceinline__ uint32_t tword(g_byte* base, uint32_t w) {
 // are read and written with device-coherent (agent-scope) accesses, and A and
 // X publish how many columns of a band are final in a progress word (launch
 // tag << 20 | columns) after their stores have completed.
+// The same holds across a level change: the last sweep of level 2n runs in
+// the horizontal direction of the first sweep of level n, and only the level
+// entry (coarse flows carried to the finer grid and re-costed, a per-point
+// step like the random search) lies between them; such a cross-level pair has
+// A on the coarse grid and X (the level entry) and B on the fine one.
 constexpr int kRoleA = 0, kRoleX = 1, kRoleB = 2;
 constexpr int kXRows = 4;
+constexpr int kPairSame = 1, kPairCross = 2;
 
 __device__ __forceinline__ int32_t ld_coh(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -536,18 +542,54 @@ __device__ __forceinline__ void rs_point(const FieldRec& f, const CostCtx& c, in
   }
 }
 
+// The level entry of one fine grid point by a group of 16 lanes, as in
+// k_level_entry, with device-coherent flow/cost accesses.
+__device__ __forceinline__ void entry_point(const FieldRec& f, const CostCtx& c, int lev, int gx, int gy, int Gw,
+                                            int Gh, int lane) {
+  int32_t fl = kEmpty, e = kInf;
+  if (!(gx & 1) && !(gy & 1)) {
+    const int Gwc = (f.Ws + 2 * c.n - 1) >> (lev + 1);
+    fl = ld_coh(grid_flow(f, lev + 1) + (size_t)(gy >> 1) * Gwc + (gx >> 1));
+    if (fl != kEmpty) {
+      const int px = gx * c.n, py = gy * c.n, fx = fx_of(fl), fy = fy_of(fl);
+      const int mx = px * c.Q + fx, my = py * c.Q + fy;
+      const int Mx = mx >> c.qshift, My = my >> c.qshift;
+      int32_t part;
+      if (lev == 0 && (c.r == 8 || c.r == 6) && px >= c.r && px + c.r < c.Ws && Mx >= c.r && Mx + c.r < c.Wd) {
+        const uint32_t* D2 = c.dst + (size_t)c.pw * (size_t)(((my & c.qmask) << c.qshift) + (mx & c.qmask));
+        g_u32* sb = (g_u32*)(c.src + (px - c.r));
+        g_u32* tb = (g_u32*)(D2 + (Mx - c.r));
+        part = c.r == 8 ? rows_sum_n1<17>(sb, c.Ws, py - 8, c.Hs - 1, tb, c.Wd, My - 8, c.Hd - 1, lane)
+                        : rows_sum_n1<13>(sb, c.Ws, py - 6, c.Hs - 1, tb, c.Wd, My - 6, c.Hd - 1, lane);
+      } else {
+        part = patch_partial(c, px, py, fx, fy, lane, 16);
+      }
+      e = group_sum<16>(part);
+    }
+  }
+  if (lane == 0) {
+    st_coh(grid_flow(f, lev) + (size_t)gy * Gw + gx, fl);
+    st_coh(grid_cost(f, lev, Gw * Gh) + (size_t)gy * Gw + gx, e);
+  }
+}
+
 // An X workgroup: rows kXRows m .. kXRows m + kXRows - 1 of band k of the
-// second sweep (direction syX), columns in chunks of 32 as the first sweep's
-// bands (direction -syX, progress words progA) finish them; random search
-// step rs (< 0: none, progress is only passed on); publishes its progress in
-// progX[k * BH / kXRows + m].
+// second sweep (level lev, direction syX), columns in chunks of 32 as the
+// first sweep's bands (direction -syX, progress words progA) finish the
+// columns they need; publishes its progress in progX[k * BH / kXRows + m].
+// Same-level pair: random search step rs (< 0: none, progress is only passed
+// on), the first sweep on the same grid.  Cross-level pair: the level entry,
+// the first sweep on the grid of level lev + 1.
 template <int BH>
-__device__ __forceinline__ void x_worker(const FieldRec& fr, const CostCtx& c, int lev, int k, int m, int sx,
-                                         int syX, const int32_t* progA, int32_t* progX, int rs, int R, uint32_t tag,
-                                         int32_t* status, uint64_t timeout) {
+__device__ __forceinline__ void x_worker(const FieldRec& fr, const CostCtx& c, int lev, bool cross, int k, int m,
+                                         int sx, int syX, const int32_t* progA, int32_t* progX, int rs, int R,
+                                         uint32_t tag, int32_t* status, uint64_t timeout) {
   constexpr int CH = kBatch;
   const int n = c.n;
   const int Gw = (fr.Ws + n - 1) >> lev, Gh = (fr.Hs + n - 1) >> lev;
+  // the first sweep's grid
+  const int la = cross ? lev + 1 : lev;
+  const int Gwa = (fr.Ws + (1 << la) - 1) >> la, Gha = (fr.Hs + (1 << la) - 1) >> la;
   const int b0 = k * BH;
   const int v0 = b0 + m * kXRows;
   const int rows = min(kXRows, min(BH, Gh - b0) - m * kXRows);
@@ -556,36 +598,48 @@ __device__ __forceinline__ void x_worker(const FieldRec& fr, const CostCtx& c, i
     publish_prog(pw, tag, Gw);
     return;
   }
-  // the first sweep's bands holding these grid rows (its rows run the other
-  // way: transformed row v here is Gh - 1 - v there)
-  const int blo = (Gh - 1 - (v0 + rows - 1)) / BH, bhi = (Gh - 1 - v0) / BH;
+  // the first sweep's bands holding these grid rows: grid rows gy (range
+  // gya..gyb) lie in row gy >> cross of the first sweep's grid, which that
+  // sweep (direction -syX) numbers Gha - 1 - (gy >> cross) if it runs upward
+  const int gya = syX > 0 ? v0 : Gh - 1 - (v0 + rows - 1), gyb = syX > 0 ? v0 + rows - 1 : Gh - 1 - v0;
+  const int sh = cross ? 1 : 0;
+  const int blo = syX > 0 ? (Gha - 1 - (gyb >> sh)) / BH : (gya >> sh) / BH;
+  const int bhi = syX > 0 ? (Gha - 1 - (gya >> sh)) / BH : (gyb >> sh) / BH;
   const int lane = threadIdx.x % 16, group = threadIdx.x / 16, ngroups = blockDim.x / 16;
   for (int c0 = 0; c0 < Gw; c0 += CH) {
     const int c1 = min(c0 + CH, Gw), cw = c1 - c0;
+    // columns of the first sweep's grid that hold this chunk's points: the
+    // last column of the chunk maps to the largest one
+    const int gxl = sx > 0 ? c1 - 1 : Gw - c1;
+    const int need = (sx > 0 ? (gxl >> sh) : Gwa - 1 - (gxl >> sh)) + 1;
     if (threadIdx.x == 0)
-      for (int b = blo; b <= bhi; ++b) wait_prog(progA + b, tag, c1, status, timeout);
+      for (int b = blo; b <= bhi; ++b) wait_prog(progA + b, tag, need, status, timeout);
     __syncthreads();
-    if (rs >= 0) {
+    if (cross || rs >= 0) {
       for (int i = group; i < rows * cw; i += ngroups) {
         const int v = v0 + i / cw, u = c0 + i % cw;
         const int gx = sx > 0 ? u : Gw - 1 - u, gy = syX > 0 ? v : Gh - 1 - v;
-        rs_point(fr, c, lev, rs, R, gx, gy, Gw, Gh, lane);
+        if (cross) entry_point(fr, c, lev, gx, gy, Gw, Gh, lane);
+        else rs_point(fr, c, lev, rs, R, gx, gy, Gw, Gh, lane);
       }
     }
     publish_prog(pw, tag, c1);
   }
 }
 
-// pair = 0: one sweep (sx, sy), one workgroup per band; pair = 1: the sweep
-// pair (sx, sy) then (sx, -sy) with the random search step rs (< 0: none)
-// between them.  na: bands over the launch's fields.
+// pair = 0: one sweep (sx, sy) at level lev, one workgroup per band;
+// kPairSame: the sweep pair (sx, sy) then (sx, -sy) at level lev with the
+// random search step rs (< 0: none) between them; kPairCross: the sweep
+// (sx, sy) at level lev + 1, the level entry of level lev, then the sweep
+// (sx, -sy) at level lev.  na: bands of level lev over the launch's fields;
+// na_a: bands of the first sweep's level.
 template <int TAIL, int BH>
 __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldRec* __restrict__ table, int f0, int nf,
                                                                int lev, int qshift, int sx, int sy, uint32_t tag,
                                                                int32_t* __restrict__ ticket,
                                                                int32_t* __restrict__ status,
-                                                               uint64_t timeout_ticks, int pair, int na, int rs,
-                                                               int R) {
+                                                               uint64_t timeout_ticks, int pair, int na, int na_a,
+                                                               int rs, int R) {
   constexpr int L = kLanesProp, CH = kBatch;
   constexpr int NS = 4 + TAIL;   // term slots per lane
   static_assert(L == 16 && CH % 2 == 0 && CH % L == 0 && TAIL <= 4, "layout");
@@ -600,27 +654,27 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
   // step ahead, so that no compute wavefront polls global memory
   const bool pollWave = __builtin_amdgcn_readfirstlane(threadIdx.x) >= BH * L;
   const int row = pollWave ? 0 : threadIdx.x / L, lane = threadIdx.x % L;
-  const int n = 1 << lev;
   if (threadIdx.x == 0) {
     // tickets are handed out in launch order; role-major, then field-major,
-    // band-minor
-    // role sizes: A and B one workgroup per band, X BH / kXRows
+    // band-minor; role sizes: A na_a, X na BH / kXRows, B na
     int tk = atomicAdd(ticket, 1), fi = f0;
     int role = -1, sub = 0;
     for (int rb = 0; rb < (pair ? 3 : 1); ++rb) {
       const int per = rb == kRoleX ? BH / kXRows : 1;
-      if (tk < na * per) {
+      const int cnt = (rb == kRoleA ? na_a : na) * per;
+      if (tk < cnt) {
         role = rb;
         sub = tk % per;
         tk /= per;
         break;
       }
-      tk -= na * per;
+      tk -= cnt;
     }
     s_role = role;
     s_sub = sub;
+    const int nr = 1 << (role == kRoleA && pair == kPairCross ? lev + 1 : lev);
     for (; fi < f0 + nf; ++fi) {
-      const int gh = (table[fi].Hs + n - 1) >> lev;
+      const int gh = (table[fi].Hs + nr - 1) / nr;
       const int nb = (gh + BH - 1) / BH;
       if (tk < nb) break;
       tk -= nb;
@@ -630,17 +684,20 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
   }
   __syncthreads();
   if (s_field >= f0 + nf || s_role < 0) return;
+  const int role = s_role;
+  if (role == kRoleA && pair == kPairCross) ++lev;   // the first sweep runs on the coarser grid
+  const int n = 1 << lev;
   const FieldRec& fr = table[s_field];
   const CostCtx c = ctx_of(fr, lev, qshift);
   const int Gw = (fr.Ws + n - 1) >> lev, Gh = (fr.Hs + n - 1) >> lev;
   int32_t* const F = grid_flow(fr, lev);
   int32_t* const C = grid_cost(fr, lev, Gw * Gh);
-  const int role = s_role;
   // progress words: A's bands, then X's workgroups
   int32_t* const progA = reinterpret_cast<int32_t*>(fr.ws + fr.o_prog);
   int32_t* const progX = progA + prog_words(fr.Hs);
   if (role == kRoleX) {
-    x_worker<BH>(fr, c, lev, s_band, s_sub, sx, -sy, progA, progX, rs, R, tag, status, timeout_ticks);
+    x_worker<BH>(fr, c, lev, pair == kPairCross, s_band, s_sub, sx, -sy, progA, progX, rs, R, tag, status,
+                 timeout_ticks);
     return;
   }
   if (role == kRoleB) sy = -sy;
@@ -925,7 +982,8 @@ __global__ void k_write_grid(const FieldRec* __restrict__ table, int lev) {
   }
 }
 
-// One propagation launch: a sweep, or a sweep pair (A, X, B workgroups).
+// One propagation launch: a sweep, or a sweep pair (A, X, B workgroups);
+// lev is the level of the (second) sweep.
 struct PropLaunch {
   int lev, qshift, sx, sy;
   uint32_t tag;
@@ -936,29 +994,28 @@ struct PropLaunch {
 };
 
 template <int BH>
-static void launch_propagate_bh(int r, int bands, hipStream_t stream, const FieldRec* table, int f0, int nf,
-                                const PropLaunch& L) {
-  const int per = L.pair ? 2 + BH / kXRows : 1;
-  const dim3 grid(bands * per), block(BH * kLanesProp + 64);
+static void launch_propagate_bh(int r, int bands, int bands_a, hipStream_t stream, const FieldRec* table, int f0,
+                                int nf, const PropLaunch& L) {
+  const dim3 grid(L.pair ? bands_a + bands * (1 + BH / kXRows) : bands), block(BH * kLanesProp + 64);
   const int S = 2 * r + 1, tail = S > 16 ? (4 * (S - 16) + 15) / 16 : 0;
 #define FF_PROP(TA)                                                                                                \
   if (tail == TA) {                                                                                                \
     k_propagate<TA, BH><<<grid, block, 0, stream>>>(table, f0, nf, L.lev, L.qshift, L.sx, L.sy, L.tag, L.ticket,    \
-                                                    L.status, L.timeout, L.pair, bands, L.rs, L.R);                \
+                                                    L.status, L.timeout, L.pair, bands, bands_a, L.rs, L.R);       \
     return;                                                                                                        \
   }
   FF_PROP(0) FF_PROP(1) FF_PROP(2) FF_PROP(3) FF_PROP(4)
 #undef FF_PROP
 }
 
-static void launch_propagate(int bh, int r, int bands, hipStream_t stream, const FieldRec* table, int f0, int nf,
-                             const PropLaunch& L) {
+static void launch_propagate(int bh, int r, int bands, int bands_a, hipStream_t stream, const FieldRec* table, int f0,
+                             int nf, const PropLaunch& L) {
   if (bh == 8)
-    launch_propagate_bh<8>(r, bands, stream, table, f0, nf, L);
+    launch_propagate_bh<8>(r, bands, bands_a, stream, table, f0, nf, L);
   else if (bh == 32)
-    launch_propagate_bh<32>(r, bands, stream, table, f0, nf, L);
+    launch_propagate_bh<32>(r, bands, bands_a, stream, table, f0, nf, L);
   else
-    launch_propagate_bh<16>(r, bands, stream, table, f0, nf, L);
+    launch_propagate_bh<16>(r, bands, bands_a, stream, table, f0, nf, L);
 }
 
 // ---------------------------------------------------------------- host plans
@@ -1170,9 +1227,42 @@ static ff_status run_batch(const ff_field_job* jobs, int n, const ff_match_param
   // watchdog for the propagation's inter-band waits: 2 s of the 100 MHz clock
   const uint64_t timeout = 200000000ull;
   int launch = 0;
+  auto sx_of = [](int i) { return ((i & 3) == 0 || (i & 3) == 3) ? 1 : -1; };
+  auto sy_of = [](int i) { return ((i & 3) == 0 || (i & 3) == 2) ? 1 : -1; };
+  auto bands_at = [&](int g0, int g1, int lv) {
+    int bands = 0;
+    for (int g = g0; g < g1; ++g) bands += (((recs[g].Hs + (1 << lv) - 1) >> lv) + bh - 1) / bh;
+    return bands;
+  };
+  // one launch per patch radius group
+  auto propagate = [&](PropLaunch L) {
+    prof_mark(FF_PROF_PROPAGATE, stream, true);
+    for (int g0 = 0; g0 < n;) {
+      int g1 = g0;
+      while (g1 < n && recs[g1].r == recs[g0].r) ++g1;
+      const int bands = bands_at(g0, g1, L.lev);
+      const int bands_a = L.pair == kPairCross ? bands_at(g0, g1, L.lev + 1) : bands;
+      L.tag = (uint32_t)(launch + 1);
+      L.ticket = tickets + launch;
+      launch_propagate(bh, recs[g0].r, bands, bands_a, stream, table, g0, g1 - g0, L);
+      ++launch;
+      g0 = g1;
+    }
+    prof_mark(FF_PROF_PROPAGATE, stream, false);
+  };
+  auto rsearch = [&](int lv, int step) {
+    prof_mark(FF_PROF_RANDOM_SEARCH, stream, true);
+    k_random_search<kLanesPt><<<dim3(rs_blocks(lv), n), 256, 0, stream>>>(table, lv, qshift, step, p->R);
+    prof_mark(FF_PROF_RANDOM_SEARCH, stream, false);
+  };
+  bool entered = false;   // this level's entry and first sweep ran in a cross-level pair
   for (int lev = k; lev >= 0; --lev) {
     cur_lev = lev;
-    if (lev < k) {
+    int i = 0;
+    if (entered) {
+      i = 1;
+      entered = false;
+    } else if (lev < k) {
       // one group of lanes per point of the coarser grid
       const unsigned gpts = (unsigned)(((size_t)pts(lev + 1) * kLanesPt + 255) / 256);
       prof_mark(FF_PROF_LEVEL_ENTRY, stream, true);
@@ -1181,52 +1271,35 @@ static ff_status run_batch(const ff_field_job* jobs, int n, const ff_match_param
       ++steps;
       if (stop()) return finish();
     }
-    auto sx_of = [](int i) { return ((i & 3) == 0 || (i & 3) == 3) ? 1 : -1; };
-    auto sy_of = [](int i) { return ((i & 3) == 0 || (i & 3) == 2) ? 1 : -1; };
-    // one launch per patch radius group; `L` names the launch's roles
-    auto propagate = [&](PropLaunch L) {
-      for (int g0 = 0; g0 < n;) {
-        int g1 = g0;
-        int bands = 0;
-        while (g1 < n && recs[g1].r == recs[g0].r) {
-          const int gh = (recs[g1].Hs + (1 << lev) - 1) >> lev;
-          bands += (gh + bh - 1) / bh;
-          ++g1;
-        }
-        L.tag = (uint32_t)(launch + 1);
-        L.ticket = tickets + launch;
-        launch_propagate(bh, recs[g0].r, bands, stream, table, g0, g1 - g0, L);
-        ++launch;
-        g0 = g1;
-      }
-    };
-    for (int i = 0; i < p->n_prop;) {
+    while (i < p->n_prop) {
       PropLaunch L{lev, qshift, sx_of(i), sy_of(i), 0, nullptr, status, timeout, 0, -1, p->R};
       if (pipe && i + 1 < p->n_prop && sx_of(i + 1) == sx_of(i)) {
-        // sweeps i and i + 1 as one pipelined launch with the random search
-        // between them; the search after sweep i + 1 follows on its own
-        L.pair = 1;
+        // sweeps i and i + 1 (opposite vertical directions) as one pipelined
+        // launch with the random search between them; the search after
+        // sweep i + 1 follows on its own
+        L.pair = kPairSame;
         L.rs = i < p->n_rs ? i : -1;
-        prof_mark(FF_PROF_PROPAGATE, stream, true);
         propagate(L);
-        prof_mark(FF_PROF_PROPAGATE, stream, false);
-        if (i + 1 < p->n_rs) {
-          prof_mark(FF_PROF_RANDOM_SEARCH, stream, true);
-          k_random_search<kLanesPt><<<dim3(rs_blocks(lev), n), 256, 0, stream>>>(table, lev, qshift, i + 1, p->R);
-          prof_mark(FF_PROF_RANDOM_SEARCH, stream, false);
-        }
+        if (i + 1 < p->n_rs) rsearch(lev, i + 1);
         i += 2;
         continue;
       }
-      prof_mark(FF_PROF_PROPAGATE, stream, true);
+      if (pipe && i == p->n_prop - 1 && i >= p->n_rs && lev > 0 && sx_of(0) == sx_of(i) && sy_of(0) == -sy_of(i)) {
+        // the level's last sweep (no search after it), the next level's
+        // entry and its first sweep as one pipelined launch
+        L.lev = lev - 1;
+        L.pair = kPairCross;
+        propagate(L);
+        if (p->n_rs > 0) rsearch(lev - 1, 0);
+        entered = true;
+        ++i;
+        continue;
+      }
       propagate(L);
-      prof_mark(FF_PROF_PROPAGATE, stream, false);
       ++steps;
       if (stop()) return finish();
       if (i < p->n_rs) {
-        prof_mark(FF_PROF_RANDOM_SEARCH, stream, true);
-        k_random_search<kLanesPt><<<dim3(rs_blocks(lev), n), 256, 0, stream>>>(table, lev, qshift, i, p->R);
-        prof_mark(FF_PROF_RANDOM_SEARCH, stream, false);
+        rsearch(lev, i);
         ++steps;
         if (stop()) return finish();
       }
