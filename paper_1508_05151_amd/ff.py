@@ -323,10 +323,13 @@ class BatchMatcher:
     `run` can be captured in a HIP graph (see `capture`)."""
 
     def __init__(self, shapes, channels=3, r=8, r2=6, k=3, subpel=4, eps=5, device="cuda", band_rows=16,
-                 use_kdtree=1):
+                 use_kdtree=1, pipeline=0):
         self.shapes = list(shapes)            # (W, H) per pair
         self.C, self.r, self.r2, self.k, self.Q, self.eps = channels, r, r2, k, subpel, eps
-        self.params = ff_default_params(k=k, band_rows=band_rows, use_kdtree=use_kdtree)
+        # a batch keeps the GPU full of bands: pipelined sweep pairs, which
+        # add workgroups to overlap a field's sweeps, are off unless asked for
+        # (autotune() times both)
+        self.params = ff_default_params(k=k, band_rows=band_rows, use_kdtree=use_kdtree, pipeline=pipeline)
         self.descs, self.blobs1, self.blobs2, self.out = [], [], [], []
         for (W, H) in self.shapes:
             d = ff_desc_init(W, H, channels, k, subpel, (r, r2) if r2 != r else (r,))

@@ -57,13 +57,15 @@ def _check_against_oracle(out, prs, seeds):
 
 
 def test_batch_equals_oracle_every_band_height(ff, batch_pairs):
+    """Every band height, with and without pipelined sweep pairs, gives the
+    oracle's bytes for every pair of the batch."""
     seeds = [11, 12, 13, 14]
     i1 = [_dev(p.img1) for p in batch_pairs]
     i2 = [_dev(p.img2) for p in batch_pairs]
     first = None
-    for bh in (16, 8, 32):
-        _say("batch band_rows", bh)
-        m = ff.BatchMatcher(SIZES, band_rows=bh)
+    for bh, pipe in ((16, 0), (8, 0), (32, 0), (16, 1), (8, 1), (32, 1)):
+        _say("batch band_rows", bh, "pipeline", pipe)
+        m = ff.BatchMatcher(SIZES, band_rows=bh, pipeline=pipe)
         out = m.run(i1, i2, seeds=seeds)
         torch.cuda.synchronize()
         assert m.status() == 0
