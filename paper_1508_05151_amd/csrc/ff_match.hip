@@ -330,24 +330,41 @@ __global__ __launch_bounds__(256) void k_random_search(const FieldRec* __restric
     const int sy = clampi((gy + yy - c.r) * c.n, 0, c.Hs - 1), sx = clampi((gx0 + xx - c.r) * c.n, 0, c.Ws - 1);
     stile[yy * TP + xx] = c.src[(size_t)sy * c.Ws + sx];
   }
+  int32_t* F = grid_flow(f, lev);
+  int32_t* C = grid_cost(f, lev, Gw * Gh);
+  const int py = gy * c.n;
+  // each point's candidate, once per point (one lane of the first wavefront
+  // per point: the Philox rounds are quarter-rate multiplies)
+  __shared__ int32_t s_fx[PTS], s_fy[PTS], s_c[PTS], s_ok[PTS];
+  if (threadIdx.x < PTS) {
+    const int gq = gx0 + threadIdx.x;
+    int ok = 0, fxq = 0, fyq = 0, cq = 0;
+    if (gq < Gw) {
+      const int32_t fl = F[gy * Gw + gq];
+      if (fl != kEmpty) {
+        const int pxq = gq * c.n;
+        const int rad = c.n * R * c.Q;
+        uint32_t u0, u1;
+        philox2((uint32_t)(py * c.Ws + pxq), (uint32_t)lev, (uint32_t)step, f.c3, f.k0, f.k1, u0, u1);
+        const uint64_t span = (uint64_t)(2 * rad + 1);
+        fxq = fx_of(fl) + (int)((u0 * span) >> 32) - rad;
+        fyq = fy_of(fl) + (int)((u1 * span) >> 32) - rad;
+        ok = centre_valid(c, pxq, py, fxq, fyq) ? 1 : 0;
+        cq = C[gy * Gw + gq];
+      }
+    }
+    s_fx[threadIdx.x] = fxq;
+    s_fy[threadIdx.x] = fyq;
+    s_c[threadIdx.x] = cq;
+    s_ok[threadIdx.x] = ok;
+  }
   __syncthreads();
   const int i = threadIdx.x / L, lane = threadIdx.x % L;
   const int gx = gx0 + i;
-  if (gx >= Gw) return;
+  if (gx >= Gw || !s_ok[i]) return;
   const int pid = gy * Gw + gx;
-  int32_t* F = grid_flow(f, lev);
-  int32_t* C = grid_cost(f, lev, Gw * Gh);
-  const int32_t fl = F[pid];
-  if (fl == kEmpty) return;
-  const int px = gx * c.n, py = gy * c.n;
-  const int rad = c.n * R * c.Q;
-  uint32_t u0, u1;
-  philox2((uint32_t)(py * c.Ws + px), (uint32_t)lev, (uint32_t)step, f.c3, f.k0, f.k1, u0, u1);
-  const uint64_t span = (uint64_t)(2 * rad + 1);
-  const int ox = (int)((u0 * span) >> 32) - rad;
-  const int oy = (int)((u1 * span) >> 32) - rad;
-  const int fx = fx_of(fl) + ox, fy = fy_of(fl) + oy;
-  if (!centre_valid(c, px, py, fx, fy)) return;
+  const int px = gx * c.n;
+  const int fx = s_fx[i], fy = s_fy[i];
   // the patch sum, source terms from the tile
   const int mx = px * c.Q + fx, my = py * c.Q + fy;
   const int Mx = mx >> c.qshift, My = my >> c.qshift;
@@ -375,7 +392,7 @@ __global__ __launch_bounds__(256) void k_random_search(const FieldRec* __restric
     }
   }
   const int32_t e = group_sum<L>(sum);
-  if (lane == 0 && e < C[pid]) {
+  if (lane == 0 && e < s_c[i]) {
     F[pid] = packf(fx, fy);
     C[pid] = e;
   }
@@ -504,25 +521,10 @@ __device__ __forceinline__ void publish_prog(int32_t* w, uint32_t tag, int cols)
   if (threadIdx.x == 0) st_coh(w, prog_word(tag, cols));
 }
 
-// The random search of one grid point by a group of L = 16 lanes, as in
-// k_random_search, with device-coherent flow/cost accesses and the source
-// patch read from the plane.
-__device__ __forceinline__ void rs_point(const FieldRec& f, const CostCtx& c, int lev, int step, int R, int gx, int gy,
-                                         int Gw, int Gh, int lane) {
-  const int pid = gy * Gw + gx;
-  int32_t* F = grid_flow(f, lev);
-  int32_t* C = grid_cost(f, lev, Gw * Gh);
-  const int32_t fl = ld_coh(F + pid), cst = ld_coh(C + pid);
-  if (fl == kEmpty) return;
-  const int px = gx * c.n, py = gy * c.n;
-  const int rad = c.n * R * c.Q;
-  uint32_t u0, u1;
-  philox2((uint32_t)(py * c.Ws + px), (uint32_t)lev, (uint32_t)step, f.c3, f.k0, f.k1, u0, u1);
-  const uint64_t span = (uint64_t)(2 * rad + 1);
-  const int ox = (int)((u0 * span) >> 32) - rad;
-  const int oy = (int)((u1 * span) >> 32) - rad;
-  const int fx = fx_of(fl) + ox, fy = fy_of(fl) + oy;
-  if (!centre_valid(c, px, py, fx, fy)) return;
+// Data term of candidate (fx, fy) at grid point (px, py) of level lev by a
+// group of 16 lanes (the sum is left in every lane of the group): whole rows
+// per lane at stride 1 when no column clamps, else the generic walk.
+__device__ __forceinline__ int32_t cand_cost(const CostCtx& c, int lev, int px, int py, int fx, int fy, int lane) {
   const int mx = px * c.Q + fx, my = py * c.Q + fy;
   const int Mx = mx >> c.qshift, My = my >> c.qshift;
   int32_t part;
@@ -535,42 +537,7 @@ __device__ __forceinline__ void rs_point(const FieldRec& f, const CostCtx& c, in
   } else {
     part = patch_partial(c, px, py, fx, fy, lane, 16);
   }
-  const int32_t e = group_sum<16>(part);
-  if (lane == 0 && e < cst) {
-    st_coh(F + pid, packf(fx, fy));
-    st_coh(C + pid, e);
-  }
-}
-
-// The level entry of one fine grid point by a group of 16 lanes, as in
-// k_level_entry, with device-coherent flow/cost accesses.
-__device__ __forceinline__ void entry_point(const FieldRec& f, const CostCtx& c, int lev, int gx, int gy, int Gw,
-                                            int Gh, int lane) {
-  int32_t fl = kEmpty, e = kInf;
-  if (!(gx & 1) && !(gy & 1)) {
-    const int Gwc = (f.Ws + 2 * c.n - 1) >> (lev + 1);
-    fl = ld_coh(grid_flow(f, lev + 1) + (size_t)(gy >> 1) * Gwc + (gx >> 1));
-    if (fl != kEmpty) {
-      const int px = gx * c.n, py = gy * c.n, fx = fx_of(fl), fy = fy_of(fl);
-      const int mx = px * c.Q + fx, my = py * c.Q + fy;
-      const int Mx = mx >> c.qshift, My = my >> c.qshift;
-      int32_t part;
-      if (lev == 0 && (c.r == 8 || c.r == 6) && px >= c.r && px + c.r < c.Ws && Mx >= c.r && Mx + c.r < c.Wd) {
-        const uint32_t* D2 = c.dst + (size_t)c.pw * (size_t)(((my & c.qmask) << c.qshift) + (mx & c.qmask));
-        g_u32* sb = (g_u32*)(c.src + (px - c.r));
-        g_u32* tb = (g_u32*)(D2 + (Mx - c.r));
-        part = c.r == 8 ? rows_sum_n1<17>(sb, c.Ws, py - 8, c.Hs - 1, tb, c.Wd, My - 8, c.Hd - 1, lane)
-                        : rows_sum_n1<13>(sb, c.Ws, py - 6, c.Hs - 1, tb, c.Wd, My - 6, c.Hd - 1, lane);
-      } else {
-        part = patch_partial(c, px, py, fx, fy, lane, 16);
-      }
-      e = group_sum<16>(part);
-    }
-  }
-  if (lane == 0) {
-    st_coh(grid_flow(f, lev) + (size_t)gy * Gw + gx, fl);
-    st_coh(grid_cost(f, lev, Gw * Gh) + (size_t)gy * Gw + gx, e);
-  }
+  return group_sum<16>(part);
 }
 
 // An X workgroup: rows kXRows m .. kXRows m + kXRows - 1 of band k of the
@@ -578,18 +545,25 @@ __device__ __forceinline__ void entry_point(const FieldRec& f, const CostCtx& c,
 // first sweep's bands (direction -syX, progress words progA) finish the
 // columns they need; publishes its progress in progX[k * BH / kXRows + m].
 // Same-level pair: random search step rs (< 0: none, progress is only passed
-// on), the first sweep on the same grid.  Cross-level pair: the level entry,
-// the first sweep on the grid of level lev + 1.
+// on), as in k_random_search, the first sweep on the same grid.  Cross-level
+// pair: the level entry, as in k_level_entry, the first sweep on the grid of
+// level lev + 1.  A chunk's candidates are formed one point per thread (flow
+// and cost loads, Philox) before the 16-lane groups cost them, so a point's
+// chain holds one memory round trip.
 template <int BH>
 __device__ __forceinline__ void x_worker(const FieldRec& fr, const CostCtx& c, int lev, bool cross, int k, int m,
                                          int sx, int syX, const int32_t* progA, int32_t* progX, int rs, int R,
                                          uint32_t tag, int32_t* status, uint64_t timeout) {
   constexpr int CH = kBatch;
+  __shared__ int32_t x_fx[kXRows * CH], x_fy[kXRows * CH], x_c[kXRows * CH], x_ok[kXRows * CH];
   const int n = c.n;
   const int Gw = (fr.Ws + n - 1) >> lev, Gh = (fr.Hs + n - 1) >> lev;
+  int32_t* const F = grid_flow(fr, lev);
+  int32_t* const C = grid_cost(fr, lev, Gw * Gh);
   // the first sweep's grid
   const int la = cross ? lev + 1 : lev;
   const int Gwa = (fr.Ws + (1 << la) - 1) >> la, Gha = (fr.Hs + (1 << la) - 1) >> la;
+  const int32_t* const Fa = grid_flow(fr, la);
   const int b0 = k * BH;
   const int v0 = b0 + m * kXRows;
   const int rows = min(kXRows, min(BH, Gh - b0) - m * kXRows);
@@ -616,11 +590,60 @@ __device__ __forceinline__ void x_worker(const FieldRec& fr, const CostCtx& c, i
       for (int b = blo; b <= bhi; ++b) wait_prog(progA + b, tag, need, status, timeout);
     __syncthreads();
     if (cross || rs >= 0) {
+      // candidates, one point per thread
+      for (int q = threadIdx.x; q < rows * cw; q += blockDim.x) {
+        const int v = v0 + q / cw, u = c0 + q % cw;
+        const int gx = sx > 0 ? u : Gw - 1 - u, gy = syX > 0 ? v : Gh - 1 - v;
+        const int px = gx * n, py = gy * n;
+        int ok = 0, fxq = 0, fyq = 0, cq = 0;
+        if (cross) {
+          // carried points keep the coarse flow; every other point is new
+          int32_t fl = kEmpty;
+          if (!(gx & 1) && !(gy & 1)) fl = ld_coh(Fa + (size_t)(gy >> 1) * Gwa + (gx >> 1));
+          if (fl != kEmpty) {
+            ok = 1;
+            fxq = fx_of(fl);
+            fyq = fy_of(fl);
+          } else {
+            st_coh(F + (size_t)gy * Gw + gx, kEmpty);
+            st_coh(C + (size_t)gy * Gw + gx, kInf);
+          }
+        } else {
+          const int32_t fl = ld_coh(F + (size_t)gy * Gw + gx);
+          if (fl != kEmpty) {
+            const int rad = n * R * c.Q;
+            uint32_t u0, u1;
+            philox2((uint32_t)(py * c.Ws + px), (uint32_t)lev, (uint32_t)rs, fr.c3, fr.k0, fr.k1, u0, u1);
+            const uint64_t span = (uint64_t)(2 * rad + 1);
+            fxq = fx_of(fl) + (int)((u0 * span) >> 32) - rad;
+            fyq = fy_of(fl) + (int)((u1 * span) >> 32) - rad;
+            ok = centre_valid(c, px, py, fxq, fyq) ? 1 : 0;
+            cq = ld_coh(C + (size_t)gy * Gw + gx);
+          }
+        }
+        x_fx[q] = fxq;
+        x_fy[q] = fyq;
+        x_c[q] = cq;
+        x_ok[q] = ok;
+      }
+      __syncthreads();
+      // their data terms, one group of 16 lanes per point
       for (int i = group; i < rows * cw; i += ngroups) {
+        if (!x_ok[i]) continue;
         const int v = v0 + i / cw, u = c0 + i % cw;
         const int gx = sx > 0 ? u : Gw - 1 - u, gy = syX > 0 ? v : Gh - 1 - v;
-        if (cross) entry_point(fr, c, lev, gx, gy, Gw, Gh, lane);
-        else rs_point(fr, c, lev, rs, R, gx, gy, Gw, Gh, lane);
+        const int fx = x_fx[i], fy = x_fy[i];
+        const int32_t e = cand_cost(c, lev, gx * n, gy * n, fx, fy, lane);
+        if (lane == 0) {
+          if (cross) {
+            // the level entry keeps the flow whatever its cost
+            st_coh(F + (size_t)gy * Gw + gx, packf(fx, fy));
+            st_coh(C + (size_t)gy * Gw + gx, e);
+          } else if (e < x_c[i]) {
+            st_coh(F + (size_t)gy * Gw + gx, packf(fx, fy));
+            st_coh(C + (size_t)gy * Gw + gx, e);
+          }
+        }
       }
     }
     publish_prog(pw, tag, c1);
