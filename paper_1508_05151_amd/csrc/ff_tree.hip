@@ -115,8 +115,11 @@ __global__ void k_tree_init(const FieldRec* __restrict__ table) {
 // (one 16-byte load), so a wavefront reads 8 full rows per instruction.
 constexpr int kLpr = 8;
 
-__device__ __forceinline__ int4 row_quad(const int32_t* V, int stride, int id, int j) {
-  return *reinterpret_cast<const int4*>(V + (size_t)id * stride + 4 * j);
+typedef int32_t v4i_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ v4i_t row_quad(const int32_t* V, int stride, int id, int j) {
+  // a global-memory load of a native vector (not a flat load, which would
+  // also count against the LDS counter)
+  return *(const __attribute__((address_space(1))) v4i_t*)(V + (size_t)id * stride + 4 * j);
 }
 
 // grid: (chunks, nodes at depth d, fields)
@@ -140,7 +143,7 @@ __global__ __launch_bounds__(kTpb) void k_tree_minmax(const FieldRec* __restrict
   if (on) {
 #pragma unroll 4
     for (int e = lo + g; e < hi; e += kTpb / kLpr) {
-      const int4 v = row_quad(t.V, t.stride, perm[start + e], q);
+      const v4i_t v = row_quad(t.V, t.stride, perm[start + e], q);
       mn[0] = min(mn[0], v.x); mx[0] = max(mx[0], v.x);
       mn[1] = min(mn[1], v.y); mx[1] = max(mx[1], v.y);
       mn[2] = min(mn[2], v.z); mx[2] = max(mx[2], v.z);
@@ -338,20 +341,56 @@ __device__ __forceinline__ void heap_range(int node, int N, int& start, int& cnt
   node_range(d, node + 1 - (1 << d), N, start, cnt);
 }
 
+// Bitonic sort of key[0, P) ascending (P a power of two, <= kTreeLds =
+// 4 kSubTpb).  Thread t holds the four consecutive keys 4t..4t+3 in
+// registers: a stage of stride j < 4 pairs keys of one thread, j < 256 keys
+// of one wavefront (shuffles), and only the strides j >= 256 go through LDS,
+// two barriers each.  Called by the whole workgroup; key[] must be settled
+// (a barrier after its last writes) before the call.
+static_assert(kTreeLds == 4 * kSubTpb, "four keys per thread");
+__device__ __forceinline__ uint64_t cas_keep(uint64_t mine, uint64_t other, int i, int j, int k) {
+  // compare-exchange of positions i and i ^ j in a sequence sorted up where
+  // (i & k) == 0: the lower position keeps the smaller key there
+  const bool up = (i & k) == 0, lower = (i & j) == 0;
+  const uint64_t lo = mine < other ? mine : other, hi = mine < other ? other : mine;
+  return lower == up ? lo : hi;
+}
+
 __device__ void bitonic_sort(uint64_t* key, int P) {
+  const int t = threadIdx.x;
+  uint64_t v[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) v[r] = key[4 * t + r];
   for (int k = 2; k <= P; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < P; i += kSubTpb) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const uint64_t a = key[i], b = key[ixj];
-          const bool up = (i & k) == 0;
-          if ((a > b) == up) { key[i] = b; key[ixj] = a; }
+      if (j >= 256) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) key[4 * t + r] = v[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 4 * t + r;
+          v[r] = cas_keep(v[r], key[i ^ j], i, j, k);
         }
+      } else if (j >= 4) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = cas_keep(v[r], __shfl_xor(v[r], j >> 2), 4 * t + r, j, k);
+      } else {
+        uint64_t w[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) w[r] = cas_keep(v[r], v[r ^ j], 4 * t + r, j, k);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = w[r];
       }
-      __syncthreads();
     }
   }
+  __syncthreads();
+  if (4 * t < P) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) key[4 * t + r] = v[r];
+  }
+  __syncthreads();
 }
 
 // grid: (2^maxTop, fields); block x finishes the subtree rooted at node x of
@@ -421,9 +460,9 @@ __global__ __launch_bounds__(kSubTpb) void k_tree_subtree(const FieldRec* __rest
         if (act && 4 * q < D) {
           const int c = s_cnt[s], st = s_start[s];
           const int a = st + c * part / gps, b = st + c * (part + 1) / gps;
-#pragma unroll 4
+#pragma unroll 8
           for (int e = a; e < b; ++e) {
-            const int4 v = row_quad(V, stride, (int)(key[e] & idmask), q);
+            const v4i_t v = row_quad(V, stride, (int)(key[e] & idmask), q);
             mn[0] = min(mn[0], v.x); mx[0] = max(mx[0], v.x);
             mn[1] = min(mn[1], v.y); mx[1] = max(mx[1], v.y);
             mn[2] = min(mn[2], v.z); mx[2] = max(mx[2], v.z);
