@@ -110,6 +110,10 @@ def main():
                     help="pair mode: skip the learned-proposal comparison")
     ap.add_argument("--learned-pairs", type=int, default=16,
                     help="pair mode: held-out 1024x436 pairs of the learned-proposal comparison")
+    ap.add_argument("--band-rows", type=int, default=16, choices=(8, 16, 32),
+                    help="pair mode: propagation band height (results are identical for every value)")
+    ap.add_argument("--pipeline", type=int, default=1, choices=(0, 1),
+                    help="pair mode: pipelined sweep pairs (results are identical)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this many MiB (the reference dispatch "
                          "for scaling hardware byte counters)")
@@ -151,7 +155,8 @@ def main():
     img1 = torch.from_numpy(pair.img1).to(dev)
     img2 = torch.from_numpy(pair.img2).to(dev)
     ff.ff_init()
-    m = ff.PairMatcher(W, H, C, r=r, r2=r2, k=k, subpel=Q, eps=eps)
+    m = ff.PairMatcher(W, H, C, r=r, r2=r2, k=k, subpel=Q, eps=eps, band_rows=args.band_rows,
+                       pipeline=args.pipeline)
     for _ in range(args.warmup):
         m.run(img1, img2, seed=1000)
     torch.cuda.synchronize()
@@ -215,7 +220,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "one 1024x436 RGB Sintel-shaped layered pair (seed 1000): descriptors x2, "
                                "F/B1/B2 fields with kd-trees, two-way consistency filter",
-                   "k": k, "r": r, "r2": r2, "R": 1, "leaf": 8, "subpel": Q, "eps": eps},
+                   "k": k, "r": r, "r2": r2, "R": 1, "leaf": 8, "subpel": Q, "eps": eps,
+                   "band_rows": args.band_rows, "pipelined_sweep_pairs": bool(args.pipeline)},
         "roofline": roof,
         "quality": {"F_inlier_rate_epe_lt_3px": round(rate, 4), "kept_fraction": round(keep, 4)},
     }
