@@ -56,7 +56,13 @@ CASES = [("square", lambda: pairs.square_pair(0), 3, (8, 6)),
          ("ragged97x61", lambda: _ragged_pair(5, 97, 61), 3, (8, 6)),
          ("gray75x50", lambda: _ragged_pair(6, 75, 50, C=1), 2, (5,)),
          ("tiny13x9", lambda: _ragged_pair(7, 13, 9), 1, (3,)),
-         ("k4_200x120", lambda: _ragged_pair(8, 200, 120, nlayers=3), 4, (8, 6))]
+         ("k4_200x120", lambda: _ragged_pair(8, 200, 120, nlayers=3), 4, (8, 6)),
+         # degenerate sizes: one pixel, one column, one row, and a 2x2 image
+         # whose every level step exceeds the image
+         ("1x1", lambda: _ragged_pair(9, 1, 1), 3, (8, 6)),
+         ("1x7", lambda: _ragged_pair(10, 1, 7), 2, (8, 6)),
+         ("9x1", lambda: _ragged_pair(11, 9, 1), 2, (8, 6)),
+         ("2x2", lambda: _ragged_pair(12, 2, 2), 3, (3,))]
 
 
 @pytest.mark.parametrize("name,make,k,radii", CASES, ids=[c[0] for c in CASES])

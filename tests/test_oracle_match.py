@@ -212,3 +212,32 @@ def test_seed_is_first_minimum_over_leaf():
                 costs.append((ffo.cost(d1, d2, k, r, gx, gy, fx, fy), ffo.pack(fx, fy)))
             best = min(costs, key=lambda t: t[0])  # min() keeps the first minimum
             assert Cf[gy, gx] == best[0] and F[gy, gx] == best[1]
+
+
+def test_data_term_is_local():
+    """Eq. 1 at n = 1 with the census of section 3.3 reads only the patch, one
+    census neighbour and one interpolation neighbour: the cost of a field's
+    flow at an interior pixel equals the cost computed on crops of both
+    images (margin r + 4) around the two patches, with the flow shifted by
+    the crops' offset."""
+    p = pairs.layered_pair(seed=8, W=96, H=72, nlayers=3)
+    r, k = 8, 2
+    o1, o2 = ffo.Desc(p.img1, k, Q, (r,)), ffo.Desc(p.img2, k, Q, (r,))
+    F, Cst = ffo.match_field(o1, o2, r, k=k, seed=1)
+    H, W = F.shape
+    dx, dy = ffo.unpack(F)
+    ys, xs = np.mgrid[0:H, 0:W]
+    mx, my = xs * Q + dx, ys * Q + dy
+    tx, ty = mx // Q, my // Q
+    mg = r + 4
+    inner = (F != ffo.pack(-32768, -32768)) & (xs >= mg) & (xs < W - mg) & (ys >= mg) & (ys < H - mg) & \
+        (tx >= mg) & (tx < W - mg) & (ty >= mg) & (ty < H - mg)
+    cand = np.flatnonzero(inner)
+    assert cand.size > 50
+    for idx in np.random.default_rng(1).choice(cand, size=12, replace=False):
+        y, x = divmod(int(idx), W)
+        cx, cy = int(tx.flat[idx]), int(ty.flat[idx])
+        d1 = ffo.Desc(np.ascontiguousarray(p.img1[y - mg:y + mg + 1, x - mg:x + mg + 1]), 0, Q, (r,))
+        d2 = ffo.Desc(np.ascontiguousarray(p.img2[cy - mg:cy + mg + 1, cx - mg:cx + mg + 1]), 0, Q, (r,))
+        e = ffo.cost(d1, d2, 0, r, mg, mg, int(dx.flat[idx]) + (x - cx) * Q, int(dy.flat[idx]) + (y - cy) * Q)
+        assert e == int(Cst.flat[idx])
