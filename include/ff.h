@@ -103,7 +103,10 @@ typedef struct {
                          columns that the first and the search have finished;
                          0: one launch per sweep and per search.  Results are
                          identical; max_steps >= 0 implies 0 */
-  int32_t reserved;   /* must be 0 */
+  int32_t watchdog_us; /* 0 (default): every wait of one workgroup on another
+                          gives up after 2 s and the call reports
+                          FF_ERR_DEVICE; > 0: that limit in microseconds
+                          (a tiny value forces the error path in tests) */
   uint64_t seed;      /* Philox key */
 } ff_match_params;
 

@@ -1088,7 +1088,7 @@ static ff_status check_params(const ff_desc* src, const ff_desc* dst, int radius
   if (p->field_id > 3) return FF_ERR_ARG;
   if (p->band_rows != 0 && p->band_rows != 8 && p->band_rows != 16 && p->band_rows != 32) return FF_ERR_ARG;
   if (p->pipeline != 0 && p->pipeline != 1) return FF_ERR_ARG;
-  if (p->reserved != 0) return FF_ERR_ARG;
+  if (p->watchdog_us < 0) return FF_ERR_ARG;
   if (p->use_kdtree) {
     if (p->leaf < 2 || p->leaf > kMaxLeaf) return FF_ERR_ARG;
     bool hs = false, hd = false;
@@ -1248,7 +1248,7 @@ static ff_status run_batch(const ff_field_job* jobs, int n, const ff_match_param
   ++steps;
   if (stop()) return finish();
   // watchdog for the propagation's inter-band waits: 2 s of the 100 MHz clock
-  const uint64_t timeout = 200000000ull;
+  const uint64_t timeout = p->watchdog_us > 0 ? (uint64_t)p->watchdog_us * 100u : 200000000ull;
   int launch = 0;
   auto sx_of = [](int i) { return ((i & 3) == 0 || (i & 3) == 3) ? 1 : -1; };
   auto sy_of = [](int i) { return ((i & 3) == 0 || (i & 3) == 2) ? 1 : -1; };

@@ -47,7 +47,7 @@ class ff_match_params(C.Structure):
     _fields_ = [("k", C.c_int32), ("R", C.c_int32), ("leaf", C.c_int32), ("n_prop", C.c_int32),
                 ("n_rs", C.c_int32), ("use_kdtree", C.c_int32), ("max_steps", C.c_int32),
                 ("field_id", C.c_uint32), ("pair_id", C.c_uint32), ("band_rows", C.c_int32),
-                ("pipeline", C.c_int32), ("reserved", C.c_int32), ("seed", C.c_uint64)]
+                ("pipeline", C.c_int32), ("watchdog_us", C.c_int32), ("seed", C.c_uint64)]
 
 
 class ff_field_job(C.Structure):

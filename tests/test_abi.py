@@ -65,13 +65,13 @@ def test_match_argument_checks_before_any_launch(ff):
     d = ff.ff_desc_init(64, 48, 3, 3, 4, (8,))
     p = ff.ff_default_params()
     assert (p.k, p.R, p.leaf, p.n_prop, p.n_rs, p.use_kdtree, p.max_steps) == (3, 1, 8, 4, 3, 1, -1)
-    assert (p.band_rows, p.pipeline, p.reserved) == (16, 1, 0)
+    assert (p.band_rows, p.pipeline, p.watchdog_us) == (16, 1, 0)
     assert ff.ff_match_workspace_bytes(d, d, 8, p) > 0
     L = ff.lib()
     # radius without WHT vectors, leaf out of range, k above the descriptors'
-    # pipeline flag 0/1 only, reserved word zero
+    # pipeline flag 0/1 only, watchdog not negative
     for r, kw in [(6, {}), (8, dict(leaf=1)), (8, dict(k=4)), (8, dict(n_rs=5)), (8, dict(field_id=4)),
-                  (8, dict(pipeline=2)), (8, dict(reserved=1))]:
+                  (8, dict(pipeline=2)), (8, dict(watchdog_us=-1))]:
         q = ff.ff_default_params(**kw)
         assert L.ff_match_workspace_bytes(C.byref(d), C.byref(d), r, C.byref(q)) == 0
     # null buffers are rejected before anything is enqueued

@@ -253,3 +253,27 @@ def test_pipelined_sweeps_equal_one_launch_per_stage(ff, band_rows):
         o1, o2 = ffo.Desc(p.img1, k, Q, (r,)), ffo.Desc(p.img2, k, Q, (r,))
         oF, oC = ffo.match_field(o1, o2, r, k=k, seed=21)
         assert np.array_equal(on[0], oF) and np.array_equal(on[1], oC)
+
+
+@pytest.mark.parametrize("pipeline", [0, 1])
+def test_watchdog_reports_device_error_then_recovers(ff, pipeline):
+    """Forced from the host: with a 1 us watchdog every wait of one band on
+    another (and, pipelined, on another role's progress) gives up at once, the
+    kernels still finish, and the call reports FF_ERR_DEVICE; the next call
+    with the default watchdog is bit-exact with the oracle again."""
+    p = pairs.square_pair(0)
+    k, r = 3, 8
+    _say("watchdog", pipeline)
+    d1, b1 = _gpu_desc(ff, p.img1, k, (r,))
+    d2, b2 = _gpu_desc(ff, p.img2, k, (r,))
+    prm = ff.ff_default_params(k=k, seed=5, pipeline=pipeline, watchdog_us=1)
+    ws = torch.empty(ff.ff_match_workspace_bytes(d1, d2, r, prm), dtype=torch.uint8, device="cuda")
+    F = torch.empty((d1.height, d1.width), dtype=torch.int32, device="cuda")
+    Cc = torch.empty_like(F)
+    ff.ff_match_field(d1, b1, d2, b2, r, prm, None, F, Cc, ws)
+    torch.cuda.synchronize()
+    assert ff.ff_read_status(ws) == -6
+    gF, gC = _gpu_field(ff, d1, b1, d2, b2, r, k=k, seed=5, pipeline=pipeline)
+    o1, o2 = ffo.Desc(p.img1, k, Q, (r,)), ffo.Desc(p.img2, k, Q, (r,))
+    oF, oC = ffo.match_field(o1, o2, r, k=k, seed=5)
+    assert np.array_equal(gF, oF) and np.array_equal(gC, oC)
