@@ -666,7 +666,10 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
   constexpr int L = kLanesProp, CH = kBatch;
   constexpr int NS = 4 + TAIL;   // term slots per lane
   static_assert(L == 16 && CH % 2 == 0 && CH % L == 0 && TAIL <= 4, "layout");
-  constexpr int kTileWords = (BH + 2 * kMaxRadius + 1) * ((kBatch + BH + 2 * kMaxRadius) | 1);
+  // rows run skewed: row i works on u = t - s(i), s(i) = i + i / 4 (one more
+  // step per wavefront), so the tile's left margin is BH + BH / 4 columns
+  constexpr int M = BH + BH / 4;
+  constexpr int kTileWords = (BH + 2 * kMaxRadius + 1) * ((kBatch + M + 2 * kMaxRadius) | 1);
   __shared__ int32_t s_band, s_field, s_role, s_sub;
   __shared__ int32_t bufF[2][BH], bufC[2][BH];
   __shared__ int32_t topF[2], topC[2];   // row 0's vertical candidate, by step parity
@@ -732,10 +735,12 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
   const int v0 = band * BH;
   if (v0 >= Gh) return;
   const int rows = min(BH, Gh - v0);
-  const int nsteps = Gw + rows - 1;
+  const int skew = row + (row >> 2);      // s(row): this row works on u = t - skew
+  const int skewLast = (rows - 1) + ((rows - 1) >> 2);
+  const int nsteps = Gw + skewLast;
   const int r = c.r, S = 2 * r + 1, Q = c.Q;
   const int TH = BH + 2 * r + 1;          // tile rows: v0-r-1 .. v0+BH-1+r
-  const int TW = (CH + BH + 2 * r) | 1;   // tile cols: tb-BH-r .. tb+CH-1+r; odd pitch (banks)
+  const int TW = (CH + M + 2 * r) | 1;    // tile cols: tb-M-r .. tb+CH-1+r; odd pitch (banks)
   const bool rowok = !pollWave && row < rows;
   const int rr = rowok ? row : rows - 1;  // inactive rows shadow a valid row
   const int gy = sy > 0 ? v0 + rr : Gh - 1 - (v0 + rr);
@@ -789,7 +794,7 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
     const int o = k < 4 ? offFull : tOff[k - 4 < TAIL ? k - 4 : 0];
     const int du = g < 2 ? o : (g == 2 ? -r - 1 : r);
     const int dv = g < 2 ? (g == 0 ? -r - 1 : r) : o;
-    stoff[k] = (r + 1 + dv) * TW + (BH + r + du);
+    stoff[k] = (r + 1 + dv) * TW + (M + r + du);
   }
   bool abandoned = false;
   auto wait_word = [&](int u, uint64_t w) -> uint64_t {
@@ -808,7 +813,7 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
     return w;
   };
   const uint32_t maxMx = (uint32_t)(Wm * Q), maxMy = (uint32_t)(Hm * Q);
-  // the polling wavefront: before the barrier that ends step col - 1, the
+  // the polling wavefront: before the barrier that ends step col - 2, the
   // band above's result at column col for row 0 (EMPTY without a band
   // above or past the row's end); `pw` holds the prefetched word for col
   uint64_t pw = above ? __hip_atomic_load(&xin[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
@@ -826,73 +831,79 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
       topC[col & 1] = cst;
     }
   };
-  // one step of the compute wavefronts
-  // The horizontal candidate of the next step is the row's own result, known
-  // before the barrier: its target geometry is prepared and its two full-slot
-  // words are loaded at the end of the step before, so those loads are in
-  // flight across the barrier (which waits for LDS operations only).
-  int32_t hFn = kEmpty, hCn = kInf;
-  int mxh = 0, myh = 0, Mxh = 0, Myh = 0;
-  uint32_t base2 = 0, base3 = 0, hb2 = 0, hb3 = 0;
-  auto prep_h = [&](int un, int32_t f, int32_t cst) {
+  // Both candidates of the next step are known at the end of a step: the
+  // horizontal one is the row's own result, the vertical one the result of
+  // the row above -- in this wavefront (moved down one 16-lane row by DPP),
+  // or, for a wavefront's first row, written to LDS by the wavefront above
+  // two steps earlier (the skew), or for row 0 handed over by the polling
+  // wavefront two steps ahead.  So every target word of the next step is
+  // loaded at the end of the step before and is in flight across the
+  // barrier (which waits for LDS operations only).
+  int32_t hFn = kEmpty, hCn = kInf, vFn = kEmpty, vCn = kInf;
+  int mxh = 0, myh = 0, mxv = 0, myv = 0;
+  uint32_t nb[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) nb[k] = 0;
+  auto prep = [&](int un, int32_t f, int32_t cst, int32_t vf, int32_t vc) {
     hFn = un > 0 ? f : kEmpty;
     hCn = un > 0 ? cst : kInf;
+    vFn = vf;
+    vCn = vc;
     const int pxn = gx_of(med3i(un, 0, Gw - 1)) * n;
     mxh = pxn * Q + fx_of(hFn);
     myh = py * Q + fy_of(hFn);
-    Mxh = mxh >> c.qshift;
-    Myh = myh >> c.qshift;
-    const uint32_t phh = dT + c.pw * (uint32_t)(((myh & c.qmask) << c.qshift) + (mxh & c.qmask));
-    base2 = phh + (uint32_t)med3i(Mxh - nsx * (r + 1), 0, Wm) * Hd;
-    base3 = phh + (uint32_t)med3i(Mxh + nsx * r, 0, Wm) * Hd;
-    const uint32_t yh = (uint32_t)med3i(Myh + oyFull, 0, Hm);
-    hb2 = tword(tgt, base2 + yh);
-    hb3 = tword(tgt, base3 + yh);
-  };
-  auto step = [&](int t, int tb) {
-    const int j = t - tb;
-    const int u = t - row;
-    const bool active = rowok && u >= 0 && u < Gw;
-    const int px = gx_of(med3i(u, 0, Gw - 1)) * n;
-    const int32_t curF0 = inF[row][j], curC0 = inC[row][j];
-    int32_t vF = row > 0 ? bufF[(t - 1) & 1][row - 1] : topF[t & 1];
-    int32_t vC = row > 0 ? bufC[(t - 1) & 1][row - 1] : topC[t & 1];
-    const int32_t hF = hFn, hC = hCn;
-    // candidate centres in 1/Q px; EMPTY (-32768, -32768) always falls
-    // outside, so the validity test also rejects empty candidates
-    const int mxv = px * Q + fx_of(vF), myv = py * Q + fy_of(vF);
-    const bool useV = active && vF != curF0 && (uint32_t)mxv <= maxMx && (uint32_t)myv <= maxMy;
-    const bool useH = active && hF != curF0 && (uint32_t)mxh <= maxMx && (uint32_t)myh <= maxMy;
+    mxv = pxn * Q + fx_of(vFn);
+    myv = py * Q + fy_of(vFn);
+    const int Mxh = mxh >> c.qshift, Myh = myh >> c.qshift;
     const int Mxv = mxv >> c.qshift, Myv = myv >> c.qshift;
+    const uint32_t phh = dT + c.pw * (uint32_t)(((myh & c.qmask) << c.qshift) + (mxh & c.qmask));
+    const uint32_t base2 = phh + (uint32_t)med3i(Mxh - nsx * (r + 1), 0, Wm) * Hd;
+    const uint32_t base3 = phh + (uint32_t)med3i(Mxh + nsx * r, 0, Wm) * Hd;
     const uint32_t phv = c.pw * (uint32_t)(((myv & c.qmask) << c.qshift) + (mxv & c.qmask));
     const uint32_t base0 = phv + (uint32_t)med3i(Myv - nsy * (r + 1), 0, Hm) * Wd;
     const uint32_t base1 = phv + (uint32_t)med3i(Myv + nsy * r, 0, Hm) * Wd;
     const uint32_t xv = (uint32_t)med3i(Mxv + oxFull, 0, Wm);
-    uint32_t bw[NS];
-    bw[0] = tword(tgt, base0 + xv);
-    bw[1] = tword(tgt, base1 + xv);
+    const uint32_t yh = (uint32_t)med3i(Myh + oyFull, 0, Hm);
+    nb[0] = tword(tgt, base0 + xv);
+    nb[1] = tword(tgt, base1 + xv);
+    nb[2] = tword(tgt, base2 + yh);
+    nb[3] = tword(tgt, base3 + yh);
 #pragma unroll
     for (int q = 0; q < TAIL; ++q) {
       const uint32_t xq = (uint32_t)med3i(Mxv + nsx * tOff[q], 0, Wm);
       const uint32_t yq = (uint32_t)med3i(Myh + nsy * tOff[q], 0, Hm);
       const uint32_t off = ((base0 + xq) & tM0[q]) | ((base1 + xq) & tM1[q]) | ((base2 + yq) & tM2[q]) |
                            ((base3 + yq) & tM3[q]);
-      bw[4 + q] = tword(tgt, off);
+      nb[4 + q] = tword(tgt, off);
     }
-    bw[2] = hb2;
-    bw[3] = hb3;
+  };
+  const bool waveFirst = (row & 3) == 0;
+  auto step = [&](int t, int tb) {
+    const int j = t - tb;
+    const int u = t - skew;
+    const bool active = rowok && u >= 0 && u < Gw;
+    const int32_t curF0 = inF[row][j], curC0 = inC[row][j];
+    // the next step's vertical candidate of a wavefront's first row: row 0
+    // from the polling wavefront, else the row above's result of step t - 1
+    const int32_t lvF = row == 0 ? topF[(t + 1) & 1] : bufF[(t - 1) & 1][row > 0 ? row - 1 : 0];
+    const int32_t lvC = row == 0 ? topC[(t + 1) & 1] : bufC[(t - 1) & 1][row > 0 ? row - 1 : 0];
+    const int32_t vF = vFn, vC = vCn, hF = hFn, hC = hCn;
+    // candidate centres in 1/Q px; EMPTY (-32768, -32768) always falls
+    // outside, so the validity test also rejects empty candidates
+    const bool useV = active && vF != curF0 && (uint32_t)mxv <= maxMx && (uint32_t)myv <= maxMy;
+    const bool useH = active && hF != curF0 && (uint32_t)mxh <= maxMx && (uint32_t)myh <= maxMy;
     const int tbase = row * TW + (u - tb);
     uint32_t aw[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) aw[k] = tile[tbase + stoff[k]];
     // entering minus leaving terms, vertical in the low half, horizontal in
     // the high half of one word (|sums| < 2^15)
-    int32_t packed = (int32_t)__popc((aw[1] ^ bw[1]) & fullMask) - (int32_t)__popc((aw[0] ^ bw[0]) & fullMask);
-    packed += (int32_t)((uint32_t)((int32_t)__popc((aw[3] ^ bw[3]) & fullMask) -
-                                   (int32_t)__popc((aw[2] ^ bw[2]) & fullMask)) << 16);
+    int32_t packed = (int32_t)__popc((aw[1] ^ nb[1]) & fullMask) - (int32_t)__popc((aw[0] ^ nb[0]) & fullMask);
+    packed += (int32_t)((uint32_t)((int32_t)__popc((aw[3] ^ nb[3]) & fullMask) -
+                                   (int32_t)__popc((aw[2] ^ nb[2]) & fullMask)) << 16);
 #pragma unroll
     for (int q = 0; q < TAIL; ++q) {
-      const int32_t pc = (int32_t)__popc((aw[4 + q] ^ bw[4 + q]) & tVal[q]);
+      const int32_t pc = (int32_t)__popc((aw[4 + q] ^ nb[4 + q]) & tVal[q]);
       packed += (int32_t)((uint32_t)((pc ^ tNeg[q]) - tNeg[q]) << tSh[q]);   // leaving groups negated
     }
     const int32_t sum = row16_sum(packed);
@@ -902,7 +913,11 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
     int32_t curF = curF0, curC = curC0;
     if (useV && vC + dvs < curC) { curF = vF; curC = vC + dvs; }
     if (useH && hC + dhs < curC) { curF = hF; curC = hC + dhs; }
-    prep_h(u + 1, curF, curC);   // the next step's horizontal candidate
+    // the next step's candidates: the row above's result moved down one row
+    // of 16 lanes (rows 1..3 of the wavefront), or the LDS value
+    const int32_t dF = __builtin_amdgcn_update_dpp(0, curF, 0x142, 0xE, 0xF, false);   // row_bcast:15
+    const int32_t dC = __builtin_amdgcn_update_dpp(0, curC, 0x142, 0xE, 0xF, false);
+    prep(u + 1, curF, curC, waveFirst ? lvF : dF, waveFirst ? lvC : dC);
     if (lane == 0) {
       bufF[t & 1][row] = curF;
       bufC[t & 1][row] = curC;
@@ -912,7 +927,6 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
         __hip_atomic_store(&xout[u], xch_pack(curF, curC, tag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   };
-  if (!pollWave) prep_h(-row, kEmpty, kInf);
   const int TT = TH * TW;
   constexpr int KPT = (kTileWords + BH * L - 1) / (BH * L);   // tile words per thread
   for (int tb = 0; tb < nsteps; tb += CH) {
@@ -924,13 +938,13 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
       __syncthreads();
     }
     // stage this batch's own flows and costs (row r at step tb + j works on
-    // u = tb + j - r) and the source tile: tile(y, x) is the source census
-    // at transformed grid (u, v) = (tb - BH - r + x, v0 - r - 1 + y),
+    // u = tb + j - s(r)) and the source tile: tile(y, x) is the source
+    // census at transformed grid (u, v) = (tb - M - r + x, v0 - r - 1 + y),
     // clamped to the image in pixels
 #pragma unroll
     for (int jj = 0; jj < CH / L; ++jj) {
       const int j = lane + jj * L;
-      const int u = tb + j - row;
+      const int u = tb + j - skew;
       if (rowok && u >= 0 && u < Gw) {
         if (coherent) {
           inF[row][j] = ld_coh(Frow + gx_of(u));
@@ -948,7 +962,7 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
       for (int k = 0; k < KPT; ++k) {
         const int e = min((int)threadIdx.x + k * BH * L, TT - 1);
         const int y = e / TW, x = e - y * TW;
-        const int gxp = gx_of(tb - BH - r + x) * n, gyp = gy_of(v0 - r - 1 + y) * n;
+        const int gxp = gx_of(tb - M - r + x) * n, gyp = gy_of(v0 - r - 1 + y) * n;
         tv[k] = c.src[(size_t)clampi(gyp, 0, c.Hs - 1) * c.Ws + clampi(gxp, 0, c.Ws - 1)];
       }
 #pragma unroll
@@ -958,11 +972,18 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
       }
     } else if (tb == 0) {
       provide(0);
+      provide(1);
     }
     __syncthreads();
+    if (tb == 0) {
+      // step 0's candidates (row 0's vertical one from the polling wavefront);
+      // a barrier before the polling wavefront reuses that LDS slot
+      if (!pollWave) prep(-skew, kEmpty, kInf, row == 0 ? topF[0] : kEmpty, row == 0 ? topC[0] : kInf);
+      lds_barrier();
+    }
     const int te = min(tb + CH, nsteps);
     for (int t = tb; t < te; ++t) {
-      if (pollWave) provide(t + 1);
+      if (pollWave) provide(t + 2);
       else step(t, tb);
       lds_barrier();
     }
@@ -970,7 +991,7 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
 #pragma unroll
     for (int jj = 0; jj < CH / L; ++jj) {
       const int j = lane + jj * L;
-      const int u = tb + j - row;
+      const int u = tb + j - skew;
       if (rowok && u >= 0 && u < Gw && tb + j < te) {
         if (coherent) {
           st_coh(Frow + gx_of(u), outF[row][j]);
@@ -981,8 +1002,8 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
         }
       }
     }
-    // after steps < te every row has finished columns u <= te - rows
-    if (pubProg) publish_prog(pubProg + band, tag, min(max(te - rows + 1, 0), Gw));
+    // after steps < te every row has finished columns u <= te - 1 - s(rows - 1)
+    if (pubProg) publish_prog(pubProg + band, tag, min(max(te - skewLast, 0), Gw));
   }
 }
 
