@@ -404,8 +404,12 @@ __global__ __launch_bounds__(256) void k_random_search(const FieldRec* __restric
 // the transformed coordinates u = sx > 0 ? gx : Gw-1-gx (same for v) every
 // sweep runs right and down.
 //
-// Step t of a band: row i handles u = t - i.  Rows hand results down through
-// a double-buffered LDS slot (one barrier per step).  The band's last row
+// Step t of a band: row i handles u = t - s(i), s(i) = i + i / 4 (each
+// wavefront of four rows one step behind the one above, so that every
+// candidate of a step is known, and its target words loaded, at the end of
+// the step before).  Rows hand results down inside a wavefront by DPP and
+// across wavefronts through a double-buffered LDS slot (one barrier per
+// step).  The band's last row
 // publishes each result as one 64-bit word (flow | cost | launch tag) with a
 // relaxed agent-scope store; row 0 of the band below polls that word until
 // the tag matches.  One single-copy-atomic word carries data and readiness,
@@ -433,7 +437,8 @@ __device__ __forceinline__ uint64_t xch_pack(int32_t f, int32_t cst, uint32_t ta
 // group is a per-lane constant.
 //
 // A step is written for a short instruction stream (one wavefront per SIMD,
-// so a step's latency is its instruction count plus one memory round trip):
+// so a step's latency is its instruction count plus what is left of one
+// memory round trip after the barrier and the step's LDS reads):
 // target words are read with 32-bit offsets from one scalar base (row-major
 // and transposed planes of a level lie in one blob), tail groups are chosen
 // with lane-constant masks, and the vertical and horizontal sums travel
@@ -443,8 +448,8 @@ constexpr int kBatch = 32;
 typedef __attribute__((address_space(1))) const char g_byte;
 
 // Workgroup barrier for LDS handoffs only: waits for this wavefront's LDS
-// operations, not for its outstanding global loads (the next step's
-// horizontal-candidate words stay in flight across it); the workgroup runs on
+// operations, not for its outstanding global loads (the next step's target
+// words stay in flight across it); the workgroup runs on
 // one CU, so completed LDS writes are visible to every wavefront after it.
 __device__ __forceinline__ void lds_barrier() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
