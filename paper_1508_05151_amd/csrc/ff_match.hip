@@ -325,22 +325,28 @@ __global__ __launch_bounds__(256) void k_random_search(const FieldRec* __restric
   // tile rows: S patch rows; pitch odd, so that the row-per-lane path's 16
   // lanes of a point fall in different banks
   const int S = 2 * c.r + 1, TWs = S - 1 + PTS, TP = TWs | 1;
+  int32_t* F = grid_flow(f, lev);
+  int32_t* C = grid_cost(f, lev, Gw * Gh);
+  const int py = gy * c.n;
+  // each point's flow and cost, loaded before the tile so that the two
+  // round trips overlap
+  const int gq = gx0 + (int)threadIdx.x;
+  int32_t fl = kEmpty, cq = 0;
+  if (threadIdx.x < PTS && gq < Gw) {
+    fl = F[gy * Gw + gq];
+    cq = C[gy * Gw + gq];
+  }
   for (int e = threadIdx.x; e < S * TWs; e += 256) {
     const int yy = e / TWs, xx = e - yy * TWs;
     const int sy = clampi((gy + yy - c.r) * c.n, 0, c.Hs - 1), sx = clampi((gx0 + xx - c.r) * c.n, 0, c.Ws - 1);
     stile[yy * TP + xx] = c.src[(size_t)sy * c.Ws + sx];
   }
-  int32_t* F = grid_flow(f, lev);
-  int32_t* C = grid_cost(f, lev, Gw * Gh);
-  const int py = gy * c.n;
   // each point's candidate, once per point (one lane of the first wavefront
   // per point: the Philox rounds are quarter-rate multiplies)
   __shared__ int32_t s_fx[PTS], s_fy[PTS], s_c[PTS], s_ok[PTS];
   if (threadIdx.x < PTS) {
-    const int gq = gx0 + threadIdx.x;
-    int ok = 0, fxq = 0, fyq = 0, cq = 0;
+    int ok = 0, fxq = 0, fyq = 0;
     if (gq < Gw) {
-      const int32_t fl = F[gy * Gw + gq];
       if (fl != kEmpty) {
         const int pxq = gq * c.n;
         const int rad = c.n * R * c.Q;
@@ -350,7 +356,6 @@ __global__ __launch_bounds__(256) void k_random_search(const FieldRec* __restric
         fxq = fx_of(fl) + (int)((u0 * span) >> 32) - rad;
         fyq = fy_of(fl) + (int)((u1 * span) >> 32) - rad;
         ok = centre_valid(c, pxq, py, fxq, fyq) ? 1 : 0;
-        cq = C[gy * Gw + gq];
       }
     }
     s_fx[threadIdx.x] = fxq;
