@@ -866,12 +866,14 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
     myv = py * Q + fy_of(vFn);
     const int Mxh = mxh >> c.qshift, Myh = myh >> c.qshift;
     const int Mxv = mxv >> c.qshift, Myv = myv >> c.qshift;
-    const uint32_t phh = dT + c.pw * (uint32_t)(((myh & c.qmask) << c.qshift) + (mxh & c.qmask));
-    const uint32_t base2 = phh + (uint32_t)med3i(Mxh - nsx * (r + 1), 0, Wm) * Hd;
-    const uint32_t base3 = phh + (uint32_t)med3i(Mxh + nsx * r, 0, Wm) * Hd;
-    const uint32_t phv = c.pw * (uint32_t)(((myv & c.qmask) << c.qshift) + (mxv & c.qmask));
-    const uint32_t base0 = phv + (uint32_t)med3i(Myv - nsy * (r + 1), 0, Hm) * Wd;
-    const uint32_t base1 = phv + (uint32_t)med3i(Myv + nsy * r, 0, Hm) * Wd;
+    // every product has both factors below 2^24 (plane words <= 2^22, phase
+    // < 64, coordinates and pitches < 8192): full-rate 24-bit multiplies
+    const uint32_t phh = dT + __umul24(c.pw, (uint32_t)(((myh & c.qmask) << c.qshift) + (mxh & c.qmask)));
+    const uint32_t base2 = phh + __umul24((uint32_t)med3i(Mxh - nsx * (r + 1), 0, Wm), Hd);
+    const uint32_t base3 = phh + __umul24((uint32_t)med3i(Mxh + nsx * r, 0, Wm), Hd);
+    const uint32_t phv = __umul24(c.pw, (uint32_t)(((myv & c.qmask) << c.qshift) + (mxv & c.qmask)));
+    const uint32_t base0 = phv + __umul24((uint32_t)med3i(Myv - nsy * (r + 1), 0, Hm), Wd);
+    const uint32_t base1 = phv + __umul24((uint32_t)med3i(Myv + nsy * r, 0, Hm), Wd);
     const uint32_t xv = (uint32_t)med3i(Mxv + oxFull, 0, Wm);
     const uint32_t yh = (uint32_t)med3i(Myh + oyFull, 0, Hm);
     nb[0] = tword(tgt, base0 + xv);
