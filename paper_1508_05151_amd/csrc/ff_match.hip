@@ -464,6 +464,13 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 __device__ __forceinline__ int med3i(int v, int lo, int hi) { return min(max(v, lo), hi); }
+// clamp to [0, hi] in one instruction (the compiler emits max then min when
+// the upper bound is not a constant); hi is uniform
+__device__ __forceinline__ uint32_t clamp0(int v, int hi) {
+  int r;
+  asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(v), "s"(hi));
+  return (uint32_t)r;
+}
 // target word at a 32-bit word offset from a uniform base: the byte offset is
 // formed in 32 bits so the load takes the scalar-base + 32-bit-offset form
 __device__ __forceinline__ uint32_t tword(g_byte* base, uint32_t w) {
@@ -777,7 +784,7 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
   const uint32_t fullMask = lane < S ? ~0u : 0u;
   const int oxFull = nsx * offFull, oyFull = nsy * offFull;
   int tOff[TAIL > 0 ? TAIL : 1], tGrp[TAIL > 0 ? TAIL : 1];
-  uint32_t tM0[TAIL > 0 ? TAIL : 1], tM1[TAIL > 0 ? TAIL : 1], tM2[TAIL > 0 ? TAIL : 1], tM3[TAIL > 0 ? TAIL : 1];
+  bool tG1[TAIL > 0 ? TAIL : 1], tG3[TAIL > 0 ? TAIL : 1], tH[TAIL > 0 ? TAIL : 1];
   uint32_t tVal[TAIL > 0 ? TAIL : 1], tSh[TAIL > 0 ? TAIL : 1];
   int32_t tNeg[TAIL > 0 ? TAIL : 1];
 #pragma unroll
@@ -789,10 +796,9 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
     const int g = ok ? g0 : 0;
     tGrp[q] = g;
     tOff[q] = 16 + (ok ? e % tl : 0) - r;
-    tM0[q] = g == 0 ? ~0u : 0u;
-    tM1[q] = g == 1 ? ~0u : 0u;
-    tM2[q] = g == 2 ? ~0u : 0u;
-    tM3[q] = g == 3 ? ~0u : 0u;
+    tG1[q] = g == 1;
+    tG3[q] = g == 3;
+    tH[q] = g >= 2;
     tVal[q] = ok ? ~0u : 0u;
     tNeg[q] = (g & 1) ? 0 : -1;
     tSh[q] = g >= 2 ? 16u : 0u;
@@ -854,39 +860,44 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
   uint32_t nb[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) nb[k] = 0;
-  auto prep = [&](int un, int32_t f, int32_t cst, int32_t vf, int32_t vc) {
-    hFn = un > 0 ? f : kEmpty;
-    hCn = un > 0 ? cst : kInf;
+  // pxq: the next column's x in 1/Q px (computed ahead, off the chain from
+  // a step's result to its successor's loads); hok: that column has a
+  // horizontal predecessor
+  const int nQshift = lev + c.qshift;   // n Q = 2^(lev + qshift)
+  auto pxq_of = [&](int un) { return gx_of(med3i(un, 0, Gw - 1)) << nQshift; };
+  auto prep = [&](int pxq, bool hok, int32_t f, int32_t cst, int32_t vf, int32_t vc) {
+    hFn = hok ? f : kEmpty;
+    hCn = hok ? cst : kInf;
     vFn = vf;
     vCn = vc;
-    const int pxn = gx_of(med3i(un, 0, Gw - 1)) * n;
-    mxh = pxn * Q + fx_of(hFn);
+    mxh = pxq + fx_of(hFn);
     myh = py * Q + fy_of(hFn);
-    mxv = pxn * Q + fx_of(vFn);
+    mxv = pxq + fx_of(vFn);
     myv = py * Q + fy_of(vFn);
     const int Mxh = mxh >> c.qshift, Myh = myh >> c.qshift;
     const int Mxv = mxv >> c.qshift, Myv = myv >> c.qshift;
     // every product has both factors below 2^24 (plane words <= 2^22, phase
     // < 64, coordinates and pitches < 8192): full-rate 24-bit multiplies
     const uint32_t phh = dT + __umul24(c.pw, (uint32_t)(((myh & c.qmask) << c.qshift) + (mxh & c.qmask)));
-    const uint32_t base2 = phh + __umul24((uint32_t)med3i(Mxh - nsx * (r + 1), 0, Wm), Hd);
-    const uint32_t base3 = phh + __umul24((uint32_t)med3i(Mxh + nsx * r, 0, Wm), Hd);
+    const uint32_t base2 = phh + __umul24(clamp0(Mxh - nsx * (r + 1), Wm), Hd);
+    const uint32_t base3 = phh + __umul24(clamp0(Mxh + nsx * r, Wm), Hd);
     const uint32_t phv = __umul24(c.pw, (uint32_t)(((myv & c.qmask) << c.qshift) + (mxv & c.qmask)));
-    const uint32_t base0 = phv + __umul24((uint32_t)med3i(Myv - nsy * (r + 1), 0, Hm), Wd);
-    const uint32_t base1 = phv + __umul24((uint32_t)med3i(Myv + nsy * r, 0, Hm), Wd);
-    const uint32_t xv = (uint32_t)med3i(Mxv + oxFull, 0, Wm);
-    const uint32_t yh = (uint32_t)med3i(Myh + oyFull, 0, Hm);
+    const uint32_t base0 = phv + __umul24(clamp0(Myv - nsy * (r + 1), Hm), Wd);
+    const uint32_t base1 = phv + __umul24(clamp0(Myv + nsy * r, Hm), Wd);
+    const uint32_t xv = clamp0(Mxv + oxFull, Wm);
+    const uint32_t yh = clamp0(Myh + oyFull, Hm);
     nb[0] = tword(tgt, base0 + xv);
     nb[1] = tword(tgt, base1 + xv);
     nb[2] = tword(tgt, base2 + yh);
     nb[3] = tword(tgt, base3 + yh);
 #pragma unroll
     for (int q = 0; q < TAIL; ++q) {
-      const uint32_t xq = (uint32_t)med3i(Mxv + nsx * tOff[q], 0, Wm);
-      const uint32_t yq = (uint32_t)med3i(Myh + nsy * tOff[q], 0, Hm);
-      const uint32_t off = ((base0 + xq) & tM0[q]) | ((base1 + xq) & tM1[q]) | ((base2 + yq) & tM2[q]) |
-                           ((base3 + yq) & tM3[q]);
-      nb[4 + q] = tword(tgt, off);
+      // the lane's group (a per-lane constant) picks the base and the free
+      // coordinate
+      const uint32_t xq = clamp0(Mxv + nsx * tOff[q], Wm);
+      const uint32_t yq = clamp0(Myh + nsy * tOff[q], Hm);
+      const uint32_t bv = tG1[q] ? base1 : base0, bh = tG3[q] ? base3 : base2;
+      nb[4 + q] = tword(tgt, (tH[q] ? bh : bv) + (tH[q] ? yq : xq));
     }
   };
   const bool waveFirst = (row & 3) == 0;
@@ -894,6 +905,7 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
     const int j = t - tb;
     const int u = t - skew;
     const bool active = rowok && u >= 0 && u < Gw;
+    const int pxq1 = pxq_of(u + 1);
     const int32_t curF0 = inF[row][j], curC0 = inC[row][j];
     // the next step's vertical candidate of a wavefront's first row: row 0
     // from the polling wavefront, else the row above's result of step t - 1
@@ -929,7 +941,7 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
     // of 16 lanes (rows 1..3 of the wavefront), or the LDS value
     const int32_t dF = __builtin_amdgcn_update_dpp(0, curF, 0x142, 0xE, 0xF, false);   // row_bcast:15
     const int32_t dC = __builtin_amdgcn_update_dpp(0, curC, 0x142, 0xE, 0xF, false);
-    prep(u + 1, curF, curC, waveFirst ? lvF : dF, waveFirst ? lvC : dC);
+    prep(pxq1, u >= 0, curF, curC, waveFirst ? lvF : dF, waveFirst ? lvC : dC);
     if (lane == 0) {
       bufF[t & 1][row] = curF;
       bufC[t & 1][row] = curC;
@@ -990,7 +1002,7 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
     if (tb == 0) {
       // step 0's candidates (row 0's vertical one from the polling wavefront);
       // a barrier before the polling wavefront reuses that LDS slot
-      if (!pollWave) prep(-skew, kEmpty, kInf, row == 0 ? topF[0] : kEmpty, row == 0 ? topC[0] : kInf);
+      if (!pollWave) prep(pxq_of(0), false, kEmpty, kInf, row == 0 ? topF[0] : kEmpty, row == 0 ? topC[0] : kInf);
       lds_barrier();
     }
     const int te = min(tb + CH, nsteps);
