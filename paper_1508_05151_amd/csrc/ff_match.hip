@@ -781,12 +781,11 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
   // validity; per tail slot its group (as selection masks), validity, sign
   // and half of the packed sum; every slot's tile offset
   const int offFull = lane - r;
-  const uint32_t fullMask = lane < S ? ~0u : 0u;
+  const uint32_t fullMask = TAIL > 0 || lane < S ? ~0u : 0u;
   const int oxFull = nsx * offFull, oyFull = nsy * offFull;
   int tOff[TAIL > 0 ? TAIL : 1], tGrp[TAIL > 0 ? TAIL : 1];
   bool tG1[TAIL > 0 ? TAIL : 1], tG3[TAIL > 0 ? TAIL : 1], tH[TAIL > 0 ? TAIL : 1];
-  uint32_t tVal[TAIL > 0 ? TAIL : 1], tSh[TAIL > 0 ? TAIL : 1];
-  int32_t tNeg[TAIL > 0 ? TAIL : 1];
+  int32_t tMul[TAIL > 0 ? TAIL : 1];
 #pragma unroll
   for (int q = 0; q < TAIL; ++q) {
     const int tl = S - 16;                   // remaining offsets per group
@@ -799,9 +798,7 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
     tG1[q] = g == 1;
     tG3[q] = g == 3;
     tH[q] = g >= 2;
-    tVal[q] = ok ? ~0u : 0u;
-    tNeg[q] = (g & 1) ? 0 : -1;
-    tSh[q] = g >= 2 ? 16u : 0u;
+    tMul[q] = ok ? ((g & 1) ? 1 : -1) * (g >= 2 ? 65536 : 1) : 0;
   }
   int stoff[NS];
 #pragma unroll
@@ -927,8 +924,7 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
                                    (int32_t)__popc((aw[2] ^ nb[2]) & fullMask)) << 16);
 #pragma unroll
     for (int q = 0; q < TAIL; ++q) {
-      const int32_t pc = (int32_t)__popc((aw[4 + q] ^ nb[4 + q]) & tVal[q]);
-      packed += (int32_t)((uint32_t)((pc ^ tNeg[q]) - tNeg[q]) << tSh[q]);   // leaving groups negated
+      packed += __mul24((int32_t)__popc(aw[4 + q] ^ nb[4 + q]), tMul[q]);
     }
     const int32_t sum = row16_sum(packed);
     const int32_t dvs = (int32_t)(int16_t)(uint16_t)((uint32_t)sum & 0xFFFFu);
