@@ -944,7 +944,10 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
       outF[row][j] = curF;
       outC[row][j] = curC;
       if (publish && active)
-        __hip_atomic_store(&xout[u], xch_pack(curF, curC, tag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // a global (not flat) store: a pending flat access would make every
+        // later wait for the target loads a wait for all loads
+        __hip_atomic_store((__attribute__((address_space(1))) uint64_t*)(xout + u), xch_pack(curF, curC, tag),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   };
   const int TT = TH * TW;
