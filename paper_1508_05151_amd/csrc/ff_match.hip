@@ -93,8 +93,9 @@ __device__ __forceinline__ void philox2(uint32_t c0, uint32_t c1, uint32_t c2, u
 // agent-scope load: it skips the vector L1, whose miss path costs more than a
 // direct L2 access for these scattered, rarely reused census words
 __device__ __forceinline__ uint32_t ld32(const uint32_t* base, uint32_t idx) {
-  return __hip_atomic_load(reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(base) + (idx << 2)),
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  typedef __attribute__((address_space(1))) const uint32_t g_u32c;
+  return __hip_atomic_load((g_u32c*)(reinterpret_cast<const char*>(base) + (idx << 2)), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ bool centre_valid(const CostCtx& c, int px, int py, int fx, int fy) {
@@ -503,11 +504,18 @@ constexpr int kRoleA = 0, kRoleX = 1, kRoleB = 2;
 constexpr int kXRows = 4;
 constexpr int kPairSame = 1, kPairCross = 2;
 
+// global-address-space accesses throughout: a flat access also counts as an
+// LDS operation and, while pending, turns a wait for some loads into a wait
+// for all of them
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gp(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
 __device__ __forceinline__ int32_t ld_coh(const int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(gp(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_coh(int32_t* p, int32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ int32_t prog_word(uint32_t tag, int cols) {
   return (int32_t)(((tag & 0xFFFu) << 20) | (uint32_t)cols);
@@ -944,10 +952,7 @@ __global__ __launch_bounds__(BH * kLanesProp + 64) void k_propagate(const FieldR
       outF[row][j] = curF;
       outC[row][j] = curC;
       if (publish && active)
-        // a global (not flat) store: a pending flat access would make every
-        // later wait for the target loads a wait for all loads
-        __hip_atomic_store((__attribute__((address_space(1))) uint64_t*)(xout + u), xch_pack(curF, curC, tag),
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(gp(xout + u), xch_pack(curF, curC, tag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   };
   const int TT = TH * TW;
