@@ -32,7 +32,7 @@ INT_PEAK_TOPS = CUS * LANES_PER_CU * CLOCK_GHZ / 1000.0   # 32-bit integer VALU 
 # from FETCH_SIZE and WRITE_SIZE counter runs scaled by a plain-copy
 # calibration; profiles/hotpath_1024x436_hbm_counters.md holds the runs.
 # Valid for the current k_propagate only.
-PROPAGATE_HBM_BYTES_PER_LAUNCH = 68.36e6
+PROPAGATE_HBM_BYTES_PER_LAUNCH = 68.47e6
 
 PROF_CLASS = {"descriptors": 1, "tree": 2, "seed": 3, "level_entry": 4, "propagate": 5, "random_search": 6,
               "filter": 7}
