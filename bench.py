@@ -119,7 +119,7 @@ def main():
                          "for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: each pair is matched on one MI355X; "
+        print(json.dumps({"error": "the matcher runs on one GPU: each pair is matched on one MI355X; "
                                    "--gpus must be 1"}), flush=True)
         sys.exit(2)
 
