@@ -271,6 +271,9 @@ const char* ff_status_string(ff_status s);
  * events (host allocation: call it outside any capture or timed loop);
  * ff_profile_end waits for them, returns the summed elapsed milliseconds and
  * the number of launches, destroys the events and disarms the hook.
+ * Errors: FF_ERR_ARG for a class outside 1..9, max_launches outside
+ * 1..2^20 or null outputs; FF_ERR_HIP if creating, recording, waiting for or
+ * timing an event failed (ff_profile_end still disarms the hook).
  */
 typedef enum {
   FF_PROF_DESCRIPTORS = 1,   /* the whole ff_compute_descriptors sequence */
