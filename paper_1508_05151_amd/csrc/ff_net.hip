@@ -285,7 +285,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__
       for (int i = 0; i < 8; ++i) sX[tap][8 * q + i][px] = (uint16_t)(w[i >> 1] >> (16 * (i & 1)));
     }
     __syncthreads();
-    if (threadIdx.x < coutp)
+    if ((int)threadIdx.x < coutp)
       for (int px = 0; px < 64; ++px) bsum += bf2f(sG[threadIdx.x][px]);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__
           pc[((size_t)tap * 32 + co) * 32 + ci] = (mt < MT && nt < NTt) ? acc[ti][mt][nt][i] : 0.f;
         }
   }
-  if (threadIdx.x < 32) partb[(size_t)blockIdx.x * 32 + threadIdx.x] = threadIdx.x < coutp ? bsum : 0.f;
+  if (threadIdx.x < 32) partb[(size_t)blockIdx.x * 32 + threadIdx.x] = (int)threadIdx.x < coutp ? bsum : 0.f;
 }
 
 // fixed-order reduction of the partials into the parameter-layout gradient
@@ -383,7 +383,7 @@ __global__ void k_loss_grad(const float* __restrict__ out, const int32_t* __rest
   red[threadIdx.x] = ls;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
   if (threadIdx.x == 0) lpart[blockIdx.x] = red[0] * inv_n;

@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kTpb) void k_tree_minmax(const FieldRec* __restrict
   }
   __syncthreads();
   const int node = (1 << d) - 1 + j;
-  if (threadIdx.x < t.D) {
+  if ((int)threadIdx.x < t.D) {
     atomicMin(&t.mm[((size_t)node * 32 + threadIdx.x) * 2], smin[threadIdx.x]);
     atomicMax(&t.mm[((size_t)node * 32 + threadIdx.x) * 2 + 1], smax[threadIdx.x]);
   }
@@ -201,7 +201,7 @@ __device__ void select_state(const int32_t* __restrict__ hist, int node, int pas
     __syncthreads();
     // inclusive scan over the block (Hillis-Steele)
     for (int o = 1; o < kTpb; o <<= 1) {
-      const int32_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+      const int32_t v = (int)threadIdx.x >= o ? part[threadIdx.x - o] : 0;
       __syncthreads();
       part[threadIdx.x] += v;
       __syncthreads();
@@ -303,8 +303,8 @@ __global__ __launch_bounds__(kTpb) void k_tree_partition(const FieldRec* __restr
   sr[threadIdx.x] = nv - nl;
   __syncthreads();
   for (int o = 1; o < kTpb; o <<= 1) {
-    const int32_t a = threadIdx.x >= o ? sl[threadIdx.x - o] : 0;
-    const int32_t b = threadIdx.x >= o ? sr[threadIdx.x - o] : 0;
+    const int32_t a = (int)threadIdx.x >= o ? sl[threadIdx.x - o] : 0;
+    const int32_t b = (int)threadIdx.x >= o ? sr[threadIdx.x - o] : 0;
     __syncthreads();
     sl[threadIdx.x] += a;
     sr[threadIdx.x] += b;
