@@ -249,7 +249,10 @@ class PairMatcher:
     """The whole hot path for one image pair on three streams: descriptors of
     both images, F = I1 -> I2 (r), B1 = I2 -> I1 (r), B2 = I2 -> I1 (r2), then
     the two-way consistency filter (sections 3.1-3.4).  Buffers are allocated
-    once for a given image size and reused."""
+    once for a given image size and reused.  run() works on the caller's
+    current stream plus three field streams: call it on the default stream,
+    or capture it in a HIP graph; a fifth stream of the caller's would share
+    one of HIP's four hardware queues with a field and serialise behind it."""
 
     def __init__(self, width, height, channels=3, r=8, r2=6, k=3, subpel=4, eps=5, n_bwd=2, device="cuda",
                  **params):
