@@ -1,7 +1,7 @@
 """GPU parity of batched matching (many pairs of mixed sizes, every stage one
 launch for all fields): each pair equals the oracle and the one-pair path byte
 for byte, for every propagation band height, eagerly and replayed from a HIP
-graph."""
+graph; the one-pair path replayed from a HIP graph equals its eager run."""
 import sys
 
 import numpy as np
@@ -130,3 +130,34 @@ def test_batch_graph_replays(ff, batch_pairs):
                     assert np.array_equal(a[key][0], b[key][0]) and np.array_equal(a[key][1], b[key][1]), key
                 else:
                     assert np.array_equal(a[key], b[key]), key
+
+
+def test_pair_graph_replays(ff, batch_pairs):
+    """The one-pair path (three field streams forked from and joined back to
+    the caller's stream by events) captured in one HIP graph: every replay,
+    with eager runs and scribbled outputs between replays, equals the eager
+    result byte for byte."""
+    p = batch_pairs[1]
+    W, H = SIZES[1]
+    i1, i2 = _dev(p.img1), _dev(p.img2)
+    m = ff.PairMatcher(W, H, 3, r=8, r2=6, k=3, subpel=Q, eps=5)
+    out = m.run(i1, i2, seed=31)
+    torch.cuda.synchronize()
+    eager = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        gout = m.run(i1, i2, seed=31)
+    for rep in range(3):
+        _say("pair graph replay", rep)
+        for key in ("F", "B1", "B2", "filtered"):
+            gout[key].fill_(7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert m.status() == [0, 0, 0]
+        for key, v in eager.items():
+            assert np.array_equal(gout[key].cpu().numpy(), v), (rep, key)
+        m.run(i1, i2, seed=5)   # eager work of its own between replays
+        torch.cuda.synchronize()
