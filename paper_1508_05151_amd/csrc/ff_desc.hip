@@ -411,6 +411,14 @@ ff_status ff_desc_init(ff_desc* d, const ff_image* img, int32_t k, int32_t subpe
   d->off_wht = off;
   off = align_up(off + (size_t)n_radii * N * d->wht_stride * 4, 256);
   d->bytes = off;
+  // the propagation sweep reads the row-major and the transposed census
+  // planes of a level from one base with 32-bit byte offsets: its largest
+  // word index, (census region words) + Q^2 N - 1, must stay below 2^30
+  // (reached only at Q = 8 with k >= 2 on large images)
+  if ((d->off_census_t - d->off_census) / 4 + (size_t)subpel * subpel * N > ((size_t)1 << 30)) {
+    *d = ff_desc{};
+    return FF_ERR_SIZE;
+  }
   return FF_OK;
 }
 

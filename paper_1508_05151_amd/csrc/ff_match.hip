@@ -89,15 +89,6 @@ __device__ __forceinline__ void philox2(uint32_t c0, uint32_t c1, uint32_t c2, u
   o1 = c1;
 }
 
-// 32-bit word load at a 32-bit word index (index < 2^30), as a relaxed
-// agent-scope load: it skips the vector L1, whose miss path costs more than a
-// direct L2 access for these scattered, rarely reused census words
-__device__ __forceinline__ uint32_t ld32(const uint32_t* base, uint32_t idx) {
-  typedef __attribute__((address_space(1))) const uint32_t g_u32c;
-  return __hip_atomic_load((g_u32c*)(reinterpret_cast<const char*>(base) + (idx << 2)), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __device__ __forceinline__ bool centre_valid(const CostCtx& c, int px, int py, int fx, int fy) {
   const int mx = px * c.Q + fx, my = py * c.Q + fy;
   return mx >= 0 && my >= 0 && mx <= (c.Wd - 1) * c.Q && my <= (c.Hd - 1) * c.Q;
@@ -474,6 +465,7 @@ __device__ __forceinline__ uint32_t clamp0(int v, int hi) {
 }
 // target word at a 32-bit word offset from a uniform base: the byte offset is
 // formed in 32 bits so the load takes the scalar-base + 32-bit-offset form
+// (ff_desc_init refuses layouts whose largest offset would not fit)
 __device__ __forceinline__ uint32_t tword(g_byte* base, uint32_t w) {
   return *reinterpret_cast<__attribute__((address_space(1))) const uint32_t*>(base + (w << 2));
 }

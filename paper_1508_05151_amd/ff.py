@@ -167,15 +167,46 @@ def ff_match_workspace_bytes(src: ff_desc, dst: ff_desc, radius: int, p: ff_matc
     return n
 
 
+def _check_i32(t, numel, what):
+    """A buffer handed to the library as a plain pointer: it must be a
+    contiguous int32 device tensor of exactly `numel` elements (the kernels
+    index it by the image or grid size and cannot check it themselves)."""
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.int32 or not t.is_contiguous():
+        raise FFError(-1, f"{what}: expected a contiguous int32 tensor")
+    if t.numel() != numel:
+        raise FFError(-1, f"{what}: {t.numel()} elements, the call needs {numel}")
+    if not t.is_cuda:
+        raise FFError(-1, f"{what}: expected a device (CUDA) tensor")
+
+
+def check_proposal(proposal, src: ff_desc, k: int):
+    """A proposal holds one packed flow per point of the coarsest grid of a
+    k-level match over src: ceil(H / 2^k) x ceil(W / 2^k)."""
+    if proposal is None:
+        return
+    hc, wc = seed_grid(src.width, src.height, k)
+    if isinstance(proposal, torch.Tensor) and proposal.dim() >= 2 and tuple(proposal.shape[-2:]) != (hc, wc):
+        raise FFError(-1, f"proposal: shape {tuple(proposal.shape)}, the seed grid is {(hc, wc)}")
+    _check_i32(proposal, hc * wc, "proposal")
+
+
 def ff_match_field(src: ff_desc, src_blob, dst: ff_desc, dst_blob, radius: int, p: ff_match_params, proposal,
                    flow, cost, workspace, stream=None):
+    check_proposal(proposal, src, p.k)
+    _check_i32(flow, src.width * src.height, "flow")
+    _check_i32(cost, src.width * src.height, "cost")
     _check(lib().ff_match_field(C.byref(src), _ptr(src_blob), C.byref(dst), _ptr(dst_blob), radius, C.byref(p),
                                 _ptr(proposal), _ptr(flow), _ptr(cost), _ptr(workspace), workspace.numel(),
                                 _stream(stream)), "ff_match_field")
 
 
 def make_job(src: ff_desc, src_blob, dst: ff_desc, dst_blob, radius, flow, cost, field_id=0, pair_id=0, seed=0,
-             proposal=None) -> ff_field_job:
+             proposal=None, k=3) -> ff_field_job:
+    """One field of a batched call; k is the batch's hierarchy depth (the
+    proposal must cover its seed grid)."""
+    check_proposal(proposal, src, k)
+    _check_i32(flow, src.width * src.height, "flow")
+    _check_i32(cost, src.width * src.height, "cost")
     j = ff_field_job()
     j.src = C.pointer(src)
     j.src_blob = src_blob.data_ptr()
@@ -365,7 +396,7 @@ class BatchMatcher:
                                                     ("B1", self.r, 1, (d, self.blobs2[i], d, self.blobs1[i])),
                                                     ("B2", self.r2, 2, (d, self.blobs2[i], d, self.blobs1[i]))):
                 jobs.append(make_job(s, sb, t, tb, rad, o[name][0], o[name][1], field_id=fid, pair_id=i,
-                                     seed=self.seeds[i], proposal=self._proposal(i, name)))
+                                     seed=self.seeds[i], proposal=self._proposal(i, name), k=self.k))
         return jobs
 
     def run(self, imgs1, imgs2, seeds=None, proposals=None, stream=None):

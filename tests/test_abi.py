@@ -111,3 +111,61 @@ def test_batch_entry_points_validate(ff):
     jobs[0].radius = 8
     assert L.ff_match_batch(jobs, 1, C.byref(p), None, 0, None) == -1
     assert L.ff_match_batch(jobs, 0, C.byref(p), None, 0, None) == -1
+
+
+def test_desc_init_refuses_layouts_beyond_the_sweeps_32bit_offsets(ff):
+    """The sweep addresses the row-major and transposed census planes of a
+    level from one base with 32-bit byte offsets; its largest word index is
+    (census region words) + Q^2 N - 1, which must stay below 2^30.  At Q = 8
+    that caps the image: k = 3 allows (k + 2) 64 N <= 2^30, N <= 3,355,443."""
+    with pytest.raises(ff.FFError) as e:
+        ff.ff_desc_init(4095, 1024, 3, 3, 8, (8, 6))
+    assert e.value.code == -2
+    with pytest.raises(ff.FFError) as e:
+        ff.ff_desc_init(4095, 1024, 3, 4, 8, (8,))
+    assert e.value.code == -2
+    for (W, H, k, q) in [(4095, 818, 3, 8), (4095, 1024, 2, 8), (4095, 1024, 1, 8), (4096, 1024, 4, 4),
+                         (8191, 512, 3, 4)]:
+        d = ff.ff_desc_init(W, H, 3, k, q, (8, 6))
+        words = (d.off_census_t - d.off_census) // 4 + q * q * W * H
+        assert words <= 1 << 30, (W, H, k, q)
+    # every accepted (size, k, Q) keeps the bound; every refused one breaks it
+    for (W, H) in [(4095, 819), (4095, 820), (3000, 1200), (2048, 2048), (4095, 1024)]:
+        for k in range(5):
+            try:
+                d = ff.ff_desc_init(W, H, 3, k, 8, (8,))
+            except ff.FFError as err:
+                assert err.code == -2
+                assert (k + 2) * 64 * W * H > 1 << 30, (W, H, k)
+                continue
+            assert (d.off_census_t - d.off_census) // 4 + 64 * W * H <= 1 << 30
+
+
+def test_binding_checks_proposal_and_outputs_before_any_launch(ff):
+    """The seed step reads proposal[gy * Gw + gx] over the k-level seed grid
+    and the outputs over the whole source image, through plain pointers: the
+    binding refuses a buffer of the wrong type, size or shape (or a host
+    tensor) before anything reaches the library."""
+    import torch
+    d = ff.ff_desc_init(64, 48, 3, 3, 4, (8,))
+    p = ff.ff_default_params()
+    ok_flow = torch.empty((48, 64), dtype=torch.int32)
+    cases = [
+        (torch.zeros((6, 8), dtype=torch.int32), "device"),          # right shape, host memory
+        (torch.zeros((12, 16), dtype=torch.int32), "seed grid"),     # the k = 2 grid
+        (torch.zeros((6, 9), dtype=torch.int32), "seed grid"),
+        (torch.zeros((48,), dtype=torch.int32), "device"),           # flat, right size
+        (torch.zeros((47,), dtype=torch.int32), "elements"),
+        (torch.zeros((6, 8), dtype=torch.int64), "int32"),
+        (torch.zeros((8, 6), dtype=torch.int32).t(), "contiguous"),
+    ]
+    for prop, msg in cases:
+        with pytest.raises(ff.FFError, match=msg):
+            ff.ff_match_field(d, None, d, None, 8, p, prop, ok_flow, ok_flow, None)
+        with pytest.raises(ff.FFError, match=msg):
+            ff.make_job(d, None, d, None, 8, ok_flow, ok_flow, proposal=prop, k=3)
+    with pytest.raises(ff.FFError, match="elements"):
+        ff.ff_match_field(d, None, d, None, 8, p, None, torch.empty((48, 63), dtype=torch.int32), ok_flow, None)
+    # a k = 2 batch needs the 12 x 16 grid
+    with pytest.raises(ff.FFError, match="device"):
+        ff.make_job(d, None, d, None, 8, ok_flow, ok_flow, proposal=torch.zeros((12, 16), dtype=torch.int32), k=2)

@@ -1,7 +1,10 @@
-"""Maximum size: an 8191 x 512 RGB pair (the largest width the descriptors
-accept at Q = 4, and 4,193,792 of the 2^22 points they allow) through the
-benchmark's launch configuration.  The oracle cannot match fields this size
-in test time, so the test checks what holds point by point:
+"""Maximum sizes: an 8191 x 512 RGB pair (the largest width the descriptors
+accept at Q = 4, and 4,193,792 of the 2^22 points they allow), and a
+4095 x 818 RGB pair at Q = 8, k = 3 (within 0.2 % of the largest image the
+sweep can address with 32-bit offsets at that Q and k: its largest target
+word index is 2^30 - 1,834,625), through the benchmark's launch
+configuration.  The oracle cannot match fields this size in test time, so the
+test checks what holds point by point:
 
 * every field is EMPTY exactly where its cost is infinite, and every flow's
   centre lies inside the other image (section 3.1: no flow leaves the image);
@@ -23,7 +26,6 @@ from synth import pairs
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-Q = 4
 EMPTY = np.int32(np.uint32(0x80008000).view(np.int32))
 INF = np.int32(2 ** 31 - 1)
 
@@ -41,13 +43,15 @@ def _unpack(f):
 
 
 @pytest.mark.timeout(600)
-def test_max_size_pair_properties():
+@pytest.mark.parametrize("W,H,Q", [(8191, 512, 4), (4095, 818, 8)])
+def test_max_size_pair_properties(W, H, Q):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1508_05151_amd import ff
     ff.ff_init()
-    W, H = 8191, 512
-    _say("max size: generating the pair", W, H)
+    d = ff.ff_desc_init(W, H, 3, 3, Q, (8, 6))
+    assert (d.off_census_t - d.off_census) // 4 + Q * Q * W * H <= 1 << 30
+    _say("max size: generating the pair", W, H, "Q", Q)
     p = pairs.layered_pair(seed=3000, W=W, H=H)
     i1, i2 = torch.from_numpy(p.img1).cuda(), torch.from_numpy(p.img2).cuda()
     _say("max size: pipelined run")

@@ -241,3 +241,35 @@ def test_data_term_is_local():
         d2 = ffo.Desc(np.ascontiguousarray(p.img2[cy - mg:cy + mg + 1, cx - mg:cx + mg + 1]), 0, Q, (r,))
         e = ffo.cost(d1, d2, 0, r, mg, mg, int(dx.flat[idx]) + (x - cx) * Q, int(dy.flat[idx]) + (y - cy) * Q)
         assert e == int(Cst.flat[idx])
+
+
+@pytest.mark.parametrize("R", [1, 2])
+def test_random_search_radius_scales_with_level(R):
+    """Section 3.2: the random-search radius at level n is R_n = R n (pixels),
+    i.e. offsets up to n R Q in 1/Q px per axis.  An exact-shift pair is
+    seeded at flow 0 everywhere (no kd-tree, an all-zero proposal), so the
+    first sweep changes nothing (every candidate equals the current flow) and
+    every change made by the first random search of the coarsest level n = 2^k
+    is one drawn offset.  The accepted offsets must stay within +-nRQ and reach
+    past 3/4 of it (the true shift lies far outside every box, so any draw
+    that lowers the cost is accepted, near the edge as often as near 0): a
+    radius of R Q (unscaled), R (n/2) Q or 2 R n Q fails one of the bounds."""
+    dx, dy = 28, -21          # px: outside every search box tested
+    I1, I2 = _shift_pair(21, 96, 128, dx, dy)
+    for k in (0, 1, 2, 3):
+        n = 1 << k
+        d1, d2 = ffo.Desc(I1, k, Q, (8,)), ffo.Desc(I2, k, Q, (8,))
+        Gh, Gw = (96 + n - 1) // n, (128 + n - 1) // n
+        zero = np.zeros((Gh, Gw), np.int32)
+        kw = dict(k=k, R=R, use_kdtree=False, proposal=zero, seed=77)
+        f_p1, _ = ffo.match_field(d1, d2, 8, max_steps=2, **kw)    # seed + P1
+        f_rs, c_rs = ffo.match_field(d1, d2, 8, max_steps=3, **kw)  # ... + RS1
+        a, b = _grid(f_p1, n), _grid(f_rs, n)
+        assert np.all(a == 0), "the first sweep over a constant field changes nothing"
+        ch = a != b
+        assert ch.sum() > 20, (k, ch.sum())
+        ox, oy = ffo.unpack(b[ch])
+        bound = n * R * Q
+        assert np.abs(ox).max() <= bound and np.abs(oy).max() <= bound, (k, R)
+        big = max(np.abs(ox).max(), np.abs(oy).max())
+        assert big > (n * R * Q) * 3 // 4, (k, R, big)
