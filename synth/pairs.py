@@ -356,6 +356,17 @@ def mixed_pairs_parallel(n_pairs: int = 64, seed0: int = 3000, sizes=MIXED_SIZES
         return pool.map(_mixed_one, [(i, seed0, sizes) for i in range(n_pairs)])
 
 
+def mixed_pairs_subset(indices, seed0: int = 3000, sizes=MIXED_SIZES, workers: int = 8):
+    """Pairs `indices` of the mixed-size batch (pair i depends only on its
+    seed seed0 + i), drawn in a process pool when workers > 0."""
+    args = [(i, seed0, sizes) for i in indices]
+    if workers <= 0:
+        return [_mixed_one(a) for a in args]
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(min(workers, len(args))) as pool:
+        return pool.map(_mixed_one, args)
+
+
 def layered_pairs(first_seed: int, count: int = 16, W: int = 1024, H: int = 436, workers: int = 0):
     """`count` layered pairs with seeds first_seed .. first_seed + count - 1
     (drawn in a process pool when workers > 0; same bytes either way)."""
