@@ -19,7 +19,9 @@
  *    pixel ("subpel" Q in {1,2,4,8}); FF_EMPTY marks a pixel with no flow.
  *    Costs are int32 Hamming sums; FF_COST_INF marks "no cost".
  *  - The library keeps no per-call device state.  Buffers belong to the
- *    caller; sizes come from the *_bytes / *_init queries below.
+ *    caller; sizes come from the *_bytes / *_init queries below.  The one
+ *    exception is ff_match_field_noalloc, whose scratch is a static device
+ *    array of the library.
  */
 #ifndef FF_H_
 #define FF_H_
@@ -256,6 +258,32 @@ ff_status ff_proposal_train_step(float* params, float* adam_m, float* adam_v, in
                                  const uint8_t* img1, const uint8_t* img2, const int32_t* labels, int32_t batch,
                                  int32_t width, int32_t height, int32_t subpel, float* grad_out, float* loss_out,
                                  void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * search as ff_match_field, with the same arguments minus the workspace, and
+ * identical outputs.  Its scratch (what ff_match_field keeps in the
+ * workspace) is one static device array of FF_NOALLOC_SCRATCH_BYTES per GPU,
+ * held until the process ends; the call allocates nothing (no hipMalloc, no
+ * host heap).  ff_init() looks the array up on the current device; call it
+ * before the first use inside a capture.
+ *  - Limit: FF_ERR_SIZE if ff_match_workspace_bytes() of the same arguments
+ *    exceeds FF_NOALLOC_SCRATCH_BYTES (64 MiB: fields of up to about 1.7 Mpx
+ *    at k = 3 and leaf 8, e.g. 1024x436, 1242x375, 1280x720, 1600x1000; not
+ *    1920x1080).  Checked before anything is enqueued.
+ *  - Every call on one GPU uses that GPU's single array and the array keeps
+ *    the last call's contents (each call clears what it needs).  Calls that
+ *    overlap on one GPU (from other streams or host threads) race and give
+ *    wrong results: serialise them on one stream.
+ *  - status: nullable device int32; after the call's work it receives the
+ *    device status word (FF_OK, or FF_ERR_DEVICE if a watchdog fired) -- what
+ *    ff_read_status reports for a workspace.
+ */
+#define FF_NOALLOC_SCRATCH_BYTES (64u << 20)
+ff_status ff_match_field_noalloc(const ff_desc* src, const void* src_blob, const ff_desc* dst, const void* dst_blob,
+                                 int32_t radius, const ff_match_params* p, const int32_t* proposal, int32_t* flow,
+                                 int32_t* cost, int32_t* status, hipStream_t stream);
 
 /* After the stream has finished: read the device status word a match call
  * left in its workspace (FF_OK, or FF_ERR_DEVICE if a watchdog fired). */

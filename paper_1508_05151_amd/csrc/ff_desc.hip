@@ -363,7 +363,10 @@ using namespace ff;
 
 extern "C" {
 
-ff_status ff_init(void) { return ensure_init(); }
+ff_status ff_init(void) {
+  const ff_status st = ensure_init();
+  return st != FF_OK ? st : noalloc_scratch(nullptr);
+}
 
 ff_status ff_desc_init(ff_desc* d, const ff_image* img, int32_t k, int32_t subpel, const int32_t* radii,
                        int32_t n_radii) {

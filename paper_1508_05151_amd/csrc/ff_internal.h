@@ -98,6 +98,10 @@ ff_status launch_status();   // maps hipGetLastError to FF_ERR_HIP
 // fill a device int32 buffer with a value (graph-safe: a kernel, no memset)
 void fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t s);
 
+// device address of the current device's no-allocation scratch array
+// (looked up once per device; out may be null to only do the lookup)
+ff_status noalloc_scratch(char** out);
+
 }  // namespace ff
 
 namespace ff {

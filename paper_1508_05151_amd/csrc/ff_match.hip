@@ -17,6 +17,7 @@
 // + (row or column entering it), 2(2r+1) terms instead of (2r+1)^2, exact
 // because every sample lookup clamps per coordinate.
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "ff_internal.h"
@@ -1150,11 +1151,26 @@ static ff_status check_job(const ff_field_job& j, const ff_match_params* p) {
   return FF_OK;
 }
 
+// Per-job host arrays of a call: held inline for a single job (so that the
+// single-field entry points touch no host heap either), on the heap for more.
+template <class T>
+struct JobArray {
+  T one{};
+  std::vector<T> many;
+  int n = 0;
+  void resize(int k) {
+    n = k;
+    if (k > 1) many.assign((size_t)k, T{});
+  }
+  T& operator[](int i) { return n > 1 ? many[(size_t)i] : one; }
+  const T& operator[](int i) const { return n > 1 ? many[(size_t)i] : one; }
+};
+
 struct BatchLayout {
   size_t off_tickets, off_table;
   int launches;
-  std::vector<size_t> off_field;   // per table entry
-  std::vector<int> order;          // table entry -> job index (grouped by radius)
+  JobArray<size_t> off_field;   // per table entry
+  JobArray<int> order;          // table entry -> job index (grouped by radius)
   size_t bytes;
 };
 
@@ -1162,7 +1178,9 @@ static BatchLayout batch_layout(const ff_field_job* jobs, int n, const ff_match_
   BatchLayout B;
   B.order.resize(n);
   for (int i = 0; i < n; ++i) B.order[i] = i;
-  std::stable_sort(B.order.begin(), B.order.end(), [&](int a, int b) { return jobs[a].radius > jobs[b].radius; });
+  if (n > 1)
+    std::stable_sort(B.order.many.begin(), B.order.many.end(),
+                     [&](int a, int b) { return jobs[a].radius > jobs[b].radius; });
   int groups = 0;
   for (int i = 0; i < n; ++i)
     if (i == 0 || jobs[B.order[i]].radius != jobs[B.order[i - 1]].radius) ++groups;
@@ -1228,10 +1246,10 @@ static FieldRec make_rec(const ff_field_job& j, const ff_match_params* p, char* 
   return r;
 }
 
-static void write_table(const std::vector<FieldRec>& recs, FieldRec* dev, hipStream_t stream) {
-  for (size_t i = 0; i < recs.size(); i += kRecsPerWrite) {
+static void write_table(const JobArray<FieldRec>& recs, int nrec, FieldRec* dev, hipStream_t stream) {
+  for (int i = 0; i < nrec; i += kRecsPerWrite) {
     RecChunk ch{};
-    const int n = (int)std::min<size_t>(kRecsPerWrite, recs.size() - i);
+    const int n = std::min(kRecsPerWrite, nrec - i);
     for (int k = 0; k < n; ++k) ch.r[k] = recs[i + k];
     k_write_table<<<1, kRecsPerWrite, 0, stream>>>(ch, n, dev + i);
   }
@@ -1244,7 +1262,8 @@ static ff_status run_batch(const ff_field_job* jobs, int n, const ff_match_param
   int32_t* status = reinterpret_cast<int32_t*>(ws);
   int32_t* tickets = reinterpret_cast<int32_t*>(ws + B.off_tickets);
   FieldRec* table = reinterpret_cast<FieldRec*>(ws + B.off_table);
-  std::vector<FieldRec> recs(n);
+  JobArray<FieldRec> recs;
+  recs.resize(n);
   int maxW = 0, maxH = 0, maxN = 0, maxTop = 0, maxG = 0;
   for (int i = 0; i < n; ++i) {
     const ff_field_job& j = jobs[B.order[i]];
@@ -1260,7 +1279,7 @@ static ff_status run_batch(const ff_field_job* jobs, int n, const ff_match_param
   const int bh = band_rows_of(p);
   fill_i32(status, 1, 0, stream);
   fill_i32(tickets, (size_t)B.launches, 0, stream);
-  write_table(recs, table, stream);
+  write_table(recs, n, table, stream);
   k_clear_xch<<<dim3(64, n), 256, 0, stream>>>(table, kMinBandRows);
   if (p->use_kdtree) {
     prof_mark(FF_PROF_TREE, stream, true);
@@ -1375,6 +1394,35 @@ static ff_status run_batch(const ff_field_job* jobs, int n, const ff_match_param
   return finish();
 }
 
+// ---------------------------------------------------------------- no-allocation scratch
+// ff_match_field_noalloc keeps what ff_match_field keeps in its workspace
+// (status word, tickets, field table, kd-tree, level grids, handoff and
+// progress words) in this one static array per device.  On the host its name
+// is only a stand-in symbol, not a device address: host code uses the address
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device (at ff_init, else at the entry point's first call there).
+static __device__ __align__(256) char scratch[FF_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[64];
+}  // namespace
+
+ff_status noalloc_scratch(char** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return FF_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return FF_ERR_HIP;
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  if (out) *out = g_scratch_ptr[dev];
+  return FF_OK;
+}
+
+__global__ void k_copy_status(const int32_t* __restrict__ from, int32_t* __restrict__ to) { *to = *from; }
+
 }  // namespace ff
 
 using namespace ff;
@@ -1454,6 +1502,31 @@ ff_status ff_match_field(const ff_desc* src, const void* src_blob, const ff_desc
   return ff_match_batch(&j, 1, p, workspace, workspace_bytes, stream);
 }
 
+ff_status ff_match_field_noalloc(const ff_desc* src, const void* src_blob, const ff_desc* dst, const void* dst_blob,
+                                 int32_t radius, const ff_match_params* p, const int32_t* proposal, int32_t* flow,
+                                 int32_t* cost, int32_t* status, hipStream_t stream) {
+  if (!p) return FF_ERR_ARG;
+  ff_status st = check_params(src, dst, radius, p);
+  if (st != FF_OK) return st;
+  const ff_field_job j = single_job(src, src_blob, dst, dst_blob, radius, p, proposal, flow, cost);
+  const BatchLayout B = batch_layout(&j, 1, p);
+  if (B.bytes > (size_t)FF_NOALLOC_SCRATCH_BYTES) return FF_ERR_SIZE;
+  st = check_job(j, p);
+  if (st != FF_OK) return st;
+  st = ensure_init();
+  if (st != FF_OK) return st;
+  char* ws = nullptr;
+  st = noalloc_scratch(&ws);
+  if (st != FF_OK) return st;
+  st = run_batch(&j, 1, p, ws, B, stream);
+  if (st != FF_OK) return st;
+  if (status) {
+    k_copy_status<<<1, 1, 0, stream>>>(reinterpret_cast<const int32_t*>(ws), status);
+    return launch_status();
+  }
+  return FF_OK;
+}
+
 ff_status ff_read_status(const void* workspace, int32_t* status_host) {
   if (!workspace || !status_host) return FF_ERR_ARG;
   if (hipMemcpy(status_host, workspace, 4, hipMemcpyDeviceToHost) != hipSuccess) return FF_ERR_HIP;
@@ -1476,9 +1549,11 @@ ff_status ff_build_kdtree(const ff_desc* d, const void* blob, int32_t radius, in
   ff_status st = ensure_init();
   if (st != FF_OK) return st;
   char* ws = static_cast<char*>(workspace);
-  std::vector<FieldRec> recs(1, make_rec(j, &p, ws + B.off_field[0]));
+  JobArray<FieldRec> recs;
+  recs.resize(1);
+  recs[0] = make_rec(j, &p, ws + B.off_field[0]);
   FieldRec* table = reinterpret_cast<FieldRec*>(ws + B.off_table);
-  write_table(recs, table, stream);
+  write_table(recs, 1, table, stream);
   st = enqueue_tree_build(table, 1, d->width * d->height, recs[0].t_top, leaf, stream);
   if (st != FF_OK) return st;
   const char* fws = ws + B.off_field[0];

@@ -95,6 +95,9 @@ def lib():
         L.ff_tree_nodes.restype = i32
         L.ff_build_kdtree.argtypes = [C.POINTER(ff_desc), P, i32, i32, P, P, P, P, C.c_size_t, P]
         L.ff_build_kdtree.restype = i32
+        L.ff_match_field_noalloc.argtypes = [C.POINTER(ff_desc), P, C.POINTER(ff_desc), P, i32,
+                                             C.POINTER(ff_match_params), P, P, P, P, P]
+        L.ff_match_field_noalloc.restype = i32
         L.ff_read_status.argtypes = [P, C.POINTER(C.c_int32)]
         L.ff_read_status.restype = i32
         L.ff_status_string.argtypes = [i32]
@@ -198,6 +201,23 @@ def ff_match_field(src: ff_desc, src_blob, dst: ff_desc, dst_blob, radius: int, 
     _check(lib().ff_match_field(C.byref(src), _ptr(src_blob), C.byref(dst), _ptr(dst_blob), radius, C.byref(p),
                                 _ptr(proposal), _ptr(flow), _ptr(cost), _ptr(workspace), workspace.numel(),
                                 _stream(stream)), "ff_match_field")
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def ff_match_field_noalloc(src: ff_desc, src_blob, dst: ff_desc, dst_blob, radius: int, p: ff_match_params,
+                           proposal, flow, cost, status=None, stream=None):
+    """ff_match_field without a workspace: the library's static per-device
+    scratch serves it (calls on one GPU must not overlap)."""
+    check_proposal(proposal, src, p.k)
+    _check_i32(flow, src.width * src.height, "flow")
+    _check_i32(cost, src.width * src.height, "cost")
+    if status is not None:
+        _check_i32(status, 1, "status")
+    _check(lib().ff_match_field_noalloc(C.byref(src), _ptr(src_blob), C.byref(dst), _ptr(dst_blob), radius,
+                                        C.byref(p), _ptr(proposal), _ptr(flow), _ptr(cost), _ptr(status),
+                                        _stream(stream)), "ff_match_field_noalloc")
 
 
 def make_job(src: ff_desc, src_blob, dst: ff_desc, dst_blob, radius, flow, cost, field_id=0, pair_id=0, seed=0,

@@ -169,3 +169,23 @@ def test_binding_checks_proposal_and_outputs_before_any_launch(ff):
     # a k = 2 batch needs the 12 x 16 grid
     with pytest.raises(ff.FFError, match="device"):
         ff.make_job(d, None, d, None, 8, ok_flow, ok_flow, proposal=torch.zeros((12, 16), dtype=torch.int32), k=2)
+
+
+def test_noalloc_entry_refuses_before_any_launch(ff):
+    """ff_match_field_noalloc checks the parameters, then the field's scratch
+    need against FF_NOALLOC_SCRATCH_BYTES (FF_ERR_SIZE), then the pointers
+    (FF_ERR_ARG) -- all before anything is enqueued."""
+    L = ff.lib()
+    p = ff.ff_default_params()
+    big = ff.ff_desc_init(1920, 1080, 3, 3, 4, (8,))
+    assert ff.ff_match_workspace_bytes(big, big, 8, p) > ff.NOALLOC_SCRATCH_BYTES
+    assert L.ff_match_field_noalloc(C.byref(big), None, C.byref(big), None, 8, C.byref(p), None, None, None, None,
+                                    None) == -2
+    ok = ff.ff_desc_init(1280, 720, 3, 3, 4, (8,))
+    assert ff.ff_match_workspace_bytes(ok, ok, 8, p) <= ff.NOALLOC_SCRATCH_BYTES
+    assert L.ff_match_field_noalloc(C.byref(ok), None, C.byref(ok), None, 8, C.byref(p), None, None, None, None,
+                                    None) == -1
+    # a radius without WHT vectors
+    assert L.ff_match_field_noalloc(C.byref(ok), None, C.byref(ok), None, 6, C.byref(p), None, None, None, None,
+                                    None) == -1
+    assert L.ff_match_field_noalloc(None, None, None, None, 8, None, None, None, None, None, None) == -1
