@@ -570,6 +570,80 @@ int match_field(const Desc& s, const Desc& d, int r, const MatchParams& P, const
   return steps;
 }
 
+// ---------------------------------------------------------------------------
+// Section 3.4, the region-based filter that follows the consistency check:
+// the partly filtered field is segmented into regions (neighbouring pixels
+// join a region when their flows differ by less than 3 px; only neighbouring
+// differences count, so a region's flow may drift arbitrarily), and each
+// region of fewer than s pixels is removed whole if at least one outlier that
+// the consistency check deleted could join it by the same rule.
+//
+// Reading: 4-neighbourhood, both for the segmentation and for "could join";
+// "differ by less than 3 px" is the Euclidean length of the flow difference,
+// strictly below 3 px: dx^2 + dy^2 < (3Q)^2 in 1/Q px.  A pixel belongs to
+// the partly filtered field iff the check kept it and its flow is set; a
+// deleted outlier is a pixel the check did not keep whose flow is set, and
+// it would join with that flow.  One pass: the regions are those of the
+// partly filtered field, and a removed region does not supply outliers to
+// another.  Each region is named by its smallest pixel index y W + x.
+bool similar3(int32_t f, int32_t g, int Q) {
+  const int64_t dx = unpack_x(f) - unpack_x(g), dy = unpack_y(f) - unpack_y(g);
+  return dx * dx + dy * dy < 9LL * Q * Q;
+}
+
+void region_filter(const int32_t* F, const uint8_t* keep, int W, int H, int Q, int s, int32_t* label,
+                   uint8_t* keep_out, int32_t* out) {
+  const size_t N = (size_t)W * H;
+  auto in_field = [&](size_t i) { return keep[i] != 0 && F[i] != kEmpty; };
+  auto deleted = [&](size_t i) { return keep[i] == 0 && F[i] != kEmpty; };
+  const int ddx[4] = {-1, 1, 0, 0}, ddy[4] = {0, 0, -1, 1};
+  std::vector<int32_t> lab(N, -1);
+  std::vector<int64_t> count(N, 0);
+  std::vector<char> joinable(N, 0);
+  std::vector<size_t> stack;
+  // flood fill from each unlabelled field pixel in raster order, so the seed
+  // of a region is its smallest pixel index
+  for (size_t i = 0; i < N; ++i) {
+    if (!in_field(i) || lab[i] >= 0) continue;
+    lab[i] = (int32_t)i;
+    stack.assign(1, i);
+    while (!stack.empty()) {
+      const size_t p = stack.back();
+      stack.pop_back();
+      ++count[i];
+      const int x = (int)(p % W), y = (int)(p / W);
+      for (int t = 0; t < 4; ++t) {
+        const int xx = x + ddx[t], yy = y + ddy[t];
+        if (xx < 0 || yy < 0 || xx >= W || yy >= H) continue;
+        const size_t q = (size_t)yy * W + xx;
+        if (in_field(q) && lab[q] < 0 && similar3(F[p], F[q], Q)) {
+          lab[q] = (int32_t)i;
+          stack.push_back(q);
+        }
+      }
+    }
+  }
+  // could a deleted outlier join the region (a 4-neighbour of one of its
+  // pixels, by the same rule)?
+  for (size_t p = 0; p < N; ++p) {
+    if (lab[p] < 0) continue;
+    const int x = (int)(p % W), y = (int)(p / W);
+    for (int t = 0; t < 4; ++t) {
+      const int xx = x + ddx[t], yy = y + ddy[t];
+      if (xx < 0 || yy < 0 || xx >= W || yy >= H) continue;
+      const size_t q = (size_t)yy * W + xx;
+      if (deleted(q) && similar3(F[p], F[q], Q)) joinable[lab[p]] = 1;
+    }
+  }
+  for (size_t p = 0; p < N; ++p) {
+    const bool removed = lab[p] >= 0 && count[lab[p]] < s && joinable[lab[p]];
+    const bool kept = lab[p] >= 0 && !removed;
+    if (label) label[p] = lab[p];
+    keep_out[p] = kept ? 1 : 0;
+    out[p] = kept ? F[p] : kEmpty;
+  }
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -748,6 +822,16 @@ int ffo_consistency(const int32_t* F, int W1, int H1, const int32_t* const* B, i
       keep[i] = ok ? 1 : 0;
       filtered[i] = ok ? f : kEmpty;
     }
+  return 0;
+}
+
+// Region-based filter of section 3.4 (see region_filter above).  F: the
+// field before the consistency check; keep: the check's mask; label
+// (nullable): region name per pixel, -1 outside the partly filtered field.
+int ffo_region_filter(const int32_t* F, const uint8_t* keep, int W, int H, int Q, int s, int32_t* label,
+                      uint8_t* keep_out, int32_t* out) {
+  if (!F || !keep || !keep_out || !out || W <= 0 || H <= 0 || Q < 1 || s < 0) return -1;
+  region_filter(F, keep, W, H, Q, s, label, keep_out, out);
   return 0;
 }
 

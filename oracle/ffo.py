@@ -51,6 +51,7 @@ def lib():
         L.ffo_match_field.argtypes = [P, P, i32, P, P, P, P, P]
         L.ffo_consistency.argtypes = [P, i32, i32, P, i32, i32, i32, i32, i32, P, P]
         L.ffo_brute_nnf.argtypes = [P, P, i32, i32, P, P]
+        L.ffo_region_filter.argtypes = [P, P, i32, i32, i32, i32, P, P, P]
         _lib = L
     return _lib
 
@@ -229,6 +230,20 @@ def consistency(F: np.ndarray, Bs, Q: int, eps_q: int):
     assert lib().ffo_consistency(_p(F), W1, H1, C.cast(ptrs, C.c_void_p), len(Bs), W2, H2, Q, eps_q,
                                  _p(keep), _p(filt)) == 0
     return keep, filt
+
+
+def region_filter(F: np.ndarray, keep: np.ndarray, Q: int, s: int):
+    """Section 3.4's region filter on the consistency check's output.
+    Returns (label, keep_out, filtered): region names (smallest pixel index,
+    -1 outside the partly filtered field), the final mask and field."""
+    F = np.ascontiguousarray(F, np.int32)
+    keep = np.ascontiguousarray(keep, np.uint8)
+    H, W = F.shape
+    label = np.empty((H, W), np.int32)
+    ko = np.empty((H, W), np.uint8)
+    out = np.empty((H, W), np.int32)
+    assert lib().ffo_region_filter(_p(F), _p(keep), W, H, Q, s, _p(label), _p(ko), _p(out)) == 0
+    return label, ko, out
 
 
 def brute_nnf(src: Desc, dst: Desc, lev: int, r: int):
