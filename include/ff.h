@@ -196,6 +196,34 @@ ff_status ff_consistency_filter(const int32_t* flow_fwd, int32_t w1, int32_t h1,
                                 int32_t* flow_filtered, hipStream_t stream);
 
 /*
+ * Section 3.4, the region-based filter that follows Eq. 5's check.  The
+ * partly filtered field (the pixels the check kept) is segmented into
+ * regions: 4-neighbours belong to one region when their flows differ by less
+ * than 3 px (dx^2 + dy^2 < (3 subpel)^2 in 1/subpel px; only neighbouring
+ * differences count).  A region of fewer than min_region pixels (s: 50 for
+ * the paper's Sintel and Middlebury settings, 150 for KITTI) is removed whole
+ * if some deleted outlier -- a pixel the check did not keep whose flow is
+ * set -- 4-adjacent to one of its pixels could join it by the same rule.
+ * One pass: removed regions do not supply outliers to other regions.
+ *  flow: w*h packed flows before the check (ff_match_field's F);
+ *  keep: w*h bytes, the check's mask (ff_consistency_filter's keep; a pixel
+ *        with keep != 0 and FF_EMPTY flow counts as neither kept nor deleted);
+ *  label: nullable, w*h int32: each kept pixel's region, named by its
+ *        smallest pixel index y*w + x; -1 for pixels the check did not keep;
+ *  keep_out, flow_out: w*h final mask (1 kept) and field (FF_EMPTY where
+ *        removed by either filter);
+ *  workspace: ff_region_filter_workspace_bytes(w, h) bytes (two int32 per
+ *        pixel), contents on entry irrelevant.
+ * Errors: FF_ERR_ARG for null pointers, sizes below 1, subpel not in
+ * {1,2,4,8} or min_region < 0; FF_ERR_SIZE beyond 8191 per side or 2^22
+ * pixels; FF_ERR_WORKSPACE if the workspace is too small.
+ */
+size_t ff_region_filter_workspace_bytes(int32_t width, int32_t height);
+ff_status ff_region_filter(const int32_t* flow, const uint8_t* keep, int32_t width, int32_t height, int32_t subpel,
+                           int32_t min_region, int32_t* label, uint8_t* keep_out, int32_t* flow_out, void* workspace,
+                           size_t workspace_bytes, hipStream_t stream);
+
+/*
  * Inspection: build the kd-tree of section 3.1 alone (the one ff_match_field
  * builds first): over every pixel of the image's WHT(radius) vectors, split
  * while a node holds more than `leaf` points, on the dimension of largest
@@ -299,7 +327,7 @@ const char* ff_status_string(ff_status s);
  * events (host allocation: call it outside any capture or timed loop);
  * ff_profile_end waits for them, returns the summed elapsed milliseconds and
  * the number of launches, destroys the events and disarms the hook.
- * Errors: FF_ERR_ARG for a class outside 1..9, max_launches outside
+ * Errors: FF_ERR_ARG for a class outside 1..10, max_launches outside
  * 1..2^20 or null outputs; FF_ERR_HIP if creating, recording, waiting for or
  * timing an event failed (ff_profile_end still disarms the hook).
  */
@@ -312,7 +340,8 @@ typedef enum {
   FF_PROF_RANDOM_SEARCH = 6,
   FF_PROF_FILTER = 7,
   FF_PROF_PROPOSAL = 8,      /* the whole ff_proposal_forward sequence */
-  FF_PROF_TRAIN = 9          /* the whole ff_proposal_train_step sequence */
+  FF_PROF_TRAIN = 9,         /* the whole ff_proposal_train_step sequence */
+  FF_PROF_REGION = 10        /* the whole ff_region_filter sequence */
 } ff_prof_class;
 ff_status ff_profile_begin(int32_t kernel_class, int32_t max_launches);
 ff_status ff_profile_end(double* total_ms, int32_t* launches);

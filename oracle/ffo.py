@@ -256,9 +256,10 @@ def brute_nnf(src: Desc, dst: Desc, lev: int, r: int):
 
 
 def match_pair(img1, img2, r: int = 8, r2: int = 6, k: int = 3, Q: int = 4, eps: int = 5, seed: int = 0,
-               pair_id: int = 0, n_bwd: int = 2, **kw):
+               pair_id: int = 0, n_bwd: int = 2, region_s=None, **kw):
     """The whole hot path on one pair: descriptors, F (r), B1 (r), B2 (r2),
-    two-way consistency filter.  Returns a dict of arrays."""
+    two-way consistency filter, and with region_s the region filter of
+    section 3.4.  Returns a dict of arrays."""
     radii = (r, r2) if n_bwd == 2 and r2 != r else (r,)
     d1 = Desc(img1, k, Q, radii)
     d2 = Desc(img2, k, Q, radii)
@@ -272,4 +273,7 @@ def match_pair(img1, img2, r: int = 8, r2: int = 6, k: int = 3, Q: int = 4, eps:
         out.update(B2=B2, CB2=CB2)
     keep, filt = consistency(F, Bs, Q, eps * Q)
     out.update(keep=keep, filtered=filt)
+    if region_s is not None:
+        lab, kr, fr = region_filter(F, keep, Q, region_s)
+        out.update(region_label=lab, keep_region=kr, filtered_region=fr)
     return out

@@ -91,6 +91,10 @@ def lib():
         L.ff_profile_end.restype = i32
         L.ff_consistency_filter.argtypes = [P, i32, i32, P, i32, i32, i32, i32, i32, P, P, P]
         L.ff_consistency_filter.restype = i32
+        L.ff_region_filter_workspace_bytes.argtypes = [i32, i32]
+        L.ff_region_filter_workspace_bytes.restype = C.c_size_t
+        L.ff_region_filter.argtypes = [P, P, i32, i32, i32, i32, P, P, P, P, C.c_size_t, P]
+        L.ff_region_filter.restype = i32
         L.ff_tree_nodes.argtypes = [i32, i32]
         L.ff_tree_nodes.restype = i32
         L.ff_build_kdtree.argtypes = [C.POINTER(ff_desc), P, i32, i32, P, P, P, P, C.c_size_t, P]
@@ -265,6 +269,29 @@ def ff_consistency_filter(flow_fwd, flows_bwd, subpel, eps_q, keep, flow_filtere
            "ff_consistency_filter")
 
 
+def ff_region_filter_workspace_bytes(width, height) -> int:
+    n = lib().ff_region_filter_workspace_bytes(width, height)
+    if n == 0:
+        raise FFError(-1, "ff_region_filter_workspace_bytes")
+    return n
+
+
+def ff_region_filter(flow, keep, subpel, min_region, keep_out, flow_out, workspace, label=None, stream=None):
+    """Section 3.4's region filter after the consistency check: flow is the
+    field before the check, keep the check's mask (H x W tensors)."""
+    h, w = flow.shape
+    _check_i32(flow, w * h, "flow")
+    _check_i32(flow_out, w * h, "flow_out")
+    if label is not None:
+        _check_i32(label, w * h, "label")
+    for t, what in ((keep, "keep"), (keep_out, "keep_out")):
+        if t.dtype != torch.uint8 or not t.is_contiguous() or t.numel() != w * h or not t.is_cuda:
+            raise FFError(-1, f"{what}: expected a contiguous uint8 CUDA tensor of {w * h} elements")
+    _check(lib().ff_region_filter(_ptr(flow), _ptr(keep), w, h, subpel, min_region, _ptr(label), _ptr(keep_out),
+                                  _ptr(flow_out), _ptr(workspace), workspace.numel(), _stream(stream)),
+           "ff_region_filter")
+
+
 def ff_tree_nodes(n_points: int, leaf: int) -> int:
     return lib().ff_tree_nodes(n_points, leaf)
 
@@ -306,8 +333,12 @@ class PairMatcher:
     one of HIP's four hardware queues with a field and serialise behind it."""
 
     def __init__(self, width, height, channels=3, r=8, r2=6, k=3, subpel=4, eps=5, n_bwd=2, device="cuda",
-                 **params):
+                 region_s=None, **params):
+        """region_s: None, or s of section 3.4's region filter, which then
+        runs after the consistency check (outputs keep_region,
+        filtered_region, region_label)."""
         self.W, self.H, self.C = width, height, channels
+        self.region_s = region_s
         self.r, self.r2, self.k, self.Q, self.eps, self.n_bwd = r, r2, k, subpel, eps, n_bwd
         radii = (r,) if (n_bwd == 1 or r2 == r) else (r, r2)
         self.desc = ff_desc_init(width, height, channels, k, subpel, radii)
@@ -325,6 +356,12 @@ class PairMatcher:
             self.cost[name] = torch.empty((height, width), dtype=torch.int32, device=device)
         self.keep = torch.empty((height, width), dtype=torch.uint8, device=device)
         self.filtered = torch.empty((height, width), dtype=torch.int32, device=device)
+        if region_s is not None:
+            self.keep_region = torch.empty((height, width), dtype=torch.uint8, device=device)
+            self.filtered_region = torch.empty((height, width), dtype=torch.int32, device=device)
+            self.region_label = torch.empty((height, width), dtype=torch.int32, device=device)
+            self.region_ws = torch.empty(ff_region_filter_workspace_bytes(width, height), dtype=torch.uint8,
+                                         device=device)
         # four streams in all (the caller's and three field streams): HIP gives
         # a process four hardware queues by default, and a fifth stream would
         # share one with a field and serialise behind it
@@ -363,8 +400,14 @@ class PairMatcher:
             main.wait_event(e)
         bwd = [self.flow["B1"]] + ([self.flow["B2"]] if self.n_bwd == 2 else [])
         ff_consistency_filter(self.flow["F"], bwd, self.Q, self.eps * self.Q, self.keep, self.filtered, main)
-        return dict(F=self.flow["F"], CF=self.cost["F"], B1=self.flow["B1"], CB1=self.cost["B1"],
-                    B2=self.flow.get("B2"), CB2=self.cost.get("B2"), keep=self.keep, filtered=self.filtered)
+        out = dict(F=self.flow["F"], CF=self.cost["F"], B1=self.flow["B1"], CB1=self.cost["B1"],
+                   B2=self.flow.get("B2"), CB2=self.cost.get("B2"), keep=self.keep, filtered=self.filtered)
+        if self.region_s is not None:
+            ff_region_filter(self.flow["F"], self.keep, self.Q, self.region_s, self.keep_region,
+                             self.filtered_region, self.region_ws, label=self.region_label, stream=main)
+            out.update(keep_region=self.keep_region, filtered_region=self.filtered_region,
+                       region_label=self.region_label)
+        return out
 
     def status(self):
         return [ff_read_status(w) for w in self.ws]

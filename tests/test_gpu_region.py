@@ -1,0 +1,136 @@
+"""GPU parity of the region filter of section 3.4 (ff_region_filter) with the
+oracle, byte for byte on every output (region names, final mask, final
+field): random piecewise fields over sizes that are smaller than, equal to
+and straddling the kernel's 64 x 16 tiles, degenerate sizes, extreme flows,
+every s from 0 to 'everything is small', the hand-worked example, a second
+call on a dirty workspace, and the whole configuration-0 pipeline with the
+filter behind the consistency check."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ffo
+from synth import pairs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ff():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1508_05151_amd import ff as _ff
+    _ff.ff_init()
+    return _ff
+
+
+def _field(seed, H, W, Q=4, p_drop=0.25, extreme=False):
+    """Piecewise-constant flows with jitter (regions of many sizes, some
+    neighbours exactly 3 px apart), a few unset flows, a random check mask."""
+    rng = np.random.default_rng(seed)
+    base = rng.integers(-6, 7, (5, 2)) * Q
+    if extreme:
+        base[:2] = [[32767, -32767], [-32768 + 1, 32767]]
+    bs = int(rng.integers(2, 9))
+    idx = rng.integers(0, 5, (H // bs + 1, W // bs + 1)).repeat(bs, 0).repeat(bs, 1)[:H, :W]
+    fx = np.clip(base[idx, 0] + rng.choice([0, 0, 0, Q, 3 * Q, -2 * Q, 5], (H, W)), -32767, 32767)
+    fy = np.clip(base[idx, 1] + rng.choice([0, 0, 0, -Q, 2 * Q, 3], (H, W)), -32767, 32767)
+    F = ffo.pack(fx, fy)
+    F[rng.random((H, W)) < 0.02] = ffo.EMPTY
+    keep = (rng.random((H, W)) >= p_drop).astype(np.uint8)
+    keep[(F == ffo.EMPTY) & (rng.random((H, W)) < 0.5)] = 1   # kept but unset: neither kept nor deleted
+    return F, keep
+
+
+def _gpu(ff, F, keep, Q, s, ws=None):
+    H, W = F.shape
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    if ws is None:
+        ws = torch.empty(ff.ff_region_filter_workspace_bytes(W, H), dtype=torch.uint8, device="cuda")
+    label = torch.full((H, W), 77, dtype=torch.int32, device="cuda")
+    ko = torch.full((H, W), 9, dtype=torch.uint8, device="cuda")
+    out = torch.full((H, W), 5, dtype=torch.int32, device="cuda")
+    ff.ff_region_filter(dev(F), dev(keep), Q, s, ko, out, ws, label=label)
+    torch.cuda.synchronize()
+    return label.cpu().numpy(), ko.cpu().numpy(), out.cpu().numpy()
+
+
+def _same(got, ref, what):
+    for g, r, name in zip(got, ref, ("label", "keep", "field")):
+        assert np.array_equal(g, r), (what, name, int((g != r).sum()))
+
+
+SIZES = [(23, 31), (1, 1), (1, 70), (70, 1), (16, 64), (17, 65), (15, 63), (32, 128), (96, 128), (97, 300),
+         (436, 1024)]
+
+
+@pytest.mark.parametrize("H,W", SIZES)
+def test_random_fields_bit_exact(ff, H, W):
+    for seed in range(3):
+        F, keep = _field(1000 * H + W + seed, H, W, extreme=(seed == 2))
+        for s in (0, 1, 4, 50, 10 ** 6):
+            _same(_gpu(ff, F, keep, 4, s), ffo.region_filter(F, keep, 4, s), (H, W, seed, s))
+
+
+def test_other_subpel_and_long_regions(ff):
+    # one snake-shaped region across many tiles (long union chains), Q = 1, 2, 8
+    H, W = 200, 300
+    F = np.zeros((H, W), np.int32)
+    keep = np.zeros((H, W), np.uint8)
+    keep[::4, :] = 1
+    keep[:, ::7] = 1
+    yy, xx = np.mgrid[0:H, 0:W]
+    for Q in (1, 2, 8):
+        F = ffo.pack((xx % 5) * Q // 2, (yy % 3) * Q)
+        dele = (yy * 13 + xx * 7) % 11 == 0
+        k = np.where(dele, 0, keep).astype(np.uint8)
+        for s in (10, 5000, 10 ** 6):
+            _same(_gpu(ff, F, k, Q, s), ffo.region_filter(F, k, Q, s), (Q, s))
+
+
+def test_hand_worked_example(ff):
+    g = json.load(open(os.path.join(GOLD, "region_filter_tiny.json")))
+    Q, H, W = g["Q"], g["H"], g["W"]
+    F = np.zeros((H, W), np.int32)
+    keep = np.zeros((H, W), np.uint8)
+    for y, row in enumerate(g["map"]):
+        for x, ch in enumerate(row):
+            fx, fy, kk = g["legend_px"][ch]
+            F[y, x] = ffo.pack(int(round(fx * Q)), int(round(fy * Q)))
+            keep[y, x] = kk
+    label, ko, out = _gpu(ff, F, keep, Q, g["s"])
+    assert np.array_equal(label, np.array(g["label"], np.int32))
+    assert np.array_equal(ko, np.array(g["keep_out"], np.uint8))
+    assert np.array_equal(out, np.where(ko == 1, F, ffo.EMPTY))
+
+
+def test_dirty_workspace_second_call(ff):
+    H, W = 130, 257
+    ws = torch.empty(ff.ff_region_filter_workspace_bytes(W, H), dtype=torch.uint8, device="cuda")
+    for seed in (5, 6):
+        F, keep = _field(seed, H, W)
+        _same(_gpu(ff, F, keep, 4, 50, ws=ws), ffo.region_filter(F, keep, 4, 50), seed)
+
+
+def test_pipeline_square_pair(ff):
+    """Configuration 0 with the region filter (s = 50) behind the check."""
+    p = pairs.square_pair(0)
+    H, W, C = p.img1.shape
+    m = ff.PairMatcher(W, H, C, r=8, r2=6, k=3, subpel=4, eps=5, region_s=50)
+    out = m.run(torch.from_numpy(p.img1).cuda(), torch.from_numpy(p.img2).cuda(), seed=7)
+    torch.cuda.synchronize()
+    assert m.status() == [0, 0, 0]
+    ref = ffo.match_pair(p.img1, p.img2, r=8, r2=6, k=3, Q=4, eps=5, seed=7, region_s=50)
+    for key in ("F", "keep", "filtered", "region_label", "keep_region", "filtered_region"):
+        assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
