@@ -644,6 +644,68 @@ void region_filter(const int32_t* F, const uint8_t* keep, int W, int H, int Q, i
   }
 }
 
+// ---------------------------------------------------------------------------
+// Section 3.5: sparsification for the interpolation step.  Over the
+// outlier-filtered field, one sample is kept per 3x3 region that still holds
+// at least e samples: the one whose summed forward-backward consistency
+// errors (the |F(p) + F^b_j(p + F(p))| of Eq. 5, over the backward fields) are
+// smallest.
+//
+// Reading: the 3x3 regions tile the image from (0,0) without overlap; those
+// at the right and bottom borders are clipped and need e samples all the
+// same.  A sample is a pixel whose filtered flow is set.  The backward flows
+// are read at the nearest pixel exactly as in the consistency check.  Each
+// error |e_j| is measured in fixed point, floor(2^14 |e_j|) with |e_j| in 1/Q
+// px, i.e. the integer square root of (ex^2 + ey^2) 2^28, so that the choice
+// is exact integer arithmetic (it differs from real-valued sums only when two
+// sums lie within 2^-14 of a 1/Q px).  A lookup outside the second image or
+// at an empty backward flow makes that sample's error the largest possible.
+// The first minimum in raster order wins.
+uint64_t isqrt64(uint64_t v) {  // floor(sqrt(v)), v < 2^62, by bisection
+  uint64_t lo = 0, hi = (uint64_t)1 << 31;  // hi * hi > v
+  while (hi - lo > 1) {
+    const uint64_t mid = lo + (hi - lo) / 2;
+    if (mid * mid <= v) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+void sparsify(const int32_t* F, int W1, int H1, const int32_t* const* B, int n_bwd, int W2, int H2, int Q, int e,
+              int32_t* pick, int32_t* sparse) {
+  const uint64_t kNone = ~(uint64_t)0;
+  const int Bw = (W1 + 2) / 3, Bh = (H1 + 2) / 3;
+  if (sparse)
+    for (size_t i = 0; i < (size_t)W1 * H1; ++i) sparse[i] = kEmpty;
+  for (int by = 0; by < Bh; ++by)
+    for (int bx = 0; bx < Bw; ++bx) {
+      int count = 0, best = -1;
+      uint64_t bestErr = 0;
+      for (int y = 3 * by; y < std::min(3 * by + 3, H1); ++y)
+        for (int x = 3 * bx; x < std::min(3 * bx + 3, W1); ++x) {
+          const size_t i = (size_t)y * W1 + x;
+          const int32_t f = F[i];
+          if (f == kEmpty) continue;
+          ++count;
+          const int fx = unpack_x(f), fy = unpack_y(f);
+          const int64_t mx = floordiv((int64_t)x * Q + fx + Q / 2, Q), my = floordiv((int64_t)y * Q + fy + Q / 2, Q);
+          uint64_t err = 0;
+          for (int j = 0; j < n_bwd && err != kNone; ++j) {
+            if (mx < 0 || my < 0 || mx >= W2 || my >= H2 || B[j][(size_t)my * W2 + mx] == kEmpty) {
+              err = kNone;
+              break;
+            }
+            const int32_t b = B[j][(size_t)my * W2 + mx];
+            const int64_t ex = fx + unpack_x(b), ey = fy + unpack_y(b);
+            err += isqrt64((uint64_t)(ex * ex + ey * ey) << 28);
+          }
+          if (best < 0 || err < bestErr) { best = (int)i; bestErr = err; }
+        }
+      const int32_t chosen = count >= e ? best : -1;
+      pick[(size_t)by * Bw + bx] = chosen;
+      if (sparse && chosen >= 0) sparse[chosen] = F[chosen];
+    }
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -834,6 +896,19 @@ int ffo_region_filter(const int32_t* F, const uint8_t* keep, int W, int H, int Q
   region_filter(F, keep, W, H, Q, s, label, keep_out, out);
   return 0;
 }
+
+// Sparsification of section 3.5 (see sparsify above).  F: the outlier-
+// filtered field; B: n_bwd backward fields; pick: ceil(H1/3) x ceil(W1/3)
+// chosen pixel indices (-1: fewer than e samples); sparse (nullable): the
+// chosen flows, FF_EMPTY elsewhere.
+int ffo_sparsify(const int32_t* F, int W1, int H1, const int32_t* const* B, int n_bwd, int W2, int H2, int Q, int e,
+                 int32_t* pick, int32_t* sparse) {
+  if (!F || !B || !pick || W1 <= 0 || H1 <= 0 || W2 <= 0 || H2 <= 0 || n_bwd < 1 || n_bwd > 4 || Q < 1) return -1;
+  sparsify(F, W1, H1, B, n_bwd, W2, H2, Q, e, pick, sparse);
+  return 0;
+}
+
+uint64_t ffo_isqrt64(uint64_t v) { return isqrt64(v); }
 
 // Exact nearest-neighbour field (the NNF row of Table 1), for tiny images
 // only: for every grid point of level lev, the minimum over every flow whose

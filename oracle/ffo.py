@@ -52,6 +52,9 @@ def lib():
         L.ffo_consistency.argtypes = [P, i32, i32, P, i32, i32, i32, i32, i32, P, P]
         L.ffo_brute_nnf.argtypes = [P, P, i32, i32, P, P]
         L.ffo_region_filter.argtypes = [P, P, i32, i32, i32, i32, P, P, P]
+        L.ffo_sparsify.argtypes = [P, i32, i32, P, i32, i32, i32, i32, i32, P, P]
+        L.ffo_isqrt64.argtypes = [C.c_uint64]
+        L.ffo_isqrt64.restype = C.c_uint64
         _lib = L
     return _lib
 
@@ -246,6 +249,27 @@ def region_filter(F: np.ndarray, keep: np.ndarray, Q: int, s: int):
     return label, ko, out
 
 
+def isqrt64(v: int) -> int:
+    return int(lib().ffo_isqrt64(v))
+
+
+def sparsify(F: np.ndarray, Bs, Q: int, e: int):
+    """Section 3.5's sparsification of the outlier-filtered field F against
+    the backward fields Bs.  Returns (pick, sparse): per 3x3 block the chosen
+    pixel index (-1 when fewer than e samples), and the chosen flows on an
+    otherwise empty field."""
+    F = np.ascontiguousarray(F, np.int32)
+    H1, W1 = F.shape
+    Bs = [np.ascontiguousarray(b, np.int32) for b in Bs]
+    H2, W2 = Bs[0].shape
+    ptrs = (C.c_void_p * len(Bs))(*[b.ctypes.data for b in Bs])
+    pick = np.empty(((H1 + 2) // 3, (W1 + 2) // 3), np.int32)
+    sparse = np.empty((H1, W1), np.int32)
+    assert lib().ffo_sparsify(_p(F), W1, H1, C.cast(ptrs, C.c_void_p), len(Bs), W2, H2, Q, e, _p(pick),
+                              _p(sparse)) == 0
+    return pick, sparse
+
+
 def brute_nnf(src: Desc, dst: Desc, lev: int, r: int):
     n = 1 << lev
     Gw, Gh = (src.W + n - 1) // n, (src.H + n - 1) // n
@@ -256,10 +280,11 @@ def brute_nnf(src: Desc, dst: Desc, lev: int, r: int):
 
 
 def match_pair(img1, img2, r: int = 8, r2: int = 6, k: int = 3, Q: int = 4, eps: int = 5, seed: int = 0,
-               pair_id: int = 0, n_bwd: int = 2, region_s=None, **kw):
+               pair_id: int = 0, n_bwd: int = 2, region_s=None, sparse_e=None, **kw):
     """The whole hot path on one pair: descriptors, F (r), B1 (r), B2 (r2),
-    two-way consistency filter, and with region_s the region filter of
-    section 3.4.  Returns a dict of arrays."""
+    two-way consistency filter, with region_s the region filter of section
+    3.4 and then, with sparse_e, the sparsification of section 3.5.  Returns a
+    dict of arrays."""
     radii = (r, r2) if n_bwd == 2 and r2 != r else (r,)
     d1 = Desc(img1, k, Q, radii)
     d2 = Desc(img2, k, Q, radii)
@@ -276,4 +301,7 @@ def match_pair(img1, img2, r: int = 8, r2: int = 6, k: int = 3, Q: int = 4, eps:
     if region_s is not None:
         lab, kr, fr = region_filter(F, keep, Q, region_s)
         out.update(region_label=lab, keep_region=kr, filtered_region=fr)
+        if sparse_e is not None:
+            pick, sp = sparsify(fr, Bs, Q, sparse_e)
+            out.update(pick=pick, sparse=sp)
     return out
