@@ -101,8 +101,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--crop", default="768x327", help="CPU baseline sample: crop WxH of the pair")
     ap.add_argument("--dominant", default="propagate", choices=sorted(PROF_CLASS))
-    ap.add_argument("--mode", default="pair", choices=("pair", "batch"),
-                    help="pair: one 1024x436 pair (headline); batch: 64 mixed-size pairs in one batched call")
+    ap.add_argument("--mode", default="pair", choices=("pair", "batch", "outliers"),
+                    help="pair: one 1024x436 pair (headline); batch: 64 mixed-size pairs in one batched call; "
+                         "outliers: removed outliers vs removed inliers of the filters over epsilon")
     ap.add_argument("--pairs", type=int, default=64, help="batch mode: number of pairs")
     ap.add_argument("--gen-workers", type=int, default=16,
                     help="processes drawing the synthetic pairs (0 = in-process; use 0 under a profiler)")
@@ -114,6 +115,8 @@ def main():
                     help="pair mode: propagation band height (results are identical for every value)")
     ap.add_argument("--pipeline", type=int, default=1, choices=(0, 1),
                     help="pair mode: pipelined sweep pairs (results are identical)")
+    ap.add_argument("--outlier-pairs", type=int, default=8,
+                    help="outliers mode: layered 1024x436 pairs (seeds 1000..)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this many MiB (the reference dispatch "
                          "for scaling hardware byte counters)")
@@ -127,6 +130,8 @@ def main():
     # synthetic pairs are drawn before anything touches the GPU (worker
     # processes are started from a process that has not initialised it)
     batch_pairs = eval_pairs = None
+    if args.mode == "outliers":
+        outlier_pairs = pairs.layered_pairs(OUTLIER_SEED0, args.outlier_pairs, workers=args.gen_workers)
     if args.mode == "batch":
         if args.gen_workers > 0:
             batch_pairs = pairs.mixed_pairs_parallel(args.pairs, workers=args.gen_workers)
@@ -143,6 +148,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.mode == "batch":
         return bench_batch(args, ff, batch_pairs, torch, dev)
+    if args.mode == "outliers":
+        return bench_outliers(args, ff, outlier_pairs, torch, dev)
     if args.calib_copy_mib:
         src = torch.ones(args.calib_copy_mib << 18, dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)
@@ -343,6 +350,65 @@ def bench_batch(args, ff, prs, torch, dev):
         "speedup_vs_one_pair_per_launch": round(ms_single / ms_batch, 3),
         "batch_equals_one_pair_path": bool(same),
     }
+    print(json.dumps(line), flush=True)
+
+
+OUTLIER_SEED0 = 1000
+OUTLIER_EPS = (0.5, 1, 1.5, 2, 2.5, 3, 4, 5, 6, 8, 10, 15, 20)
+
+
+def bench_outliers(args, ff, prs, torch, dev, outlier_px=5.0, s=50):
+    """Figure 6 of the paper (section 4.1) on synthetic ground truth: for each
+    epsilon, the share of outliers (end-point error above 5 px) and of
+    inliers that a filter removes, for the one-way check (F against B1), the
+    two-way check (B1 and B2) and the two-way check followed by the region
+    filter (s = 50).  Over every pixel whose F is set (occluded ones
+    included: their ground truth is defined), summed over the pairs."""
+    import numpy as np
+    Q = 4
+    ff.ff_init()
+    H, W = prs[0].img1.shape[:2]
+    m = ff.PairMatcher(W, H, 3, r=8, r2=6, k=3, subpel=Q, eps=5)
+    keep = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    filt = torch.empty((H, W), dtype=torch.int32, device=dev)
+    keep2 = torch.empty_like(keep)
+    filt2 = torch.empty_like(filt)
+    ws = torch.empty(ff.ff_region_filter_workspace_bytes(W, H), dtype=torch.uint8, device=dev)
+    modes = ("one-way", "two-way", "two-way+region")
+    tally = {mode: {e: [0, 0] for e in OUTLIER_EPS} for mode in modes}   # removed outliers, removed inliers
+    n_out = n_in = 0
+    for p in prs:
+        out = m.run(torch.from_numpy(p.img1).to(dev), torch.from_numpy(p.img2).to(dev), seed=p.seed)
+        torch.cuda.synchronize()
+        assert m.status() == [0, 0, 0]
+        F = out["F"].cpu().numpy()
+        u = F.astype(np.int64) & 0xFFFFFFFF
+        dx = (((u & 0xFFFF) ^ 0x8000) - 0x8000) / Q
+        dy = ((((u >> 16) & 0xFFFF) ^ 0x8000) - 0x8000) / Q
+        valid = F != ff.FF_EMPTY
+        epe = np.hypot(dx - p.flow[..., 0], dy - p.flow[..., 1])
+        outl = valid & (epe > outlier_px)
+        inl = valid & ~outl
+        n_out += int(outl.sum())
+        n_in += int(inl.sum())
+        for e in OUTLIER_EPS:
+            for mode in modes:
+                bwd = [out["B1"]] if mode == "one-way" else [out["B1"], out["B2"]]
+                ff.ff_consistency_filter(out["F"], bwd, Q, int(round(e * Q)), keep, filt)
+                k = keep
+                if mode == "two-way+region":
+                    ff.ff_region_filter(out["F"], keep, Q, s, keep2, filt2, ws)
+                    k = keep2
+                rem = k.cpu().numpy() == 0
+                tally[mode][e][0] += int((rem & outl).sum())
+                tally[mode][e][1] += int((rem & inl).sum())
+    curve = {mode: [[e, round(100.0 * tally[mode][e][0] / max(n_out, 1), 3),
+                     round(100.0 * tally[mode][e][1] / max(n_in, 1), 3)] for e in OUTLIER_EPS] for mode in modes}
+    line = {"experiment": "removed outliers vs removed inliers over epsilon (the paper's Figure 6)",
+            "workload": f"{len(prs)} layered 1024x436 pairs (seeds {OUTLIER_SEED0}..{OUTLIER_SEED0 + len(prs) - 1}), "
+                        f"outlier = end-point error > {outlier_px} px, region filter s = {s}",
+            "pixels_with_flow": n_out + n_in, "outlier_share_pct": round(100.0 * n_out / max(n_out + n_in, 1), 3),
+            "curve_eps_removed_outliers_pct_removed_inliers_pct": curve}
     print(json.dumps(line), flush=True)
 
 

@@ -224,6 +224,33 @@ ff_status ff_region_filter(const int32_t* flow, const uint8_t* keep, int32_t wid
                            size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * Section 3.5: sparsification of the outlier-filtered field for the
+ * interpolation that follows the search (not part of this library).  The
+ * image is tiled from (0,0) by non-overlapping 3x3 regions (clipped at the
+ * right and bottom borders); each region that still holds at least
+ * min_samples samples (e: 4 for the paper's Sintel setting, 7 Middlebury,
+ * 9 KITTI) keeps exactly one, the sample whose summed forward-backward
+ * consistency errors over the backward fields are smallest; a sample is a
+ * pixel whose flow is set.  Errors are those of Eq. 5, |F(p) + B_j(m)| with m
+ * the nearest pixel of p + F(p) (rounding half up), each measured as
+ * floor(2^14 |e_j|) with |e_j| in 1/subpel px (exact integer square root); a
+ * lookup outside the second image or at an FF_EMPTY backward flow counts as
+ * the largest error; the first minimum in raster order wins.
+ *  flow: w1*h1 filtered field (ff_region_filter's flow_out, or
+ *        ff_consistency_filter's flow_filtered), FF_EMPTY where removed;
+ *  flow_bwd: host array of n_bwd (1..4) device pointers to w2*h2 fields;
+ *  pick: ceil(h1/3) x ceil(w1/3) int32: the chosen pixel index y*w1 + x of
+ *        each region, -1 if it holds fewer than min_samples samples;
+ *  flow_sparse: nullable, w1*h1: the chosen samples' flows, FF_EMPTY
+ *        elsewhere.
+ * Errors: FF_ERR_ARG for null pointers, sizes below 1, n_bwd outside 1..4 or
+ * subpel not in {1,2,4,8}; FF_ERR_SIZE beyond 8191 per side or 2^22 pixels.
+ */
+ff_status ff_sparsify(const int32_t* flow, int32_t w1, int32_t h1, const int32_t* const* flow_bwd, int32_t n_bwd,
+                      int32_t w2, int32_t h2, int32_t subpel, int32_t min_samples, int32_t* pick,
+                      int32_t* flow_sparse, hipStream_t stream);
+
+/*
  * Inspection: build the kd-tree of section 3.1 alone (the one ff_match_field
  * builds first): over every pixel of the image's WHT(radius) vectors, split
  * while a node holds more than `leaf` points, on the dimension of largest
@@ -327,7 +354,7 @@ const char* ff_status_string(ff_status s);
  * events (host allocation: call it outside any capture or timed loop);
  * ff_profile_end waits for them, returns the summed elapsed milliseconds and
  * the number of launches, destroys the events and disarms the hook.
- * Errors: FF_ERR_ARG for a class outside 1..10, max_launches outside
+ * Errors: FF_ERR_ARG for a class outside 1..11, max_launches outside
  * 1..2^20 or null outputs; FF_ERR_HIP if creating, recording, waiting for or
  * timing an event failed (ff_profile_end still disarms the hook).
  */
@@ -341,7 +368,8 @@ typedef enum {
   FF_PROF_FILTER = 7,
   FF_PROF_PROPOSAL = 8,      /* the whole ff_proposal_forward sequence */
   FF_PROF_TRAIN = 9,         /* the whole ff_proposal_train_step sequence */
-  FF_PROF_REGION = 10        /* the whole ff_region_filter sequence */
+  FF_PROF_REGION = 10,       /* the whole ff_region_filter sequence */
+  FF_PROF_SPARSIFY = 11      /* ff_sparsify */
 } ff_prof_class;
 ff_status ff_profile_begin(int32_t kernel_class, int32_t max_launches);
 ff_status ff_profile_end(double* total_ms, int32_t* launches);

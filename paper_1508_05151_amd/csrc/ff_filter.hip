@@ -250,6 +250,74 @@ __global__ __launch_bounds__(256) void k_rf_final(const int32_t* __restrict__ F,
   out[g] = kept ? F[g] : kEmpty;
 }
 
+// ---------------------------------------------------------------- sparsification
+// Section 3.5: one sample per 3x3 region of the outlier-filtered field that
+// still holds at least e samples -- the sample whose summed consistency
+// errors |F(p) + B_j(m)| (m the nearest pixel of p + F(p), as in Eq. 5) are
+// smallest, first in raster order on ties.  Each error is measured in fixed
+// point, floor(2^14 |e_j|) with |e_j| in 1/Q px, by an exact integer square
+// root, so the choice is integer arithmetic; a lookup outside the second
+// image or at an empty backward flow counts as the largest error.  Regions
+// tile the image from (0,0) and are clipped at the borders.
+
+// floor(sqrt(v)) for v < 2^62: a floating-point estimate made exact by
+// integer tests (the estimate is within one of the result)
+__device__ __forceinline__ uint64_t isqrt_u64(uint64_t v) {
+  uint64_t r = (uint64_t)__builtin_sqrt((double)v);
+  if (r > (1ull << 31)) r = 1ull << 31;
+  while (r * r > v) --r;
+  while ((r + 1) * (r + 1) <= v) ++r;
+  return r;
+}
+
+// one thread per 3x3 region; grid: (ceil(ceil(W1 / 3) / 256), ceil(H1 / 3))
+__global__ __launch_bounds__(256) void k_sparsify(const int32_t* __restrict__ F, int W1, int H1, BwdPtrs B, int nb,
+                                                  int W2, int H2, int qshift, int e, int32_t* __restrict__ pick,
+                                                  int32_t* __restrict__ sparse) {
+  const int Bw = (W1 + 2) / 3;
+  const int bx = blockIdx.x * blockDim.x + threadIdx.x, by = blockIdx.y;
+  if (bx >= Bw) return;
+  const uint64_t kNone = ~0ull;
+  const int half = (1 << qshift) >> 1;
+  const int x0 = 3 * bx, y0 = 3 * by;
+  const int x1 = min(x0 + 3, W1), y1 = min(y0 + 3, H1);
+  int count = 0, best = -1;
+  uint64_t bestErr = 0;
+  for (int y = y0; y < y1; ++y)
+    for (int x = x0; x < x1; ++x) {
+      const int i = y * W1 + x;
+      const int32_t f = F[i];
+      if (f == kEmpty) continue;
+      ++count;
+      const int fx = fx_of(f), fy = fy_of(f);
+      const int mx = ((x << qshift) + fx + half) >> qshift;
+      const int my = ((y << qshift) + fy + half) >> qshift;
+      uint64_t err = 0;
+      const bool inside = mx >= 0 && my >= 0 && mx < W2 && my < H2;
+      for (int j = 0; j < nb; ++j) {
+        const int32_t b = inside ? B.p[j][my * W2 + mx] : kEmpty;
+        if (b == kEmpty) {
+          err = kNone;
+          break;
+        }
+        const int64_t ex = fx + fx_of(b), ey = fy + fy_of(b);
+        err += isqrt_u64((uint64_t)(ex * ex + ey * ey) << 28);
+      }
+      if (best < 0 || err < bestErr) {
+        best = i;
+        bestErr = err;
+      }
+    }
+  const int32_t chosen = count >= e ? best : -1;
+  pick[by * Bw + bx] = chosen;
+  if (sparse)
+    for (int y = y0; y < y1; ++y)
+      for (int x = x0; x < x1; ++x) {
+        const int i = y * W1 + x;
+        sparse[i] = i == chosen ? F[i] : kEmpty;
+      }
+}
+
 }  // namespace ff
 
 using namespace ff;
@@ -301,5 +369,27 @@ extern "C" ff_status ff_region_filter(const int32_t* flow, const uint8_t* keep, 
   k_rf_count<<<(N + 255) / 256, 256, 0, stream>>>(N, parent, info);
   k_rf_final<<<(N + 255) / 256, 256, 0, stream>>>(flow, N, min_region, parent, info, label, keep_out, flow_out);
   prof_mark(FF_PROF_REGION, stream, false);
+  return launch_status();
+}
+
+extern "C" ff_status ff_sparsify(const int32_t* flow, int32_t w1, int32_t h1, const int32_t* const* flow_bwd,
+                                 int32_t n_bwd, int32_t w2, int32_t h2, int32_t subpel, int32_t min_samples,
+                                 int32_t* pick, int32_t* flow_sparse, hipStream_t stream) {
+  if (!flow || !flow_bwd || !pick) return FF_ERR_ARG;
+  if (w1 < 1 || h1 < 1 || w2 < 1 || h2 < 1 || n_bwd < 1 || n_bwd > 4) return FF_ERR_ARG;
+  if (subpel != 1 && subpel != 2 && subpel != 4 && subpel != 8) return FF_ERR_ARG;
+  if (w1 > kMaxDim || h1 > kMaxDim || w2 > kMaxDim || h2 > kMaxDim || (int64_t)w1 * h1 > kMaxPoints ||
+      (int64_t)w2 * h2 > kMaxPoints)
+    return FF_ERR_SIZE;
+  BwdPtrs B{};
+  for (int j = 0; j < n_bwd; ++j) {
+    if (!flow_bwd[j]) return FF_ERR_ARG;
+    B.p[j] = flow_bwd[j];
+  }
+  const int Bw = (w1 + 2) / 3, Bh = (h1 + 2) / 3;
+  prof_mark(FF_PROF_SPARSIFY, stream, true);
+  k_sparsify<<<dim3((Bw + 255) / 256, Bh), 256, 0, stream>>>(flow, w1, h1, B, n_bwd, w2, h2, ilog2i(subpel),
+                                                              min_samples, pick, flow_sparse);
+  prof_mark(FF_PROF_SPARSIFY, stream, false);
   return launch_status();
 }

@@ -95,6 +95,8 @@ def lib():
         L.ff_region_filter_workspace_bytes.restype = C.c_size_t
         L.ff_region_filter.argtypes = [P, P, i32, i32, i32, i32, P, P, P, P, C.c_size_t, P]
         L.ff_region_filter.restype = i32
+        L.ff_sparsify.argtypes = [P, i32, i32, P, i32, i32, i32, i32, i32, P, P, P]
+        L.ff_sparsify.restype = i32
         L.ff_tree_nodes.argtypes = [i32, i32]
         L.ff_tree_nodes.restype = i32
         L.ff_build_kdtree.argtypes = [C.POINTER(ff_desc), P, i32, i32, P, P, P, P, C.c_size_t, P]
@@ -292,6 +294,22 @@ def ff_region_filter(flow, keep, subpel, min_region, keep_out, flow_out, workspa
            "ff_region_filter")
 
 
+def ff_sparsify(flow, flows_bwd, subpel, min_samples, pick, flow_sparse=None, stream=None):
+    """Section 3.5's sparsification: flow is the outlier-filtered field,
+    pick the ceil(H/3) x ceil(W/3) int32 output."""
+    h1, w1 = flow.shape
+    h2, w2 = flows_bwd[0].shape
+    _check_i32(flow, w1 * h1, "flow")
+    for b in flows_bwd:
+        _check_i32(b, w2 * h2, "flow_bwd")
+    _check_i32(pick, ((h1 + 2) // 3) * ((w1 + 2) // 3), "pick")
+    if flow_sparse is not None:
+        _check_i32(flow_sparse, w1 * h1, "flow_sparse")
+    arr = (C.c_void_p * len(flows_bwd))(*[b.data_ptr() for b in flows_bwd])
+    _check(lib().ff_sparsify(_ptr(flow), w1, h1, C.cast(arr, C.c_void_p), len(flows_bwd), w2, h2, subpel,
+                             min_samples, _ptr(pick), _ptr(flow_sparse), _stream(stream)), "ff_sparsify")
+
+
 def ff_tree_nodes(n_points: int, leaf: int) -> int:
     return lib().ff_tree_nodes(n_points, leaf)
 
@@ -333,12 +351,16 @@ class PairMatcher:
     one of HIP's four hardware queues with a field and serialise behind it."""
 
     def __init__(self, width, height, channels=3, r=8, r2=6, k=3, subpel=4, eps=5, n_bwd=2, device="cuda",
-                 region_s=None, **params):
+                 region_s=None, sparse_e=None, **params):
         """region_s: None, or s of section 3.4's region filter, which then
         runs after the consistency check (outputs keep_region,
-        filtered_region, region_label)."""
+        filtered_region, region_label); sparse_e: None, or e of section
+        3.5's sparsification of the region-filtered field (outputs pick,
+        sparse; needs region_s)."""
+        if sparse_e is not None and region_s is None:
+            raise ValueError("sparse_e needs region_s (sparsification follows the region filter)")
         self.W, self.H, self.C = width, height, channels
-        self.region_s = region_s
+        self.region_s, self.sparse_e = region_s, sparse_e
         self.r, self.r2, self.k, self.Q, self.eps, self.n_bwd = r, r2, k, subpel, eps, n_bwd
         radii = (r,) if (n_bwd == 1 or r2 == r) else (r, r2)
         self.desc = ff_desc_init(width, height, channels, k, subpel, radii)
@@ -362,6 +384,9 @@ class PairMatcher:
             self.region_label = torch.empty((height, width), dtype=torch.int32, device=device)
             self.region_ws = torch.empty(ff_region_filter_workspace_bytes(width, height), dtype=torch.uint8,
                                          device=device)
+        if sparse_e is not None:
+            self.pick = torch.empty(((height + 2) // 3, (width + 2) // 3), dtype=torch.int32, device=device)
+            self.sparse = torch.empty((height, width), dtype=torch.int32, device=device)
         # four streams in all (the caller's and three field streams): HIP gives
         # a process four hardware queues by default, and a fifth stream would
         # share one with a field and serialise behind it
@@ -407,6 +432,9 @@ class PairMatcher:
                              self.filtered_region, self.region_ws, label=self.region_label, stream=main)
             out.update(keep_region=self.keep_region, filtered_region=self.filtered_region,
                        region_label=self.region_label)
+            if self.sparse_e is not None:
+                ff_sparsify(self.filtered_region, bwd, self.Q, self.sparse_e, self.pick, self.sparse, stream=main)
+                out.update(pick=self.pick, sparse=self.sparse)
         return out
 
     def status(self):

@@ -134,3 +134,89 @@ def test_pipeline_square_pair(ff):
     ref = ffo.match_pair(p.img1, p.img2, r=8, r2=6, k=3, Q=4, eps=5, seed=7, region_s=50)
     for key in ("F", "keep", "filtered", "region_label", "keep_region", "filtered_region"):
         assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
+
+
+# ------------------------------------------------------------------ sparsification (section 3.5)
+def _sparse_inputs(seed, H, W, Q=4, extreme=False):
+    rng = np.random.default_rng(seed)
+    lim = 32767 if extreme else 3 * Q
+    fx = rng.integers(-lim, lim + 1, (H, W))
+    fy = rng.integers(-lim, lim + 1, (H, W))
+    F = ffo.pack(fx, fy)
+    F[rng.random((H, W)) < 0.4] = ffo.EMPTY
+    Bs = []
+    for _ in range(2):
+        if extreme:
+            B = ffo.pack(rng.integers(-32767, 32768, (H, W)), rng.integers(-32767, 32768, (H, W)))
+        else:
+            B = ffo.pack(-fx + rng.integers(-6, 7, (H, W)), -fy + rng.integers(-6, 7, (H, W)))
+        B[rng.random((H, W)) < 0.05] = ffo.EMPTY
+        Bs.append(B)
+    return F, Bs
+
+
+def _gpu_sparse(ff, F, Bs, Q, e):
+    H, W = F.shape
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    pick = torch.full(((H + 2) // 3, (W + 2) // 3), 3, dtype=torch.int32, device="cuda")
+    sp = torch.full((H, W), 3, dtype=torch.int32, device="cuda")
+    ff.ff_sparsify(dev(F), [dev(b) for b in Bs], Q, e, pick, sp)
+    torch.cuda.synchronize()
+    return pick.cpu().numpy(), sp.cpu().numpy()
+
+
+@pytest.mark.parametrize("H,W", [(1, 1), (2, 70), (70, 2), (3, 3), (26, 31), (97, 300), (436, 1024)])
+def test_sparsify_random_bit_exact(ff, H, W):
+    for seed, extreme in ((1, False), (2, False), (3, True)):
+        F, Bs = _sparse_inputs(seed * 7919 + H * W, H, W, extreme=extreme)
+        for nb in (1, 2):
+            for e in (0, 1, 4, 9, 10):
+                got = _gpu_sparse(ff, F, Bs[:nb], 4, e)
+                ref = ffo.sparsify(F, Bs[:nb], 4, e)
+                assert np.array_equal(got[0], ref[0]), (H, W, seed, nb, e)
+                assert np.array_equal(got[1], ref[1]), (H, W, seed, nb, e)
+
+
+def test_sparsify_other_subpel_and_sizes(ff):
+    F, Bs = _sparse_inputs(77, 40, 53)
+    B2 = [np.ascontiguousarray(b[:31, :47]) for b in Bs]    # a second image of another size
+    for Q in (1, 2, 8):
+        for e in (1, 4):
+            got = _gpu_sparse(ff, F, B2, Q, e)
+            ref = ffo.sparsify(F, B2, Q, e)
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (Q, e)
+
+
+def test_sparsify_hand_worked_example(ff):
+    g = json.load(open(os.path.join(GOLD, "sparsify_tiny.json")))
+    H, W = g["H"], g["W"]
+    F = np.full((H, W), ffo.pack(*g["F_default"]), np.int32)
+    for x, y in g["F_empty"]:
+        F[y, x] = ffo.EMPTY
+    for k, v in g["F_set"].items():
+        x, y = map(int, k.split(","))
+        F[y, x] = ffo.pack(*v)
+    Bs = []
+    for name in ("B1", "B2"):
+        B = np.full((H, W), ffo.pack(*g["B_default"]), np.int32)
+        for k, v in g[name].items():
+            x, y = map(int, k.split(","))
+            B[y, x] = ffo.EMPTY if v == "empty" else ffo.pack(*v)
+        Bs.append(B)
+    pick, _ = _gpu_sparse(ff, F, Bs, g["Q"], g["e"])
+    assert np.array_equal(pick, np.array(g["pick"], np.int32))
+
+
+def test_pipeline_square_pair_sparsified(ff):
+    """Configuration 0 through both filters and the sparsification (s = 50,
+    e = 4: the paper's Sintel settings)."""
+    p = pairs.square_pair(3)
+    H, W, C = p.img1.shape
+    m = ff.PairMatcher(W, H, C, r=8, r2=6, k=3, subpel=4, eps=5, region_s=50, sparse_e=4)
+    out = m.run(torch.from_numpy(p.img1).cuda(), torch.from_numpy(p.img2).cuda(), seed=11)
+    torch.cuda.synchronize()
+    assert m.status() == [0, 0, 0]
+    ref = ffo.match_pair(p.img1, p.img2, r=8, r2=6, k=3, Q=4, eps=5, seed=11, region_s=50, sparse_e=4)
+    for key in ("keep", "keep_region", "filtered_region", "pick", "sparse"):
+        assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
+    assert (ref["pick"] >= 0).sum() > 0.5 * ref["pick"].size
