@@ -7,9 +7,14 @@ B1 = I2->I1 (r=8), B2 = I2->I1 (r2=6) each with its kd-tree, and the two-way
 consistency filter (sections 3.1-3.4, parameters of section 4: k=3, R=1,
 l=8, eps=5).  Inputs are resident in HBM before the timed region.
 
-Prints one JSON line with the throughput (Mpixel/s = W*H / time per pair),
-the dominant kernel's measured rate against its roofline and the CPU oracle
-timed on a bounded sample of the same workload.
+Prints one JSON line: the throughput (Mpixel/s = W*H / time per pair); the
+dominant kernel's measured rate against its roofline; every other kernel
+class against its own bound (algorithmic bytes per launch over the measured
+launch time); the level-1 propagation sweep's time per wavefront step;
+secondary workloads (the paper's fast variant, the skewed-motion recipe, the
+path through the region filter and sparsification of sections 3.4-3.5, 64
+mixed-size pairs in one batched call, the learned proposal); and the CPU
+oracle on the same pair, split by stage.
 """
 import argparse
 import json
@@ -28,18 +33,29 @@ CUS, LANES_PER_CU, CLOCK_GHZ = 256, 64, 2.4
 INT_PEAK_TOPS = CUS * LANES_PER_CU * CLOCK_GHZ / 1000.0   # 32-bit integer VALU ops, 39.3 T/s
 
 # HBM bytes per k_propagate launch (average over the 27 launches of one pair:
-# single sweeps and pipelined sweep pairs),
-# from FETCH_SIZE and WRITE_SIZE counter runs scaled by a plain-copy
-# calibration; profiles/hotpath_1024x436_hbm_counters.md holds the runs.
-# Valid for the current k_propagate only.
+# single sweeps and pipelined sweep pairs), from FETCH_SIZE and WRITE_SIZE
+# counter runs scaled by a plain-copy calibration; the counter runs are
+# summarised in profiles/hotpath_1024x436_hbm_counters.md.  Valid for the
+# k_propagate the summary names only.
 PROPAGATE_HBM_BYTES_PER_LAUNCH = 68.47e6
 
-PROF_CLASS = {"descriptors": 1, "tree": 2, "seed": 3, "level_entry": 4, "propagate": 5, "random_search": 6,
-              "filter": 7}
+K, R, R2, Q, EPS, LEAF = 3, 8, 6, 4, 5, 8
+SPARSE_S, SPARSE_E = 50, 4            # section 4: s and e for Sintel
+HEADLINE_SEED = 1000
+LEARNED_SEED0 = 4000
+OUTLIER_SEED0 = 1000
+WEIGHTS = os.path.join(ROOT, "paper_1508_05151_amd", "weights", "proposal_1024x436.safetensors")
 
 
 def grid_points(W, H, k):
     return [((W + (1 << l) - 1) >> l) * ((H + (1 << l) - 1) >> l) for l in range(k + 1)]
+
+
+def tree_depth(N, leaf):
+    d = 0
+    while (N + (1 << d) - 1) // (1 << d) > leaf:
+        d += 1
+    return d
 
 
 def propagate_ops_per_pair(W, H, k, radii, n_prop=4):
@@ -79,18 +95,126 @@ def per_point_ops_in_sweep_launches(W, H, k, radii, n_prop=4, n_rs=3):
     return sum(terms * (2 * r + 1) ** 2 * 2 for r in radii)
 
 
-def cpu_sample(crop_w, crop_h):
-    """The oracle (plain single-threaded C++) on the same hot path over a
-    crop of the benchmark pair; returns Mpixel/s of that sample."""
+def algorithmic_bytes(W, H, C=3, k=K, q=Q, n_radii=2, leaf=LEAF):
+    """Bytes each kernel class must move per launch at this size: its inputs
+    read once and its outputs written once (per image for the descriptor
+    stages, per tree for the kd-tree)."""
+    N = W * H
+    return {
+        "lab": N * (C + C),                                   # RGB in, Lab8 out
+        "smooth": N * (C + (k + 1) * C * 2),                  # Lab8 in, (k+1) int16 levels out
+        "census": N * ((k + 1) * C * 2 + 2 * (k + 1) * q * q * 4),   # levels in, planes in both layouts out
+        "wht": N * (C + n_radii * 9 * C * 4),                 # Lab8 in, 9 C int32 per radius out
+        "descriptors": N * (C + C + (k + 1) * C * 2 + 2 * (k + 1) * q * q * 4 + n_radii * 9 * C * 4),
+        # the survey's bound for a median-split build: every level reads the
+        # node's vectors (9 C int32) once
+        "tree": tree_depth(N, leaf) * 9 * C * 4 * N,
+        "filter": N * (4 + 2 * 4 + 1 + 4),                    # F, B1, B2 (looked up) in; keep, field out
+        "region": N * (4 + 1 + 4 + 1 + 4),                    # F, keep in; names, mask, field out
+        "sparsify": N * (4 + 2 * 4 + 4) + ((W + 2) // 3) * ((H + 2) // 3) * 4,   # field, 2 lookups, sparse, picks
+    }
+
+
+# ------------------------------------------------------------------ CPU oracle (rank 0 only)
+def _oracle_stages(args):
+    """One full run of the oracle on the pair, stage by stage, on one core."""
+    img1, img2, core = args
+    try:
+        os.sched_setaffinity(0, {core})
+    except (AttributeError, OSError):
+        pass
     from oracle import ffo
-    from synth import pairs
-    p = pairs.layered_pair(1000)
-    i1 = p.img1[:crop_h, :crop_w].copy()
-    i2 = p.img2[:crop_h, :crop_w].copy()
+    t = {}
     t0 = time.perf_counter()
-    ffo.match_pair(i1, i2, r=8, r2=6, k=3, Q=4, eps=5, seed=1000)
-    dt = time.perf_counter() - t0
-    return crop_w * crop_h / dt / 1e6, dt
+    d1 = ffo.Desc(img1, K, Q, (R, R2))
+    d2 = ffo.Desc(img2, K, Q, (R, R2))
+    t["descriptors"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for d, rad in ((d2, R), (d1, R), (d1, R2)):       # the trees of F, B1, B2 (each field builds its own)
+        ffo.kdtree_build(d.wht(rad).reshape(-1, 27), LEAF)
+    t["trees"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    F, _ = ffo.match_field(d1, d2, R, k=K, seed=HEADLINE_SEED, field_id=0)
+    t["F"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    B1, _ = ffo.match_field(d2, d1, R, k=K, seed=HEADLINE_SEED, field_id=1)
+    t["B1"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    B2, _ = ffo.match_field(d2, d1, R2, k=K, seed=HEADLINE_SEED, field_id=2)
+    t["B2"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    keep, _ = ffo.consistency(F, [B1, B2], Q, EPS * Q)
+    t["filter"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, _, fr = ffo.region_filter(F, keep, Q, SPARSE_S)
+    t["region_filter"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ffo.sparsify(fr, [B1, B2], Q, SPARSE_E)
+    t["sparsify"] = time.perf_counter() - t0
+    # the benchmark's step: descriptors, three fields (each with its tree), check
+    t["path"] = t["descriptors"] + t["F"] + t["B1"] + t["B2"] + t["filter"]
+    return t
+
+
+def cpu_baseline(pair, reps=3):
+    """The oracle (plain single-threaded C++) on the benchmark pair, `reps`
+    runs side by side in processes pinned to distinct cores; median per
+    stage.  Mpixel/s = W*H / median time of the benchmark's step."""
+    import multiprocessing as mp
+    cores = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else list(range(reps))
+    jobs = [(pair.img1, pair.img2, cores[i % len(cores)]) for i in range(reps)]
+    with mp.get_context("spawn").Pool(reps) as pool:
+        runs = pool.map(_oracle_stages, jobs)
+    med = {key: statistics.median(r[key] for r in runs) for key in runs[0]}
+    H, W = pair.img1.shape[:2]
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": round(W * H / med["path"] / 1e6, 5), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+            "sample": f"the whole benchmark pair ({W}x{H}): descriptors x2, F, B1, B2 (each with its kd-tree), "
+                      f"two-way check; median of {reps} single-threaded runs made side by side on distinct cores",
+            "seconds_median": {k: round(v, 3) for k, v in med.items()},
+            "host": {"cpu_model": model, "nproc": os.cpu_count(),
+                     "cores_available": len(cores)}}
+
+
+# ------------------------------------------------------------------ GPU timing helpers
+def time_steps(run, torch, steps):
+    """Wall time per step of `run` (K steps between synchronisations) and
+    the per-step event times."""
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for i in range(steps):
+        starts[i].record()
+        out = run()
+        ends[i].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) * 1000.0 / steps, [s.elapsed_time(e) for s, e in zip(starts, ends)], out
+
+
+def class_times(ff, run, torch, classes, reps=5, per_step=64):
+    """Average launch time (ms) and launches per step of each kernel class,
+    each from its own profiled run of `reps` steps."""
+    res = {}
+    for c in classes:
+        torch.cuda.synchronize()
+        ff.ff_profile_begin(c, per_step * reps)
+        for _ in range(reps):
+            run()
+        torch.cuda.synchronize()
+        tot, n, _ = ff.ff_profile_end()
+        res[c] = (tot / max(n, 1), n / reps)
+    return res
 
 
 def main():
@@ -99,55 +223,61 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--crop", default="768x327", help="CPU baseline sample: crop WxH of the pair")
-    ap.add_argument("--dominant", default="propagate", choices=sorted(PROF_CLASS))
+    ap.add_argument("--cpu-reps", type=int, default=3, help="CPU baseline: oracle runs (side by side)")
     ap.add_argument("--mode", default="pair", choices=("pair", "batch", "outliers"),
-                    help="pair: one 1024x436 pair (headline); batch: 64 mixed-size pairs in one batched call; "
-                         "outliers: removed outliers vs removed inliers of the filters over epsilon")
-    ap.add_argument("--pairs", type=int, default=64, help="batch mode: number of pairs")
+                    help="pair: one 1024x436 pair (headline, with every secondary block); batch: 64 mixed-size "
+                         "pairs in one batched call alone; outliers: removed outliers vs removed inliers of the "
+                         "filters over epsilon")
+    ap.add_argument("--pairs", type=int, default=64, help="batch block: number of mixed-size pairs")
     ap.add_argument("--gen-workers", type=int, default=16,
                     help="processes drawing the synthetic pairs (0 = in-process; use 0 under a profiler)")
-    ap.add_argument("--no-learned", action="store_true",
-                    help="pair mode: skip the learned-proposal comparison")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-pair batch block")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the per-kernel table and the secondary workloads")
     ap.add_argument("--learned-pairs", type=int, default=16,
-                    help="pair mode: held-out 1024x436 pairs of the learned-proposal comparison")
-    ap.add_argument("--band-rows", type=int, default=16, choices=(8, 16, 32),
-                    help="pair mode: propagation band height (results are identical for every value)")
-    ap.add_argument("--pipeline", type=int, default=1, choices=(0, 1),
-                    help="pair mode: pipelined sweep pairs (results are identical)")
+                    help="held-out 1024x436 pairs of the learned-proposal comparison")
     ap.add_argument("--outlier-pairs", type=int, default=8,
                     help="outliers mode: layered 1024x436 pairs (seeds 1000..)")
+    ap.add_argument("--band-rows", type=int, default=16, choices=(8, 16, 32),
+                    help="propagation band height of the headline pair (results are identical for every value)")
+    ap.add_argument("--pipeline", type=int, default=1, choices=(0, 1),
+                    help="pipelined sweep pairs on the headline pair (results are identical)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this many MiB (the reference dispatch "
                          "for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "the matcher runs on one GPU: each pair is matched on one MI355X; "
-                                   "--gpus must be 1"}), flush=True)
+        print(json.dumps({"error": "this benchmark measures one GPU: the build matches each pair on one MI355X "
+                                   "and runs no multi-GPU path; --gpus must be 1"}), flush=True)
         sys.exit(2)
 
     from synth import pairs
     # synthetic pairs are drawn before anything touches the GPU (worker
     # processes are started from a process that has not initialised it)
-    batch_pairs = eval_pairs = None
+    batch_pairs = eval_pairs = outlier_pairs = None
     if args.mode == "outliers":
         outlier_pairs = pairs.layered_pairs(OUTLIER_SEED0, args.outlier_pairs, workers=args.gen_workers)
-    if args.mode == "batch":
-        if args.gen_workers > 0:
-            batch_pairs = pairs.mixed_pairs_parallel(args.pairs, workers=args.gen_workers)
-        else:
-            batch_pairs = pairs.mixed_pairs(args.pairs)
-    elif not args.no_learned:
+    if args.mode == "batch" or (args.mode == "pair" and not args.no_batch):
+        batch_pairs = (pairs.mixed_pairs_parallel(args.pairs, workers=args.gen_workers) if args.gen_workers > 0
+                       else pairs.mixed_pairs(args.pairs))
+    if args.mode == "pair" and not args.no_learned:
         eval_pairs = pairs.layered_pairs(LEARNED_SEED0, args.learned_pairs, workers=args.gen_workers)
+    pair = pairs.layered_pair(HEADLINE_SEED)
+    skewed = pairs.layered_pair(HEADLINE_SEED, motion="skewed") if args.mode == "pair" else None
+    cpu = None
+    if args.mode == "pair" and not args.no_cpu:
+        cpu = cpu_baseline(pair, args.cpu_reps)
 
-    import numpy as np
     import torch
     from paper_1508_05151_amd import ff
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    ff.ff_init()
     if args.mode == "batch":
-        return bench_batch(args, ff, batch_pairs, torch, dev)
+        print(json.dumps(bench_batch(args, ff, batch_pairs, torch, dev)), flush=True)
+        return
     if args.mode == "outliers":
         return bench_outliers(args, ff, outlier_pairs, torch, dev)
     if args.calib_copy_mib:
@@ -156,63 +286,43 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    pair = pairs.layered_pair(1000)
     H, W, C = pair.img1.shape
-    k, r, r2, Q, eps = 3, 8, 6, 4, 5
     img1 = torch.from_numpy(pair.img1).to(dev)
     img2 = torch.from_numpy(pair.img2).to(dev)
-    ff.ff_init()
-    m = ff.PairMatcher(W, H, C, r=r, r2=r2, k=k, subpel=Q, eps=eps, band_rows=args.band_rows,
+    m = ff.PairMatcher(W, H, C, r=R, r2=R2, k=K, subpel=Q, eps=EPS, band_rows=args.band_rows,
                        pipeline=args.pipeline)
+    run = lambda: m.run(img1, img2, seed=HEADLINE_SEED)
     for _ in range(args.warmup):
-        m.run(img1, img2, seed=1000)
+        run()
     torch.cuda.synchronize()
     if args.warmup:
         assert m.status() == [0, 0, 0], m.status()
 
     # timed region: K whole-path steps; the dominant kernel class is bracketed
-    # with HIP events on the streams it runs on (library profiling hook)
-    launches_per_step = {"propagate": 3 * (k + 1) * 4, "random_search": 3 * (k + 1) * 3, "descriptors": 2,
-                         "tree": 3, "seed": 3, "level_entry": 3 * k, "filter": 1}[args.dominant]
-    ff._check(ff.lib().ff_profile_begin(PROF_CLASS[args.dominant], launches_per_step * args.steps + 8),
-              "ff_profile_begin")
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        starts[i].record()
-        out = m.run(img1, img2, seed=1000)
-        ends[i].record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    import ctypes
-    tot = ctypes.c_double(0)
-    nl = ctypes.c_int32(0)
-    ff._check(ff.lib().ff_profile_end(ctypes.byref(tot), ctypes.byref(nl)), "ff_profile_end")
+    # with HIP events on the streams it runs on (library profiling hook), and
+    # each of its launches is timed
+    per_field = 9 if args.pipeline else 12
+    ff.ff_profile_begin("propagate", 3 * 16 * args.steps + 8)
+    ms_per_step, per_step, out = time_steps(run, torch, args.steps)
+    tot, nl, each = ff.ff_profile_end(each=3 * per_field * args.steps)
     assert m.status() == [0, 0, 0], m.status()
-    per_step = [s.elapsed_time(e) for s, e in zip(starts, ends)]
-    ms_per_step = (t1 - t0) * 1000.0 / args.steps
     value = W * H / (ms_per_step / 1000.0) / 1e6
 
     # dominant kernel against its roofline (integer VALU: census terms)
-    avg_launch_ms = tot.value / max(nl.value, 1)
-    roof = None
-    if args.dominant == "propagate":
-        # launches per step as measured (a pipelined sweep pair is one launch)
-        ops_per_launch = (propagate_ops_per_pair(W, H, k, (r, r, r2)) +
-                          per_point_ops_in_sweep_launches(W, H, k, (r, r, r2))) / (nl.value / args.steps)
-        achieved = ops_per_launch / (avg_launch_ms / 1000.0) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(INT_PEAK_TOPS, 2), "unit": "TOP/s",
-                "frac": round(achieved / INT_PEAK_TOPS, 5), "traffic": PROPAGATE_HBM_BYTES_PER_LAUNCH,
-                "traffic_GBps": round(PROPAGATE_HBM_BYTES_PER_LAUNCH / (avg_launch_ms / 1000.0) / 1e9, 2),
-                "kernel": "k_propagate", "avg_launch_ms": round(avg_launch_ms, 4), "launches": nl.value,
-                "ops_per_launch": int(ops_per_launch)}
+    avg_launch_ms = tot / max(nl, 1)
+    ops_per_launch = (propagate_ops_per_pair(W, H, K, (R, R, R2)) +
+                      per_point_ops_in_sweep_launches(W, H, K, (R, R, R2))) / (nl / args.steps)
+    achieved = ops_per_launch / (avg_launch_ms / 1000.0) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(INT_PEAK_TOPS, 2), "unit": "TOP/s",
+            "frac": round(achieved / INT_PEAK_TOPS, 5), "traffic": PROPAGATE_HBM_BYTES_PER_LAUNCH,
+            "traffic_GBps": round(PROPAGATE_HBM_BYTES_PER_LAUNCH / (avg_launch_ms / 1000.0) / 1e9, 2),
+            "kernel": "k_propagate", "avg_launch_ms": round(avg_launch_ms, 4), "launches": nl,
+            "ops_per_launch": int(ops_per_launch)}
 
     keep = out["keep"].float().mean().item()
     rate = pairs.inlier_rate(out["F"].cpu().numpy(), pair, Q)
     line = {
-        "metric": "flow-field Mpixel/s at 1024\u00d7436, plain vs learned proposal; % of HBM roofline",
+        "metric": "flow-field Mpixel/s at 1024×436, plain vs learned proposal; % of HBM roofline",
         "value": round(value, 3),
         "unit": "Mpixel/s",
         "n_gpus": 1,
@@ -225,26 +335,112 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "one 1024x436 RGB Sintel-shaped layered pair (seed 1000): descriptors x2, "
-                               "F/B1/B2 fields with kd-trees, two-way consistency filter",
-                   "k": k, "r": r, "r2": r2, "R": 1, "leaf": 8, "subpel": Q, "eps": eps,
+        "config": {"workload": "one 1024x436 RGB Sintel-shaped layered pair (seed 1000, 6 layers, translations "
+                               "U(+-200) px): descriptors x2, F/B1/B2 fields with kd-trees, two-way consistency "
+                               "filter",
+                   "k": K, "r": R, "r2": R2, "R": 1, "leaf": LEAF, "subpel": Q, "eps": EPS,
                    "band_rows": args.band_rows, "pipelined_sweep_pairs": bool(args.pipeline)},
         "roofline": roof,
-        "quality": {"F_inlier_rate_epe_lt_3px": round(rate, 4), "kept_fraction": round(keep, 4)},
+        "quality": {"F_inlier_rate_epe_lt_3px": round(rate, 4), "kept_fraction": round(keep, 4),
+                    "occluded_fraction": round(float(pair.occluded.mean()), 4)},
     }
+    if not args.no_secondary:
+        line["kernels"] = kernel_table(ff, run, torch, W, H, C)
+        if args.pipeline and len(each) >= 3 * per_field:
+            line["level1_sweep"] = level1_sweep(each, per_field, args.steps, W, H, args.band_rows)
+        line["secondary"] = secondary(ff, torch, dev, pair, skewed, args.steps)
+    if batch_pairs is not None:
+        line["batch"] = bench_batch(args, ff, batch_pairs, torch, dev, steps=5)
     if eval_pairs is not None:
         line["learned_proposal"] = bench_learned(ff, pair, img1, img2, eval_pairs, torch, dev, value, rate)
-    if not args.no_cpu:
-        cw, ch = (int(v) for v in args.crop.split("x"))
-        mpx, dt = cpu_sample(cw, ch)
-        line["cpu_baseline"] = {"value": round(mpx, 5), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
-                                "sample": f"whole hot path on the top-left {cw}x{ch} crop of the same pair "
-                                          f"({cw * ch} px, {dt:.1f} s single-threaded)"}
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 
-LEARNED_SEED0 = 4000
-WEIGHTS = os.path.join(ROOT, "paper_1508_05151_amd", "weights", "proposal_1024x436.safetensors")
+def kernel_table(ff, run, torch, W, H, C):
+    """Every kernel class of the step against its own bound: algorithmic
+    bytes per launch over the measured launch time, against the HBM peak."""
+    ab = algorithmic_bytes(W, H, C)
+    classes = ["lab", "smooth", "census", "wht", "descriptors", "tree", "seed", "level_entry", "random_search",
+               "filter"]
+    t = class_times(ff, run, torch, classes)
+    table = {}
+    for c in classes:
+        ms, per = t[c]
+        row = {"avg_launch_ms": round(ms, 4), "launches_per_step": round(per, 2)}
+        if per == 0:
+            row["note"] = "no launch of its own: runs inside the pipelined sweep launches"
+        elif c in ab:
+            gbs = ab[c] / (ms / 1000.0) / 1e9
+            row.update(bound="hbm", algorithmic_bytes=ab[c], GBps=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
+        else:
+            row.update(bound="alu/latency")
+        table[c] = row
+    return table
+
+
+def level1_sweep(each, per_field, steps, W, H, bh):
+    """The last propagation launch of each field is level 1's single sweep
+    (pipelined schedule): its time per wavefront step.  A band starts
+    skew + 2 steps after the band above (the skew of its rows plus two steps
+    of hand-off lookahead) and runs Gw + skew steps."""
+    sweeps = [each[s * 3 * per_field + f * per_field + per_field - 1] for s in range(steps) for f in range(3)]
+    ms = statistics.median(sweeps)
+    bands = (H + bh - 1) // bh
+    skew = bh - 1 + (bh - 1) // 4
+    wave_steps = W + skew + (skew + 2) * (bands - 1)
+    return {"median_ms": round(ms, 4), "wavefront_steps": wave_steps,
+            "ns_per_step": round(ms * 1e6 / wave_steps, 1),
+            "cycles_per_step_at_2.4GHz": round(ms * 1e-3 * CLOCK_GHZ * 1e9 / wave_steps, 0)}
+
+
+def secondary(ff, torch, dev, pair, skewed, steps):
+    """The paper's fast variant (r = 6, one backward field, section 4.2),
+    the skewed-motion recipe, and the path through the region filter and
+    the sparsification (sections 3.4, 3.5)."""
+    from synth import pairs
+    H, W, C = pair.img1.shape
+    res = {}
+    i1, i2 = torch.from_numpy(pair.img1).to(dev), torch.from_numpy(pair.img2).to(dev)
+
+    def measure(m, a, b, p):
+        run = lambda: m.run(a, b, seed=p.seed)
+        run()
+        ms, _, out = time_steps(run, torch, steps)
+        assert all(s == 0 for s in m.status()), m.status()
+        return ms, out
+
+    fast = ff.PairMatcher(W, H, C, r=6, r2=6, k=K, subpel=Q, eps=EPS, n_bwd=1)
+    ms, out = measure(fast, i1, i2, pair)
+    res["fast_variant"] = {"workload": "the benchmark pair with r = 6 and one backward field (section 4.2)",
+                           "Mpixel_per_s": round(W * H / ms / 1e3, 3), "ms_per_pair": round(ms, 4),
+                           "F_inlier_rate_epe_lt_3px": round(pairs.inlier_rate(out["F"].cpu().numpy(), pair, Q), 4)}
+    del fast
+    m = ff.PairMatcher(W, H, C, r=R, r2=R2, k=K, subpel=Q, eps=EPS)
+    s1, s2 = torch.from_numpy(skewed.img1).to(dev), torch.from_numpy(skewed.img2).to(dev)
+    ms, out = measure(m, s1, s2, skewed)
+    res["skewed_motion_recipe"] = {
+        "workload": "seed 1000 with layer translations 200 u v^2 per axis (u, v ~ U(-1, 1)): mostly small motions",
+        "Mpixel_per_s": round(W * H / ms / 1e3, 3), "ms_per_pair": round(ms, 4),
+        "F_inlier_rate_epe_lt_3px": round(pairs.inlier_rate(out["F"].cpu().numpy(), skewed, Q), 4),
+        "occluded_fraction": round(float(skewed.occluded.mean()), 4)}
+    del m
+    mf = ff.PairMatcher(W, H, C, r=R, r2=R2, k=K, subpel=Q, eps=EPS, region_s=SPARSE_S, sparse_e=SPARSE_E)
+    ms, out = measure(mf, i1, i2, pair)
+    ab = algorithmic_bytes(W, H, C)
+    run = lambda: mf.run(i1, i2, seed=pair.seed)
+    t = class_times(ff, run, torch, ["region", "sparsify"])
+    kept = out["keep_region"].float().mean().item()
+    res["with_region_filter_and_sparsification"] = {
+        "workload": f"the benchmark step followed by the region filter (s = {SPARSE_S}) and the sparsification "
+                    f"(e = {SPARSE_E})",
+        "Mpixel_per_s": round(W * H / ms / 1e3, 3), "ms_per_pair": round(ms, 4),
+        "kept_after_region_filter": round(kept, 4), "samples": int((out["pick"] >= 0).sum().item()),
+        "kernels": {c: {"avg_launch_ms": round(t[c][0], 4), "algorithmic_bytes": ab[c],
+                        "GBps": round(ab[c] / (t[c][0] / 1000.0) / 1e9, 1),
+                        "frac": round(ab[c] / (t[c][0] / 1000.0) / 1e9 / HBM_PEAK_GBS, 4)} for c in t}}
+    return res
 
 
 def bench_learned(ff, pair, img1, img2, eval_pairs, torch, dev, plain_value, plain_rate, steps=5):
@@ -260,11 +456,11 @@ def bench_learned(ff, pair, img1, img2, eval_pairs, torch, dev, plain_value, pla
     res = {"weights": os.path.relpath(WEIGHTS, ROOT),
            "pair": {"plain": {"Mpixel_per_s": round(plain_value, 3), "inlier_F": round(plain_rate, 4)}}}
     for mode, use_tree in (("plain+learned", 1), ("learned", 0)):
-        m = ff.PairMatcher(W, H, 3, r=8, r2=6, k=3, subpel=4, eps=5, use_kdtree=use_tree)
+        m = ff.PairMatcher(W, H, 3, r=R, r2=R2, k=K, subpel=Q, eps=EPS, use_kdtree=use_tree)
 
         def once():
             pf, pb = proposal.proposals_both_ways(net, b1, b2)
-            return m.run(img1, img2, seed=1000, proposal=(pf[0], pb[0]))
+            return m.run(img1, img2, seed=HEADLINE_SEED, proposal=(pf[0], pb[0]))
 
         once()
         torch.cuda.synchronize()
@@ -275,7 +471,7 @@ def bench_learned(ff, pair, img1, img2, eval_pairs, torch, dev, plain_value, pla
         ms = (time.perf_counter() - t0) * 1000.0 / steps
         assert m.status() == [0, 0, 0], m.status()
         res["pair"][mode] = {"Mpixel_per_s": round(W * H / ms / 1e3, 3),
-                             "inlier_F": round(pairs.inlier_rate(out["F"].cpu().numpy(), pair, 4), 4)}
+                             "inlier_F": round(pairs.inlier_rate(out["F"].cpu().numpy(), pair, Q), 4)}
     ev = proposal.evaluate(net, eval_pairs, reps=3, log=lambda s: None)
     res["batch"] = {"workload": f"{len(eval_pairs)} held-out 1024x436 layered pairs (seeds {LEARNED_SEED0}.."
                                 f"{LEARNED_SEED0 + len(eval_pairs) - 1}) in one batched call",
@@ -286,17 +482,17 @@ def bench_learned(ff, pair, img1, img2, eval_pairs, torch, dev, plain_value, pla
     return res
 
 
-def bench_batch(args, ff, prs, torch, dev):
+def bench_batch(args, ff, prs, torch, dev, steps=None):
     """64 pairs of mixed sizes: descriptors of all 128 images, one
     ff_match_batch call for all 192 fields, 64 consistency filters -- the
     whole batch captured in one HIP graph; against the same pairs run one
     pair per launch sequence (PairMatcher, three streams per pair)."""
+    steps = steps or args.steps
     shapes = [(p.img1.shape[1], p.img1.shape[0]) for p in prs]
     i1 = [torch.from_numpy(p.img1).to(dev) for p in prs]
     i2 = [torch.from_numpy(p.img2).to(dev) for p in prs]
     seeds = [p.seed for p in prs]
     total_px = sum(w * h for w, h in shapes)
-    ff.ff_init()
     m = ff.BatchMatcher(shapes)
     m.run(i1, i2, seeds=seeds)
     torch.cuda.synchronize()
@@ -309,55 +505,59 @@ def bench_batch(args, ff, prs, torch, dev):
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
         m.run(i1, i2, seeds=seeds)
-    for _ in range(args.warmup):
+    for _ in range(max(args.warmup, 1)):
         g.replay()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         g.replay()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     assert m.status() == 0
-    ms_batch = (t1 - t0) * 1000.0 / args.steps
+    ms_batch = (t1 - t0) * 1000.0 / steps
     # one pair per launch sequence, same pairs (buffers allocated up front)
-    singles = [ff.PairMatcher(w, h, 3, r=8, r2=6, k=3, subpel=4, eps=5) for (w, h) in shapes]
+    singles = [ff.PairMatcher(w, h, 3, r=R, r2=R2, k=K, subpel=Q, eps=EPS) for (w, h) in shapes]
     for i, sm in enumerate(singles):
         sm.run(i1[i], i2[i], seed=seeds[i], pair_id=i)
     torch.cuda.synchronize()
+    reps = max(1, steps // 2)
     t0 = time.perf_counter()
-    for _ in range(max(1, args.steps // 2)):
+    for _ in range(reps):
         for i, sm in enumerate(singles):
             sm.run(i1[i], i2[i], seed=seeds[i], pair_id=i)
     torch.cuda.synchronize()
-    ms_single = (time.perf_counter() - t0) * 1000.0 / max(1, args.steps // 2)
-    same = all(torch.equal(singles[i].flow["F"], m.out[i]["F"][0]) and
-               torch.equal(singles[i].keep, m.out[i]["keep"]) for i in range(len(prs)))
-    line = {
+    ms_single = (time.perf_counter() - t0) * 1000.0 / reps
+    same = all(torch.equal(singles[i].flow[f], m.out[i][f][0]) and torch.equal(singles[i].cost[f], m.out[i][f][1])
+               for i in range(len(prs)) for f in ("F", "B1", "B2")) and \
+        all(torch.equal(singles[i].keep, m.out[i]["keep"]) and torch.equal(singles[i].filtered, m.out[i]["filtered"])
+            for i in range(len(prs)))
+    del singles
+    return {
         "metric": "batched matching of mixed-size pairs: Mpixel/s and pairs/s, one batched call vs one pair "
                   "per launch",
         "value": round(total_px / (ms_batch / 1000.0) / 1e6, 3),
         "unit": "Mpixel/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "n_gpus": 1, "steps": steps,
         "ms_per_step": round(ms_batch, 3),
         "pairs_per_s": round(len(prs) / (ms_batch / 1000.0), 2),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": f"{len(prs)} layered pairs of mixed sizes (320x240 to 1242x375, 2-8 layers), "
-                               f"{total_px} px per batch; whole batch replayed from one HIP graph",
-                   "band_rows": best_bh, "pipelined_sweep_pairs": bool(best_pipe)},
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"{len(prs)} layered pairs of mixed sizes (320x240 to 1242x375, 2-8 layers, seeds "
+                               f"3000..{3000 + len(prs) - 1}), {total_px} px per batch; descriptors, all fields in "
+                               f"one ff_match_batch call, filters; whole batch replayed from one HIP graph",
+                   "band_rows": best_bh, "pipelined_sweep_pairs": bool(best_pipe),
+                   "autotune": "band height x sweep-pair pipelining, fastest of 6 on this batch"},
         "one_pair_per_launch": {"ms_per_batch": round(ms_single, 3),
                                 "Mpixel_per_s": round(total_px / (ms_single / 1000.0) / 1e6, 3),
                                 "pairs_per_s": round(len(prs) / (ms_single / 1000.0), 2)},
         "speedup_vs_one_pair_per_launch": round(ms_single / ms_batch, 3),
         "batch_equals_one_pair_path": bool(same),
     }
-    print(json.dumps(line), flush=True)
 
 
-OUTLIER_SEED0 = 1000
 OUTLIER_EPS = (0.5, 1, 1.5, 2, 2.5, 3, 4, 5, 6, 8, 10, 15, 20)
 
 
-def bench_outliers(args, ff, prs, torch, dev, outlier_px=5.0, s=50):
+def bench_outliers(args, ff, prs, torch, dev, outlier_px=5.0, s=SPARSE_S):
     """Figure 6 of the paper (section 4.1) on synthetic ground truth: for each
     epsilon, the share of outliers (end-point error above 5 px) and of
     inliers that a filter removes, for the one-way check (F against B1), the
@@ -365,10 +565,8 @@ def bench_outliers(args, ff, prs, torch, dev, outlier_px=5.0, s=50):
     filter (s = 50).  Over every pixel whose F is set (occluded ones
     included: their ground truth is defined), summed over the pairs."""
     import numpy as np
-    Q = 4
-    ff.ff_init()
     H, W = prs[0].img1.shape[:2]
-    m = ff.PairMatcher(W, H, 3, r=8, r2=6, k=3, subpel=Q, eps=5)
+    m = ff.PairMatcher(W, H, 3, r=R, r2=R2, k=K, subpel=Q, eps=EPS)
     keep = torch.empty((H, W), dtype=torch.uint8, device=dev)
     filt = torch.empty((H, W), dtype=torch.int32, device=dev)
     keep2 = torch.empty_like(keep)

@@ -354,7 +354,7 @@ const char* ff_status_string(ff_status s);
  * events (host allocation: call it outside any capture or timed loop);
  * ff_profile_end waits for them, returns the summed elapsed milliseconds and
  * the number of launches, destroys the events and disarms the hook.
- * Errors: FF_ERR_ARG for a class outside 1..11, max_launches outside
+ * Errors: FF_ERR_ARG for a class outside 1..15, max_launches outside
  * 1..2^20 or null outputs; FF_ERR_HIP if creating, recording, waiting for or
  * timing an event failed (ff_profile_end still disarms the hook).
  */
@@ -369,10 +369,17 @@ typedef enum {
   FF_PROF_PROPOSAL = 8,      /* the whole ff_proposal_forward sequence */
   FF_PROF_TRAIN = 9,         /* the whole ff_proposal_train_step sequence */
   FF_PROF_REGION = 10,       /* the whole ff_region_filter sequence */
-  FF_PROF_SPARSIFY = 11      /* ff_sparsify */
+  FF_PROF_SPARSIFY = 11,     /* ff_sparsify */
+  FF_PROF_LAB = 12,          /* descriptor stages: Lab8 */
+  FF_PROF_SMOOTH = 13,       /*   smoothed images I^n (all levels) */
+  FF_PROF_CENSUS = 14,       /*   census planes (all levels and phases, both layouts) */
+  FF_PROF_WHT = 15           /*   WHT vectors (all radii) */
 } ff_prof_class;
 ff_status ff_profile_begin(int32_t kernel_class, int32_t max_launches);
 ff_status ff_profile_end(double* total_ms, int32_t* launches);
+/* The same, also writing the first max_each launches' durations (ms, host
+ * array, in the order the launches were issued) to each_ms. */
+ff_status ff_profile_end_each(double* total_ms, int32_t* launches, double* each_ms, int32_t max_each);
 
 #ifdef __cplusplus
 }

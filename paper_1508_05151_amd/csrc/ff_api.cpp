@@ -47,7 +47,7 @@ extern "C" {
 
 ff_status ff_profile_begin(int32_t kernel_class, int32_t max_launches) {
   using namespace ff;
-  if (kernel_class < 1 || kernel_class > 11 || max_launches < 1 || max_launches > 1 << 20) return FF_ERR_ARG;
+  if (kernel_class < 1 || kernel_class > 15 || max_launches < 1 || max_launches > 1 << 20) return FF_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   g_prof_class = 0;
   destroy_events();
@@ -65,9 +65,9 @@ ff_status ff_profile_begin(int32_t kernel_class, int32_t max_launches) {
   return FF_OK;
 }
 
-ff_status ff_profile_end(double* total_ms, int32_t* launches) {
+ff_status ff_profile_end_each(double* total_ms, int32_t* launches, double* each_ms, int32_t max_each) {
   using namespace ff;
-  if (!total_ms || !launches) return FF_ERR_ARG;
+  if (!total_ms || !launches || max_each < 0 || (max_each > 0 && !each_ms)) return FF_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   g_prof_class = 0;
   double t = 0.0;
@@ -79,6 +79,7 @@ ff_status ff_profile_end(double* total_ms, int32_t* launches) {
         hipEventElapsedTime(&ms, g_prof_start[i], g_prof_stop[i]) != hipSuccess)
       st = FF_ERR_HIP;
     t += ms;
+    if (i < max_each) each_ms[i] = ms;
   }
   destroy_events();
   g_prof_open = g_prof_done = 0;
@@ -86,6 +87,10 @@ ff_status ff_profile_end(double* total_ms, int32_t* launches) {
   *total_ms = t;
   *launches = n;
   return st;
+}
+
+ff_status ff_profile_end(double* total_ms, int32_t* launches) {
+  return ff_profile_end_each(total_ms, launches, nullptr, 0);
 }
 
 const char* ff_status_string(ff_status s) {

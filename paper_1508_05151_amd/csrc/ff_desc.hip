@@ -444,7 +444,10 @@ ff_status ff_compute_descriptors(const ff_desc* d, const ff_image* img, const ui
   const unsigned gx = (unsigned)((W + 255) / 256);
 
   prof_mark(FF_PROF_DESCRIPTORS, stream, true);
+  prof_mark(FF_PROF_LAB, stream, true);
   k_lab8<<<dim3(gx, H), tb, 0, stream>>>(pixels, W, H, C, img->row_stride, lab);
+  prof_mark(FF_PROF_LAB, stream, false);
+  prof_mark(FF_PROF_SMOOTH, stream, true);
   k_scale16<<<(unsigned)((C * N + 255) / 256), tb, 0, stream>>>(lab, smooth, C * N);
   for (int lev = 1; lev <= d->k; ++lev) {
     const int n = 1 << lev;
@@ -456,11 +459,15 @@ ff_status ff_compute_descriptors(const ff_desc* d, const ff_image* img, const ui
     const int shift = 14 + 2 * lev - 4;
     k_lanczos_v<<<dim3(gx, H, C), tb, 0, stream>>>(T, W, H, n, lev - 1, Hc, shift, smooth + (size_t)lev * C * N);
   }
+  prof_mark(FF_PROF_SMOOTH, stream, false);
+  prof_mark(FF_PROF_WHT, stream, true);
   for (int i = 0; i < d->n_radii; ++i) {
     int32_t* V = reinterpret_cast<int32_t*>(base + d->off_wht + (size_t)i * N * d->wht_stride * 4);
     k_wht_h<<<dim3(gx, H, C), tb, 0, stream>>>(lab, W, H, d->radii[i], scratch);
     k_wht_v<<<dim3(gx, H), tb, 0, stream>>>(scratch, W, H, C, d->radii[i], d->wht_stride, V);
   }
+  prof_mark(FF_PROF_WHT, stream, false);
+  prof_mark(FF_PROF_CENSUS, stream, true);
   const size_t pw = N;
   for (int lev = 0; lev <= d->k; ++lev) {
     uint32_t* out = reinterpret_cast<uint32_t*>(base + d->off_census) + (size_t)lev * d->subpel * d->subpel * pw;
@@ -479,6 +486,7 @@ ff_status ff_compute_descriptors(const ff_desc* d, const ff_image* img, const ui
     k_transpose<<<dim3((W + 31) / 32, (H + 31) / 32, planes), dim3(32, 8), 0, stream>>>(
         reinterpret_cast<const uint32_t*>(base + d->off_census), W, H, reinterpret_cast<uint32_t*>(base + d->off_census_t));
   }
+  prof_mark(FF_PROF_CENSUS, stream, false);
   prof_mark(FF_PROF_DESCRIPTORS, stream, false);
   return launch_status();
 }

@@ -89,6 +89,8 @@ def lib():
         L.ff_profile_begin.restype = i32
         L.ff_profile_end.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.ff_profile_end.restype = i32
+        L.ff_profile_end_each.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int32), P, i32]
+        L.ff_profile_end_each.restype = i32
         L.ff_consistency_filter.argtypes = [P, i32, i32, P, i32, i32, i32, i32, i32, P, P, P]
         L.ff_consistency_filter.restype = i32
         L.ff_region_filter_workspace_bytes.argtypes = [i32, i32]
@@ -317,6 +319,24 @@ def ff_tree_nodes(n_points: int, leaf: int) -> int:
 def ff_build_kdtree(d: ff_desc, blob, radius, leaf, node_dim, node_split, perm, workspace, stream=None):
     _check(lib().ff_build_kdtree(C.byref(d), _ptr(blob), radius, leaf, _ptr(node_dim), _ptr(node_split), _ptr(perm),
                                  _ptr(workspace), workspace.numel(), _stream(stream)), "ff_build_kdtree")
+
+
+PROF = {"descriptors": 1, "tree": 2, "seed": 3, "level_entry": 4, "propagate": 5, "random_search": 6, "filter": 7,
+        "proposal": 8, "train": 9, "region": 10, "sparsify": 11, "lab": 12, "smooth": 13, "census": 14, "wht": 15}
+
+
+def ff_profile_begin(kernel_class: str, max_launches: int):
+    _check(lib().ff_profile_begin(PROF[kernel_class], max_launches), "ff_profile_begin")
+
+
+def ff_profile_end(each: int = 0):
+    """Returns (total ms, launches, per-launch ms of the first `each`)."""
+    tot = C.c_double(0)
+    n = C.c_int32(0)
+    buf = (C.c_double * max(each, 1))()
+    _check(lib().ff_profile_end_each(C.byref(tot), C.byref(n), C.cast(buf, C.c_void_p) if each else None, each),
+           "ff_profile_end")
+    return tot.value, n.value, [buf[i] for i in range(min(each, n.value))]
 
 
 def ff_read_status(workspace) -> int:

@@ -44,7 +44,7 @@ def _affine_params(cx, cy, tx, ty, rot_deg, scale):
     return [cx, cy, tx, ty, a, b, c, d]
 
 
-def _draw_layers(rng, W, H, nlayers):
+def _draw_layers(rng, W, H, nlayers, motion="uniform"):
     """Host-side draws for one pair: affine params (L x 8), polygons
     (L x MAX_VERTS x 2, padded with the first vertex; layer 0 = background),
     vertex counts, gain."""
@@ -63,8 +63,8 @@ def _draw_layers(rng, W, H, nlayers):
         p = np.concatenate([p, np.repeat(p[:1], MAX_VERTS - nv, 0)], 0)
         polys.append(p)
         ux, uy, vx, vy = rng.uniform(-1, 1, 4)
-        aff.append(_affine_params(cx, cy, MAX_T * ux * vx * vx, MAX_T * uy * vy * vy, rng.uniform(-5, 5),
-                                  rng.uniform(0.9, 1.1)))
+        tx, ty = (MAX_T * ux, MAX_T * uy) if motion == "uniform" else (MAX_T * ux * vx * vx, MAX_T * uy * vy * vy)
+        aff.append(_affine_params(cx, cy, tx, ty, rng.uniform(-5, 5), rng.uniform(0.9, 1.1)))
     gain = rng.uniform(0.9, 1.1)
     return np.array(aff), np.stack(polys), gain
 
@@ -84,13 +84,13 @@ def _inside(poly, xs, ys):
     return res
 
 
-def layered_batch(seeds, W=1024, H=436, nlayers=6, device="cuda"):
+def layered_batch(seeds, W=1024, H=436, nlayers=6, device="cuda", motion="uniform"):
     """len(seeds) pairs (B x H x W x 3 uint8 each) plus their ground-truth
-    flow (B x H x W x 2 float32)."""
+    flow (B x H x W x 2 float32); motion as in synth.pairs.layered_pair."""
     B, L = len(seeds), nlayers + 1
     m = int(MAX_T) + 64
     hc, wc = H + 2 * m, W + 2 * m
-    draws = [_draw_layers(np.random.default_rng(s), W, H, nlayers) for s in seeds]
+    draws = [_draw_layers(np.random.default_rng(s), W, H, nlayers, motion) for s in seeds]
     aff = torch.tensor(np.stack([d[0] for d in draws]), dtype=torch.float32, device=device)     # B L 8
     polys = torch.tensor(np.stack([d[1] for d in draws]), dtype=torch.float32, device=device)   # B L V 2
     gain = torch.tensor([d[2] for d in draws], dtype=torch.float32, device=device)

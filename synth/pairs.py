@@ -246,7 +246,7 @@ def square_pair(seed: int = 0) -> Pair:
 
 
 def _affine_layers_pair(rng, W, H, C, nlayers, seed, recipe, noise, gain_range,
-                        max_t=200.0, max_rot=5.0, scale=(0.9, 1.1)):
+                        max_t=200.0, max_rot=5.0, scale=(0.9, 1.1), motion="skewed"):
     m = int(max_t) + 64
     layers = []
     bg = _texture(rng, H + 2 * m, W + 2 * m, C)
@@ -260,25 +260,29 @@ def _affine_layers_pair(rng, W, H, C, nlayers, seed, recipe, noise, gain_range,
         cx = rng.uniform(0.1 * W, 0.9 * W)
         cy = rng.uniform(0.1 * H, 0.9 * H)
         poly = _star_polygon(rng, cx, cy, mean_r, int(rng.integers(5, 12)))
-        # translation up to max_t per axis, skewed towards small motions
-        # (max_t * u * v^2, u, v ~ U(-1, 1)) so that occlusion stays near a
-        # tenth of the frame instead of a third
+        # translation up to max_t per axis: uniform on [-max_t, max_t]
+        # ("uniform"), or skewed towards small motions (max_t * u * v^2,
+        # u, v ~ U(-1, 1): "skewed"); the same four draws either way
         ux, uy, vx, vy = rng.uniform(-1, 1, 4)
-        f, i = _affine(cx, cy, max_t * ux * vx * vx, max_t * uy * vy * vy,
-                       rng.uniform(-max_rot, max_rot), rng.uniform(*scale))
+        if motion == "uniform":
+            tx, ty = max_t * ux, max_t * uy
+        else:
+            tx, ty = max_t * ux * vx * vx, max_t * uy * vy * vy
+        f, i = _affine(cx, cy, tx, ty, rng.uniform(-max_rot, max_rot), rng.uniform(*scale))
         layers.append(_Layer(tex, m, _polygon_inside(poly), f, i))
     gain = None if gain_range is None else rng.uniform(*gain_range)
     return _render(layers, W, H, C, rng, noise, gain, seed, recipe)
 
 
-def layered_pair(seed: int = 1000, W: int = 1024, H: int = 436, nlayers: int = 6) -> Pair:
+def layered_pair(seed: int = 1000, W: int = 1024, H: int = 436, nlayers: int = 6, motion: str = "uniform") -> Pair:
     """Sintel-shaped RGB pair: 1/f background (translation U(+-10), rotation
     U(+-2 deg), scale U(0.97, 1.03)) plus `nlayers` star polygons of 5..30 %
     area, each with an affine motion about its centroid (translation
-    200 * u * v^2 per axis with u, v ~ U(-1, 1), rotation U(+-5 deg), scale
-    U(0.9, 1.1)); frame-2 gain U(0.9, 1.1) and noise sigma = 2."""
+    U(+-200) per axis, or with motion="skewed" 200 u v^2 with u, v ~ U(-1, 1),
+    which keeps occlusion nearer a tenth of the frame; rotation U(+-5 deg),
+    scale U(0.9, 1.1)); frame-2 gain U(0.9, 1.1) and noise sigma = 2."""
     rng = np.random.default_rng(seed)
-    return _affine_layers_pair(rng, W, H, 3, nlayers, seed, "layered", 2.0, (0.9, 1.1))
+    return _affine_layers_pair(rng, W, H, 3, nlayers, seed, "layered", 2.0, (0.9, 1.1), motion=motion)
 
 
 def driving_pair(seed: int = 2000, W: int = 1242, H: int = 375) -> Pair:
@@ -331,7 +335,7 @@ MIXED_SIZES = ((320, 240), (640, 480), (1024, 436), (1242, 375))
 
 def mixed_pairs(n_pairs: int = 64, seed0: int = 3000, sizes=MIXED_SIZES):
     """Mixed-size batch: sizes uniform over `sizes`, 2..8 affine layers each
-    (layered recipe, RGB)."""
+    (layered recipe, RGB, translations U(+-min(200, W / 5)))."""
     out = []
     for i in range(n_pairs):
         seed = seed0 + i
@@ -339,7 +343,7 @@ def mixed_pairs(n_pairs: int = 64, seed0: int = 3000, sizes=MIXED_SIZES):
         W, H = sizes[int(rng.integers(0, len(sizes)))]
         nl = int(rng.integers(2, 9))
         out.append(_affine_layers_pair(rng, W, H, 3, nl, seed, "mixed", 2.0, (0.9, 1.1),
-                                       max_t=min(200.0, 0.2 * W)))
+                                       max_t=min(200.0, 0.2 * W), motion="uniform"))
     return out
 
 
@@ -367,14 +371,16 @@ def mixed_pairs_subset(indices, seed0: int = 3000, sizes=MIXED_SIZES, workers: i
         return pool.map(_mixed_one, args)
 
 
-def layered_pairs(first_seed: int, count: int = 16, W: int = 1024, H: int = 436, workers: int = 0):
+def layered_pairs(first_seed: int, count: int = 16, W: int = 1024, H: int = 436, workers: int = 0,
+                  motion: str = "uniform"):
     """`count` layered pairs with seeds first_seed .. first_seed + count - 1
     (drawn in a process pool when workers > 0; same bytes either way)."""
+    args = [(first_seed + i, W, H, 6, motion) for i in range(count)]
     if workers <= 0:
-        return [layered_pair(first_seed + i, W, H) for i in range(count)]
+        return [layered_pair(*a) for a in args]
     import multiprocessing as mp
-    with mp.get_context("spawn").Pool(workers) as pool:
-        return pool.starmap(layered_pair, [(first_seed + i, W, H) for i in range(count)])
+    with mp.get_context("spawn").Pool(min(workers, count)) as pool:
+        return pool.starmap(layered_pair, args)
 
 
 def inlier_rate(flow_q: np.ndarray, gt: Pair, Q: int, thresh_px: float = 3.0,
