@@ -224,10 +224,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-reps", type=int, default=3, help="CPU baseline: oracle runs (side by side)")
-    ap.add_argument("--mode", default="pair", choices=("pair", "batch", "outliers"),
+    ap.add_argument("--mode", default="pair", choices=("pair", "batch", "outliers", "ablation"),
                     help="pair: one 1024x436 pair (headline, with every secondary block); batch: 64 mixed-size "
                          "pairs in one batched call alone; outliers: removed outliers vs removed inliers of the "
-                         "filters over epsilon")
+                         "filters over epsilon; ablation: the measures of Table 1 over k, l, R and the fast "
+                         "variant")
     ap.add_argument("--pairs", type=int, default=64, help="batch block: number of mixed-size pairs")
     ap.add_argument("--gen-workers", type=int, default=16,
                     help="processes drawing the synthetic pairs (0 = in-process; use 0 under a profiler)")
@@ -256,8 +257,19 @@ def main():
     # synthetic pairs are drawn before anything touches the GPU (worker
     # processes are started from a process that has not initialised it)
     batch_pairs = eval_pairs = outlier_pairs = None
-    if args.mode == "outliers":
+    if args.mode in ("outliers", "ablation"):
         outlier_pairs = pairs.layered_pairs(OUTLIER_SEED0, args.outlier_pairs, workers=args.gen_workers)
+    if args.mode == "ablation":
+        outlier_pairs = {
+            "layered 1024x436, translations U(+-200) px, noise 2": outlier_pairs,
+            "layered 1024x436, translations U(+-200) px, noise 12": pairs.layered_pairs(
+                OUTLIER_SEED0, args.outlier_pairs, workers=args.gen_workers, noise=12.0),
+            "layered 1024x436, smooth 1/f^2 textures, translations U(+-200) px, noise 4": pairs.layered_pairs(
+                OUTLIER_SEED0, args.outlier_pairs, workers=args.gen_workers, noise=4.0, beta=2.0),
+            "layered 1024x436, smooth 1/f^2.5 textures, translations U(+-200) px, noise 6": pairs.layered_pairs(
+                OUTLIER_SEED0, args.outlier_pairs, workers=args.gen_workers, noise=6.0, beta=2.5),
+            "KITTI-shaped 1242x375 gray (radial expansion to 250 px, flat regions, noise 3)": pairs.driving_pairs(
+                2000, args.outlier_pairs, workers=args.gen_workers)}
     if args.mode == "batch" or (args.mode == "pair" and not args.no_batch):
         batch_pairs = (pairs.mixed_pairs_parallel(args.pairs, workers=args.gen_workers) if args.gen_workers > 0
                        else pairs.mixed_pairs(args.pairs))
@@ -280,6 +292,8 @@ def main():
         return
     if args.mode == "outliers":
         return bench_outliers(args, ff, outlier_pairs, torch, dev)
+    if args.mode == "ablation":
+        return bench_ablation(args, ff, outlier_pairs, torch, dev)
     if args.calib_copy_mib:
         src = torch.ones(args.calib_copy_mib << 18, dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)
@@ -608,6 +622,74 @@ def bench_outliers(args, ff, prs, torch, dev, outlier_px=5.0, s=SPARSE_S):
             "pixels_with_flow": n_out + n_in, "outlier_share_pct": round(100.0 * n_out / max(n_out + n_in, 1), 3),
             "curve_eps_removed_outliers_pct_removed_inliers_pct": curve}
     print(json.dumps(line), flush=True)
+
+
+ABLATION = (
+    ("k=3 (paper's setting)", dict(k=3)),
+    ("k=2", dict(k=2)),
+    ("k=1", dict(k=1)),
+    ("k=0 (no hierarchy)", dict(k=0)),
+    ("k=3, l=4", dict(k=3, leaf=4)),
+    ("k=3, l=16", dict(k=3, leaf=16)),
+    ("k=3, R=2", dict(k=3, R=2)),
+    ("k=3, r=6, one backward field (fast variant)", dict(k=3, r=6, r2=6, n_bwd=1)),
+)
+
+
+def bench_ablation(args, ff, workloads, torch, dev):
+    """The measures of Table 1 (section 4.1) on synthetic ground truth for
+    the settings the paper varies: the share of F's flows within 3 px of the
+    truth, the end-point error bounded at 10 px per flow (EPE10) and the raw
+    end-point error, over non-occluded pixels, plus the kept share and the
+    throughput of the whole path.  An empty flow counts as wrong, with an
+    error of 10 px in EPE10 and left out of EPE.  One table per workload."""
+    tables = {name: ablation_rows(ff, prs, torch, dev) for name, prs in workloads.items()}
+    line = {"experiment": "Table 1's measures over the search settings on synthetic ground truth",
+            "workload": f"{args.outlier_pairs} pairs per workload, non-occluded pixels; throughput of the whole "
+                        f"path per pair",
+            "tables": tables}
+    print(json.dumps(line), flush=True)
+
+
+def ablation_rows(ff, prs, torch, dev):
+    import numpy as np
+    H, W, C = prs[0].img1.shape if prs[0].img1.ndim == 3 else (*prs[0].img1.shape, 1)
+    eps = 1 if C == 1 else EPS
+    rows = []
+    for name, kw in ABLATION:
+        kk, r, r2, nb = kw.get("k", K), kw.get("r", R), kw.get("r2", R2), kw.get("n_bwd", 2)
+        m = ff.PairMatcher(W, H, C, r=r, r2=r2, k=kk, subpel=Q, eps=eps, n_bwd=nb, leaf=kw.get("leaf", LEAF),
+                           R=kw.get("R", 1))
+        ok = n = 0
+        e10 = e = 0.0
+        n_set = kept = 0
+        ms_tot = 0.0
+        for p in prs:
+            i1, i2 = torch.from_numpy(p.img1).to(dev), torch.from_numpy(p.img2).to(dev)
+            run = lambda: m.run(i1, i2, seed=p.seed)
+            run()
+            run()
+            ms, _, out = time_steps(run, torch, 5)
+            assert all(st == 0 for st in m.status())
+            ms_tot += ms
+            F = out["F"].cpu().numpy()
+            u = F.astype(np.int64) & 0xFFFFFFFF
+            dx = (((u & 0xFFFF) ^ 0x8000) - 0x8000) / Q
+            dy = ((((u >> 16) & 0xFFFF) ^ 0x8000) - 0x8000) / Q
+            valid = F != ff.FF_EMPTY
+            nocc = ~p.occluded
+            epe = np.hypot(dx - p.flow[..., 0], dy - p.flow[..., 1])
+            ok += int((valid & nocc & (epe < 3.0)).sum())
+            n += int(nocc.sum())
+            e10 += float(np.where(valid, np.minimum(epe, 10.0), 10.0)[nocc].sum())
+            e += float(epe[valid & nocc].sum())
+            n_set += int((valid & nocc).sum())
+            kept += int(out["keep"].sum().item())
+        del m
+        rows.append({"setting": name, "le3px_pct": round(100.0 * ok / n, 3), "EPE10": round(e10 / n, 4),
+                     "EPE": round(e / max(n_set, 1), 4), "kept_pct": round(100.0 * kept / (len(prs) * W * H), 3),
+                     "Mpixel_per_s": round(len(prs) * W * H / ms_tot / 1e3, 3)})
+    return rows
 
 
 if __name__ == "__main__":

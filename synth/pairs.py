@@ -62,13 +62,14 @@ class Pair:
 # --------------------------------------------------------------------------
 # textures
 
-def _texture(rng: np.random.Generator, h: int, w: int, channels: int) -> np.ndarray:
-    """1/f noise: white noise -> FFT -> amplitude * 1/max(|k|,1) -> inverse
-    FFT -> stretch the 1st..99th percentile to [0, 255] (float64)."""
+def _texture(rng: np.random.Generator, h: int, w: int, channels: int, beta: float = 1.0) -> np.ndarray:
+    """1/f^beta noise (beta = 1 unless a recipe asks for smoother textures):
+    white noise -> FFT -> amplitude * 1/max(|k|,1)^beta -> inverse FFT ->
+    stretch the 1st..99th percentile to [0, 255] (float64)."""
     out = np.empty((h, w, channels), np.float64)
     ky = np.fft.fftfreq(h)[:, None] * h
     kx = np.fft.rfftfreq(w)[None, :] * w
-    amp = 1.0 / np.maximum(np.sqrt(kx * kx + ky * ky), 1.0)
+    amp = 1.0 / np.maximum(np.sqrt(kx * kx + ky * ky), 1.0) ** beta
     for c in range(channels):
         noise = rng.standard_normal((h, w))
         spec = np.fft.rfft2(noise) * amp
@@ -246,15 +247,15 @@ def square_pair(seed: int = 0) -> Pair:
 
 
 def _affine_layers_pair(rng, W, H, C, nlayers, seed, recipe, noise, gain_range,
-                        max_t=200.0, max_rot=5.0, scale=(0.9, 1.1), motion="skewed"):
+                        max_t=200.0, max_rot=5.0, scale=(0.9, 1.1), motion="skewed", beta=1.0):
     m = int(max_t) + 64
     layers = []
-    bg = _texture(rng, H + 2 * m, W + 2 * m, C)
+    bg = _texture(rng, H + 2 * m, W + 2 * m, C, beta)
     f, i = _affine(W / 2, H / 2, rng.uniform(-10, 10), rng.uniform(-10, 10),
                    rng.uniform(-2, 2), rng.uniform(0.97, 1.03))
     layers.append(_Layer(bg, m, lambda xs, ys: np.ones(xs.shape, bool), f, i))
     for _ in range(nlayers):
-        tex = _texture(rng, H + 2 * m, W + 2 * m, C)
+        tex = _texture(rng, H + 2 * m, W + 2 * m, C, beta)
         frac = rng.uniform(0.05, 0.30)
         mean_r = math.sqrt(frac * W * H / math.pi)
         cx = rng.uniform(0.1 * W, 0.9 * W)
@@ -274,15 +275,19 @@ def _affine_layers_pair(rng, W, H, C, nlayers, seed, recipe, noise, gain_range,
     return _render(layers, W, H, C, rng, noise, gain, seed, recipe)
 
 
-def layered_pair(seed: int = 1000, W: int = 1024, H: int = 436, nlayers: int = 6, motion: str = "uniform") -> Pair:
+def layered_pair(seed: int = 1000, W: int = 1024, H: int = 436, nlayers: int = 6, motion: str = "uniform",
+                 noise: float = 2.0, beta: float = 1.0) -> Pair:
     """Sintel-shaped RGB pair: 1/f background (translation U(+-10), rotation
     U(+-2 deg), scale U(0.97, 1.03)) plus `nlayers` star polygons of 5..30 %
     area, each with an affine motion about its centroid (translation
     U(+-200) per axis, or with motion="skewed" 200 u v^2 with u, v ~ U(-1, 1),
     which keeps occlusion nearer a tenth of the frame; rotation U(+-5 deg),
-    scale U(0.9, 1.1)); frame-2 gain U(0.9, 1.1) and noise sigma = 2."""
+    scale U(0.9, 1.1)); frame-2 gain U(0.9, 1.1) and Gaussian noise of
+    standard deviation `noise` (2 in the benchmark recipe).  beta > 1 gives
+    smoother 1/f^beta textures (small patches become ambiguous)."""
     rng = np.random.default_rng(seed)
-    return _affine_layers_pair(rng, W, H, 3, nlayers, seed, "layered", 2.0, (0.9, 1.1), motion=motion)
+    return _affine_layers_pair(rng, W, H, 3, nlayers, seed, "layered", noise, (0.9, 1.1), motion=motion,
+                               beta=beta)
 
 
 def driving_pair(seed: int = 2000, W: int = 1242, H: int = 375) -> Pair:
@@ -360,6 +365,16 @@ def mixed_pairs_parallel(n_pairs: int = 64, seed0: int = 3000, sizes=MIXED_SIZES
         return pool.map(_mixed_one, [(i, seed0, sizes) for i in range(n_pairs)])
 
 
+def driving_pairs(first_seed: int, count: int = 8, workers: int = 0):
+    """`count` KITTI-shaped pairs with seeds first_seed .. first_seed + count - 1."""
+    seeds = [first_seed + i for i in range(count)]
+    if workers <= 0:
+        return [driving_pair(s) for s in seeds]
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(min(workers, count)) as pool:
+        return pool.map(driving_pair, seeds)
+
+
 def mixed_pairs_subset(indices, seed0: int = 3000, sizes=MIXED_SIZES, workers: int = 8):
     """Pairs `indices` of the mixed-size batch (pair i depends only on its
     seed seed0 + i), drawn in a process pool when workers > 0."""
@@ -372,10 +387,10 @@ def mixed_pairs_subset(indices, seed0: int = 3000, sizes=MIXED_SIZES, workers: i
 
 
 def layered_pairs(first_seed: int, count: int = 16, W: int = 1024, H: int = 436, workers: int = 0,
-                  motion: str = "uniform"):
+                  motion: str = "uniform", noise: float = 2.0, beta: float = 1.0):
     """`count` layered pairs with seeds first_seed .. first_seed + count - 1
     (drawn in a process pool when workers > 0; same bytes either way)."""
-    args = [(first_seed + i, W, H, 6, motion) for i in range(count)]
+    args = [(first_seed + i, W, H, 6, motion, noise, beta) for i in range(count)]
     if workers <= 0:
         return [layered_pair(*a) for a in args]
     import multiprocessing as mp
