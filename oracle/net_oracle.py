@@ -146,10 +146,15 @@ def masked_l1(out, labels_px):
     return loss, grad
 
 
-def backward(theta, acts, gout, exact=False):
-    """Parameter gradient (float64, parameter layout) from dL/d(out)."""
+def backward(theta, acts, gout, exact=False, magnitude=False):
+    """Parameter gradient (float64, parameter layout) from dL/d(out).  With
+    magnitude=True also the gradient's magnitude in the same layout: each
+    weight's sum of |input activation| x |output gradient| over its products
+    and each bias's sum of |output gradient| (the scale of the rounding
+    error a sum of those products can carry)."""
     params = split_params(theta)
     grads = [None] * len(LAYERS)
+    mags = [None] * len(LAYERS)
     g = gout
     for li in range(len(LAYERS) - 1, -1, -1):
         ci, co, s, d, relu = LAYERS[li]
@@ -160,8 +165,22 @@ def backward(theta, acts, gout, exact=False):
             g = bf16(g, exact)
         gx, dW, db = conv_backward(acts[li], bf16(W, exact), g, s, d)
         grads[li] = (dW, db)
+        if magnitude:
+            _, mW, mb = conv_backward(np.abs(acts[li]), np.abs(bf16(W, exact)), np.abs(g), s, d)
+            mags[li] = (mW, mb)
         g = gx
-    return np.concatenate([np.concatenate([dW.reshape(-1), db]) for dW, db in grads])
+    flat = np.concatenate([np.concatenate([dW.reshape(-1), db]) for dW, db in grads])
+    if not magnitude:
+        return flat
+    return flat, np.concatenate([np.concatenate([mW.reshape(-1), mb]) for mW, mb in mags])
+
+
+def forward_magnitude(theta, acts):
+    """Per output element of the last layer, the sum of |weight| x |input
+    activation| over its products plus |bias| (the scale of the rounding
+    error the last layer's sum can carry)."""
+    (ci, co, s, d, relu), (W, b) = LAYERS[-1], split_params(theta)[-1]
+    return conv(np.abs(acts[-2]), np.abs(bf16(W)), np.abs(b), s, d)
 
 
 def adam_step(theta, m, v, g, step, lr, b1=0.9, b2=0.999, eps=1e-8):

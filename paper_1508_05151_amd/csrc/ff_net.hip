@@ -7,26 +7,35 @@
 // (32,32,2,1,y) (32,32,1,4,y) (32,32,1,8,y) (32,2,1,1,n); padding =
 // dilation; flow in px = 32 * output.  Weights and activations are bf16,
 // every product sum accumulates in fp32 on the matrix cores
-// (v_mfma_f32_16x16x16_bf16); master weights and Adam state are fp32.
+// (gfx950's v_mfma_f32_16x16x32_bf16: 16 x 16 outputs, 32 products each);
+// master weights and Adam state are fp32.
 //
-// All three convolutions are implicit GEMMs on 16x16 MFMA tiles:
+// All three convolutions are implicit GEMMs on 16x16x32 MFMA tiles:
 //   forward        M = output pixels, N = Cout, K = 9 taps x Cin
 //   backward-data  M = input pixels,  N = Cin,  K = 9 taps x Cout
 //   backward-weight per tap: M = Cout, N = Cin, K = pixels, split over fixed
 //                  pixel chunks and reduced in a fixed order (deterministic)
 // Tensors are NHWC; Cin is padded to 8 (input) or 32 channels so that one
-// lane's 4 consecutive K values are 4 contiguous channels of one tap.
+// lane's 8 consecutive K values are 8 contiguous channels of one tap (one
+// 16-byte load).  Lane l of a 16x16x32 MFMA holds A[m = l % 16][k = 8 (l / 16)
+// .. + 7], B[k = 8 (l / 16) .. + 7][n = l % 16] and D[m = 4 (l / 16) + i][n =
+// l % 16], i = 0..3.  The forward and backward-data kernels stage the layer's
+// packed weight fragments (at most 18 KB) in LDS once per workgroup; every
+// wavefront then runs several 16-pixel tiles against them.
 #include <math.h>
 
 #include "ff_internal.h"
 
 namespace ff {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kNetLayers = 6;
 constexpr int kWChunks = 512;   // most backward-weight partials per layer
+constexpr int kKStep = 32;      // K per MFMA
+constexpr int kMaxKChunks = 9;  // 9 taps x 32 channels / 32
+constexpr int kTilesPerWave = 4;   // 16-pixel tiles per wavefront (forward, backward-data)
 
 struct NetLayer {
   int cin, cout, stride, dil, relu;
@@ -49,19 +58,20 @@ static int param_offset(int layer) {
   return o;
 }
 static int param_total() { return param_offset(kNetLayers); }
-static int chunks_of(int cinp) { return (9 * cinp + 15) / 16; }
+static int chunks_of(int cinp) { return (9 * cinp + kKStep - 1) / kKStep; }
 static int tiles_of(int c) { return (c + 15) / 16; }
 
 // ---------------------------------------------------------------- packing
-// forward B fragments: Wb[c][nt][g][n][i] = W[co = 16 nt + n][ci][tap] for
-// K index k = 16 c + 4 g + i = tap * cinp + ci (zero where out of range)
+// forward B fragments, one 16-byte fragment per (chunk, tile, lane):
+// Wb[c][nt][g][n][i] = W[co = 16 nt + n][ci][tap] for K index
+// k = 32 c + 8 g + i = tap * cinp + ci (zero where out of range)
 __global__ void k_pack_fwd(const float* __restrict__ theta, int off, int cin, int cout, int cinp, int nchunks,
                            int ntiles, uint16_t* __restrict__ wb) {
-  const int total = nchunks * ntiles * 4 * 16 * 4;
+  const int total = nchunks * ntiles * 64 * 8;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
-    const int i = e & 3, n = (e >> 2) & 15, g = (e >> 6) & 3, rest = e >> 8;
+    const int i = e & 7, n = (e >> 3) & 15, g = (e >> 7) & 3, rest = e >> 9;
     const int nt = rest % ntiles, c = rest / ntiles;
-    const int k = 16 * c + 4 * g + i;
+    const int k = kKStep * c + 8 * g + i;
     const int tap = k / cinp, ci = k % cinp, co = 16 * nt + n;
     float w = 0.f;
     if (tap < 9 && ci < cin && co < cout) w = theta[off + (co * cin + ci) * 9 + tap];
@@ -72,11 +82,11 @@ __global__ void k_pack_fwd(const float* __restrict__ theta, int off, int cin, in
 // backward-data B fragments: K index k = tap * coutp + co, N = ci
 __global__ void k_pack_bwd(const float* __restrict__ theta, int off, int cin, int cout, int coutp, int nchunks,
                            int ntiles, uint16_t* __restrict__ wb) {
-  const int total = nchunks * ntiles * 4 * 16 * 4;
+  const int total = nchunks * ntiles * 64 * 8;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
-    const int i = e & 3, n = (e >> 2) & 15, g = (e >> 6) & 3, rest = e >> 8;
+    const int i = e & 7, n = (e >> 3) & 15, g = (e >> 7) & 3, rest = e >> 9;
     const int nt = rest % ntiles, c = rest / ntiles;
-    const int k = 16 * c + 4 * g + i;
+    const int k = kKStep * c + 8 * g + i;
     const int tap = k / coutp, co = k % coutp, ci = 16 * nt + n;
     float w = 0.f;
     if (tap < 9 && co < cout && ci < cin) w = theta[off + (co * cin + ci) * 9 + tap];
@@ -105,66 +115,70 @@ __global__ void k_pack_input(const uint8_t* __restrict__ i1, const uint8_t* __re
   }
 }
 
-__device__ __forceinline__ bf16x4 ld_bf16x4(const uint16_t* p) {
-  const uint2 u = *reinterpret_cast<const uint2*>(p);
-  bf16x4 r;
-  r[0] = (short)(u.x & 0xFFFF);
-  r[1] = (short)(u.x >> 16);
-  r[2] = (short)(u.y & 0xFFFF);
-  r[3] = (short)(u.y >> 16);
-  return r;
+// eight bf16 (16 bytes, 16-byte aligned) as an MFMA operand
+__device__ __forceinline__ bf16x8 ld_bf16x8(const uint16_t* p) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
+}
+__device__ __forceinline__ bf16x8 bf16x8_of(uint4 u) { return __builtin_bit_cast(bf16x8, u); }
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
 // ---------------------------------------------------------------- forward
-// One wavefront = 16 output pixels x NT*16 output channels.  Epilogue adds
-// the bias, applies ReLU and stores bf16 (or fp32 for the last layer).
+// One wavefront = kTilesPerWave tiles of 16 output pixels x NT*16 output
+// channels, against the layer's weight fragments staged in LDS.  Epilogue
+// adds the bias, applies ReLU and stores bf16 (or fp32 for the last layer).
 template <int NT>
 __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x, int Bn, int H, int W, int cinp,
                                                   int Ho, int Wo, int stride, int dil, int nchunks,
-                                                  const uint16_t* __restrict__ wb, const float* __restrict__ bias,
+                                                  const uint4* __restrict__ wb, const float* __restrict__ bias,
                                                   int cout, int coutp, int relu, uint16_t* __restrict__ y,
                                                   float* __restrict__ yf) {
+  __shared__ uint4 sW[kMaxKChunks * NT * 64];
+  for (int e = threadIdx.x; e < nchunks * NT * 64; e += blockDim.x) sW[e] = wb[e];
+  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const size_t npx = (size_t)Bn * Ho * Wo;
-  const size_t base = ((size_t)blockIdx.x * 4 + wave) * 16;
-  if (base >= npx) return;
   const int m = lane & 15, g = lane >> 4;
-  const size_t p = base + m;
-  const bool pv = p < npx;
-  const int ox = pv ? (int)(p % Wo) : 0;
-  const int oy = pv ? (int)((p / Wo) % Ho) : 0;
-  const int b = pv ? (int)(p / ((size_t)Wo * Ho)) : 0;
-  f32x4 acc[NT];
+  for (int ti = 0; ti < kTilesPerWave; ++ti) {
+    const size_t base = (((size_t)blockIdx.x * 4 + wave) * kTilesPerWave + ti) * 16;
+    if (base >= npx) break;
+    const size_t p = base + m;
+    const bool pv = p < npx;
+    const int ox = pv ? (int)(p % Wo) : 0;
+    const int oy = pv ? (int)((p / Wo) % Ho) : 0;
+    const int b = pv ? (int)(p / ((size_t)Wo * Ho)) : 0;
+    f32x4 acc[NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int c = 0; c < nchunks; ++c) {
-    const int k0 = 16 * c + 4 * g;
-    const int tap = k0 / cinp, ci0 = k0 % cinp;
-    bf16x4 a = bf16x4{0, 0, 0, 0};
-    if (pv && tap < 9) {
-      const int iy = oy * stride - dil + (tap / 3) * dil, ix = ox * stride - dil + (tap % 3) * dil;
-      if (iy >= 0 && iy < H && ix >= 0 && ix < W) a = ld_bf16x4(x + (((size_t)b * H + iy) * W + ix) * cinp + ci0);
+    for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < nchunks; ++c) {
+      const int k0 = kKStep * c + 8 * g;
+      const int tap = k0 / cinp, ci0 = k0 % cinp;
+      uint4 av = make_uint4(0, 0, 0, 0);
+      if (pv && tap < 9) {
+        const int iy = oy * stride - dil + (tap / 3) * dil, ix = ox * stride - dil + (tap % 3) * dil;
+        if (iy >= 0 && iy < H && ix >= 0 && ix < W)
+          av = *reinterpret_cast<const uint4*>(x + (((size_t)b * H + iy) * W + ix) * cinp + ci0);
+      }
+      const bf16x8 a = bf16x8_of(av);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = mfma32(a, bf16x8_of(sW[(c * NT + t) * 64 + lane]), acc[t]);
     }
+    // D[row = 4 g + i][col = m]: pixel base + 4 g + i, channel 16 t + m
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const bf16x4 bb = ld_bf16x4(wb + ((((size_t)c * NT + t) * 4 + g) * 16 + m) * 4);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[t], 0, 0, 0);
-    }
-  }
-  // D[row = 4 g + i][col = m]: pixel base + 4 g + i, channel 16 t + m
+      const int co = 16 * t + m;
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int co = 16 * t + m;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const size_t q = base + 4 * g + i;
-      if (q >= npx || co >= coutp) continue;
-      float v = co < cout ? acc[t][i] + bias[co] : 0.f;
-      if (relu) v = fmaxf(v, 0.f);
-      if (yf) {
-        if (co < cout) yf[q * cout + co] = v;
-      } else {
-        y[q * coutp + co] = f2bf(v);
+      for (int i = 0; i < 4; ++i) {
+        const size_t q = base + 4 * g + i;
+        if (q >= npx || co >= coutp) continue;
+        float v = co < cout ? acc[t][i] + bias[co] : 0.f;
+        if (relu) v = fmaxf(v, 0.f);
+        if (yf) {
+          if (co < cout) yf[q * cout + co] = v;
+        } else {
+          y[q * coutp + co] = f2bf(v);
+        }
       }
     }
   }
@@ -174,51 +188,54 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x
 // dX[q][ci] = sum over taps and co of G[p(q, tap)][co] W[co][ci][tap], with
 // p = ((y + dil - ky dil) / s, (x + dil - kx dil) / s) where divisible and
 // inside; then the ReLU of the producing layer: stored gradient =
-// dX * (Aprev > 0), bf16.
+// dX * (Aprev > 0), bf16.  Tiles and LDS staging as in the forward kernel.
 template <int NT>
 __global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t* __restrict__ G, int Bn, int Ho, int Wo, int coutp,
                                                        int H, int W, int stride, int dil, int nchunks,
-                                                       const uint16_t* __restrict__ wbt, int cinp,
+                                                       const uint4* __restrict__ wbt, int cinp,
                                                        const uint16_t* __restrict__ aprev, uint16_t* __restrict__ gprev) {
+  __shared__ uint4 sW[kMaxKChunks * NT * 64];
+  for (int e = threadIdx.x; e < nchunks * NT * 64; e += blockDim.x) sW[e] = wbt[e];
+  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const size_t npx = (size_t)Bn * H * W;
-  const size_t base = ((size_t)blockIdx.x * 4 + wave) * 16;
-  if (base >= npx) return;
   const int m = lane & 15, g = lane >> 4;
-  const size_t q = base + m;
-  const bool qv = q < npx;
-  const int x = qv ? (int)(q % W) : 0;
-  const int y = qv ? (int)((q / W) % H) : 0;
-  const int b = qv ? (int)(q / ((size_t)W * H)) : 0;
-  f32x4 acc[NT];
+  for (int ti = 0; ti < kTilesPerWave; ++ti) {
+    const size_t base = (((size_t)blockIdx.x * 4 + wave) * kTilesPerWave + ti) * 16;
+    if (base >= npx) break;
+    const size_t q = base + m;
+    const bool qv = q < npx;
+    const int x = qv ? (int)(q % W) : 0;
+    const int y = qv ? (int)((q / W) % H) : 0;
+    const int b = qv ? (int)(q / ((size_t)W * H)) : 0;
+    f32x4 acc[NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int c = 0; c < nchunks; ++c) {
-    const int k0 = 16 * c + 4 * g;
-    const int tap = k0 / coutp, co0 = k0 % coutp;
-    bf16x4 a = bf16x4{0, 0, 0, 0};
-    if (qv && tap < 9) {
-      const int ty = y + dil - (tap / 3) * dil, tx = x + dil - (tap % 3) * dil;
-      if (ty >= 0 && tx >= 0 && ty % stride == 0 && tx % stride == 0) {
-        const int oy = ty / stride, ox = tx / stride;
-        if (oy < Ho && ox < Wo) a = ld_bf16x4(G + (((size_t)b * Ho + oy) * Wo + ox) * coutp + co0);
+    for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < nchunks; ++c) {
+      const int k0 = kKStep * c + 8 * g;
+      const int tap = k0 / coutp, co0 = k0 % coutp;
+      uint4 av = make_uint4(0, 0, 0, 0);
+      if (qv && tap < 9) {
+        const int ty = y + dil - (tap / 3) * dil, tx = x + dil - (tap % 3) * dil;
+        if (ty >= 0 && tx >= 0 && ty % stride == 0 && tx % stride == 0) {
+          const int oy = ty / stride, ox = tx / stride;
+          if (oy < Ho && ox < Wo) av = *reinterpret_cast<const uint4*>(G + (((size_t)b * Ho + oy) * Wo + ox) * coutp + co0);
+        }
       }
+      const bf16x8 a = bf16x8_of(av);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = mfma32(a, bf16x8_of(sW[(c * NT + t) * 64 + lane]), acc[t]);
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const bf16x4 bb = ld_bf16x4(wbt + ((((size_t)c * NT + t) * 4 + g) * 16 + m) * 4);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[t], 0, 0, 0);
-    }
-  }
+      const int ci = 16 * t + m;
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int ci = 16 * t + m;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const size_t r = base + 4 * g + i;
-      if (r >= npx || ci >= cinp) continue;
-      const float mask = bf2f(aprev[r * cinp + ci]) > 0.f ? 1.f : 0.f;
-      gprev[r * cinp + ci] = f2bf(acc[t][i] * mask);
+      for (int i = 0; i < 4; ++i) {
+        const size_t r = base + 4 * g + i;
+        if (r >= npx || ci >= cinp) continue;
+        const float mask = bf2f(aprev[r * cinp + ci]) > 0.f ? 1.f : 0.f;
+        gprev[r * cinp + ci] = f2bf(acc[t][i] * mask);
+      }
     }
   }
 }
@@ -227,15 +244,17 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t* __restric
 // Block = one fixed chunk of `chunk` output pixels (a multiple of 64, chosen
 // per layer so that a launch has up to kWChunks blocks); for every tap:
 // part[chunk][tap][co][ci] = sum_p G[p][co] X[p_in(p, tap)][ci] on MFMA
-// (A = G^T from LDS, B = X_tap from LDS), bias partial sum_p G[p][co].
-// Wave w handles taps w, w + 4, w + 8.  Staging reads 8 channels (16 bytes)
-// per load and transposes them into channel-major LDS rows.
+// (A = G^T from LDS, B = X_tap from LDS, K = pixels, 8 per lane), bias
+// partial sum_p G[p][co].  Wave w handles taps w, w + 4, w + 8.  Staging
+// reads 8 channels (16 bytes) per load and transposes them into
+// channel-major LDS rows (pitch 72: rows start 16-byte aligned).
+constexpr int kWPitch = 64 + 8;
 __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__ G, int Bn, int Ho, int Wo, int coutp,
                                                     const uint16_t* __restrict__ X, int H, int W, int cinp, int stride,
                                                     int dil, int chunk, float* __restrict__ part,
                                                     float* __restrict__ partb) {
-  __shared__ __align__(16) uint16_t sG[32][64 + 4];      // [co][pixel]
-  __shared__ __align__(16) uint16_t sX[9][32][64 + 4];   // [tap][ci][pixel]
+  __shared__ __align__(16) uint16_t sG[32][kWPitch];      // [co][pixel]
+  __shared__ __align__(16) uint16_t sX[9][32][kWPitch];   // [tap][ci][pixel]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m = lane & 15, g = lane >> 4;
   const size_t npx = (size_t)Bn * Ho * Wo;
@@ -251,8 +270,8 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__
   float bsum = 0.f;   // thread t < coutp: bias partial of channel t
   __shared__ int sPix[64][3];   // b, oy, ox of the 64 staged output pixels
   // channel rows beyond the padded channel counts stay zero
-  for (int e = threadIdx.x; e < 32 * 68; e += 256) (&sG[0][0])[e] = 0;
-  for (int e = threadIdx.x; e < 9 * 32 * 68; e += 256) (&sX[0][0][0])[e] = 0;
+  for (int e = threadIdx.x; e < 32 * kWPitch; e += 256) (&sG[0][0])[e] = 0;
+  for (int e = threadIdx.x; e < 9 * 32 * kWPitch; e += 256) (&sX[0][0][0])[e] = 0;
   const int gq = coutp / 8, xq = cinp / 8;   // 16-byte quads per pixel
   for (size_t s0 = c0; s0 < c0 + chunk && s0 < npx; s0 += 64) {
     if (threadIdx.x < 64) {
@@ -288,8 +307,8 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__
     if ((int)threadIdx.x < coutp)
       for (int px = 0; px < 64; ++px) bsum += bf2f(sG[threadIdx.x][px]);
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const int pk = 16 * ks + 4 * g;   // this lane's 4 pixels
+    for (int ks = 0; ks < 64 / kKStep; ++ks) {
+      const int pk = kKStep * ks + 8 * g;   // this lane's 8 pixels
 #pragma unroll
       for (int ti = 0; ti < 3; ++ti) {
         const int tap = wave + 4 * ti;
@@ -297,12 +316,11 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
           if (mt >= MT) continue;
-          const bf16x4 a = ld_bf16x4(&sG[16 * mt + m][pk]);
+          const bf16x8 a = ld_bf16x8(&sG[16 * mt + m][pk]);
 #pragma unroll
           for (int nt = 0; nt < 2; ++nt) {
             if (nt >= NTt) continue;
-            const bf16x4 bb = ld_bf16x4(&sX[tap][16 * nt + m][pk]);
-            acc[ti][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[ti][mt][nt], 0, 0, 0);
+            acc[ti][mt][nt] = mfma32(a, ld_bf16x8(&sX[tap][16 * nt + m][pk]), acc[ti][mt][nt]);
           }
         }
       }
@@ -328,20 +346,26 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__
   if (threadIdx.x < 32) partb[(size_t)blockIdx.x * 32 + threadIdx.x] = (int)threadIdx.x < coutp ? bsum : 0.f;
 }
 
-// fixed-order reduction of the partials into the parameter-layout gradient
+// fixed-order reduction of the partials into the parameter-layout gradient:
+// thread e owns partial slot e = (tap * 32 + co) * 32 + ci, so the threads
+// of a wavefront read consecutive words of each chunk's partials
 __global__ void k_reduce_w(const float* __restrict__ part, const float* __restrict__ partb, int nchunk, int cin,
                            int cout, int off, float* __restrict__ grad) {
-  const int nw = cout * cin * 9;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nw + cout; e += gridDim.x * blockDim.x) {
-    float s = 0.f;
-    if (e < nw) {
-      const int tap = e % 9, ci = (e / 9) % cin, co = e / (9 * cin);
-      for (int c = 0; c < nchunk; ++c) s += part[(((size_t)c * 9 + tap) * 32 + co) * 32 + ci];
+  constexpr int kSlots = 9 * 32 * 32;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < kSlots + 32; e += gridDim.x * blockDim.x) {
+    if (e < kSlots) {
+      const int ci = e % 32, co = (e / 32) % 32, tap = e / (32 * 32);
+      if (ci >= cin || co >= cout) continue;
+      float s = 0.f;
+      for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * kSlots + e];
+      grad[off + (co * cin + ci) * 9 + tap] = s;
     } else {
-      const int co = e - nw;
+      const int co = e - kSlots;
+      if (co >= cout) continue;
+      float s = 0.f;
       for (int c = 0; c < nchunk; ++c) s += partb[(size_t)c * 32 + co];
+      grad[off + cout * cin * 9 + co] = s;
     }
-    grad[off + e] = s;
   }
 }
 
@@ -454,8 +478,8 @@ static NetPlan net_plan(int Bn, int W, int H) {
   }
   size_t maxpx = 0;
   for (int l = 0; l < kNetLayers; ++l) {
-    P.off_wb[l] = take((size_t)chunks_of(kNet[l].cinp) * tiles_of(kNet[l].cout) * 256 * 2);
-    P.off_wbt[l] = take((size_t)chunks_of(kNet[l].coutp) * tiles_of(kNet[l].cin) * 256 * 2);
+    P.off_wb[l] = take((size_t)chunks_of(kNet[l].cinp) * tiles_of(kNet[l].cout) * 64 * 16);
+    P.off_wbt[l] = take((size_t)chunks_of(kNet[l].coutp) * tiles_of(kNet[l].cin) * 64 * 16);
     maxpx = std::max(maxpx, (size_t)Bn * P.H[l + 1] * P.W[l + 1]);
   }
   (void)maxpx;
@@ -484,16 +508,17 @@ static void enqueue_forward(const NetPlan& P, int Bn, const float* theta, const 
     k_pack_fwd<<<64, 256, 0, s>>>(theta, param_offset(l), L.cin, L.cout, L.cinp, nch, nt, wb);
     const float* bias = theta + param_offset(l) + L.cout * L.cin * 9;
     const size_t npx = (size_t)Bn * P.H[l + 1] * P.W[l + 1];
-    const unsigned blocks = (unsigned)((npx + 63) / 64);
+    const unsigned blocks = (unsigned)((npx + 64 * kTilesPerWave - 1) / (64 * kTilesPerWave));
     const uint16_t* xin = reinterpret_cast<const uint16_t*>(ws + P.off_x[l]);
     uint16_t* yout = l + 1 < kNetLayers ? reinterpret_cast<uint16_t*>(ws + P.off_x[l + 1]) : nullptr;
     float* yf = l + 1 == kNetLayers ? reinterpret_cast<float*>(ws + P.off_x[l + 1]) : nullptr;
+    const uint4* wbv = reinterpret_cast<const uint4*>(wb);
     if (nt == 2)
       k_conv_fwd<2><<<blocks, 256, 0, s>>>(xin, Bn, P.H[l], P.W[l], L.cinp, P.H[l + 1], P.W[l + 1], L.stride, L.dil, nch,
-                                           wb, bias, L.cout, L.coutp, L.relu, yout, yf);
+                                           wbv, bias, L.cout, L.coutp, L.relu, yout, yf);
     else
       k_conv_fwd<1><<<blocks, 256, 0, s>>>(xin, Bn, P.H[l], P.W[l], L.cinp, P.H[l + 1], P.W[l + 1], L.stride, L.dil, nch,
-                                           wb, bias, L.cout, L.coutp, L.relu, yout, yf);
+                                           wbv, bias, L.cout, L.coutp, L.relu, yout, yf);
   }
 }
 
@@ -584,15 +609,16 @@ ff_status ff_proposal_train_step(float* params, float* adam_m, float* adam_v, in
       uint16_t* wbt = reinterpret_cast<uint16_t*>(ws + P.off_wbt[l]);
       k_pack_bwd<<<64, 256, 0, stream>>>(params, param_offset(l), L.cin, L.cout, gch, nchb, ntb, wbt);
       const size_t nin = (size_t)batch * P.H[l] * P.W[l];
-      const unsigned blocks = (unsigned)((nin + 63) / 64);
+      const unsigned blocks = (unsigned)((nin + 64 * kTilesPerWave - 1) / (64 * kTilesPerWave));
       uint16_t* gprev = reinterpret_cast<uint16_t*>(ws + P.off_g[l]);
       const uint16_t* aprev = X;
+      const uint4* wbtv = reinterpret_cast<const uint4*>(wbt);
       if (ntb == 2)
         k_conv_bwd_data<2><<<blocks, 256, 0, stream>>>(G, batch, P.H[l + 1], P.W[l + 1], gch, P.H[l], P.W[l], L.stride,
-                                                       L.dil, nchb, wbt, L.cinp, aprev, gprev);
+                                                       L.dil, nchb, wbtv, L.cinp, aprev, gprev);
       else
         k_conv_bwd_data<1><<<blocks, 256, 0, stream>>>(G, batch, P.H[l + 1], P.W[l + 1], gch, P.H[l], P.W[l], L.stride,
-                                                       L.dil, nchb, wbt, L.cinp, aprev, gprev);
+                                                       L.dil, nchb, wbtv, L.cinp, aprev, gprev);
     }
   }
   const int np = param_total();
