@@ -486,6 +486,7 @@ def bench_learned(ff, pair, img1, img2, eval_pairs, torch, dev, plain_value, pla
         assert m.status() == [0, 0, 0], m.status()
         res["pair"][mode] = {"Mpixel_per_s": round(W * H / ms / 1e3, 3),
                              "inlier_F": round(pairs.inlier_rate(out["F"].cpu().numpy(), pair, Q), 4)}
+    res["network"] = network_kernels(ff, net, eval_pairs, torch, dev)
     ev = proposal.evaluate(net, eval_pairs, reps=3, log=lambda s: None)
     res["batch"] = {"workload": f"{len(eval_pairs)} held-out 1024x436 layered pairs (seeds {LEARNED_SEED0}.."
                                 f"{LEARNED_SEED0 + len(eval_pairs) - 1}) in one batched call",
@@ -494,6 +495,58 @@ def bench_learned(ff, pair, img1, img2, eval_pairs, torch, dev, plain_value, pla
                        for m in ("plain", "plain+learned", "learned")},
                     "network_alone_at_seed_points": round(ev["network_only_seed_points"], 4)}
     return res
+
+
+NET_LAYERS = ((6, 32, 2, 1), (32, 32, 2, 1), (32, 32, 2, 1), (32, 32, 1, 4), (32, 32, 1, 8), (32, 2, 1, 1))
+BF16_PEAK_TFLOPS = 2500.0    # dense bf16 MFMA
+
+
+def net_flops(W, H):
+    """Multiply-adds x 2 of one forward pass (the convolutions' products)."""
+    f = 0
+    for ci, co, st, _ in NET_LAYERS:
+        W, H = (W + st - 1) // st, (H + st - 1) // st
+        f += 2 * 9 * ci * co * W * H
+    return f
+
+
+def network_kernels(ff, net, eval_pairs, torch, dev, reps=10):
+    """The network's forward pass over the batch (both directions, as the
+    learned modes run it) and one training step of the batch, against the
+    dense bf16 MFMA peak."""
+    import numpy as np
+    from paper_1508_05151_amd import proposal
+    H, W = eval_pairs[0].img1.shape[:2]
+    i1 = torch.from_numpy(np.stack([p.img1 for p in eval_pairs])).to(dev)
+    i2 = torch.from_numpy(np.stack([p.img2 for p in eval_pairs])).to(dev)
+    B = i1.shape[0]
+    proposal.proposals_both_ways(net, i1, i2)
+    torch.cuda.synchronize()
+    ff.ff_profile_begin("proposal", reps + 2)
+    for _ in range(reps):
+        proposal.proposals_both_ways(net, i1, i2)
+    torch.cuda.synchronize()
+    tot, n, _ = ff.ff_profile_end()
+    fwd_ms = tot / max(n, 1)
+    flops = net_flops(W, H) * 2 * B
+    hc, wc = ff.seed_grid(W, H)
+    labels = torch.zeros((B, hc, wc), dtype=torch.int32, device=dev)
+    g = ff.ProposalNet(net.params.detach().clone(), device=dev)
+    g.gradient(i1, i2, labels)
+    torch.cuda.synchronize()
+    ff.ff_profile_begin("train", reps + 2)
+    for _ in range(reps):
+        g.gradient(i1, i2, labels)
+    torch.cuda.synchronize()
+    tot, n, _ = ff.ff_profile_end()
+    tr_ms = tot / max(n, 1)
+    achieved = flops / (fwd_ms / 1000.0) / 1e12
+    return {"forward_both_directions_ms": round(fwd_ms, 4), "pairs": B,
+            "forward_gflop": round(flops / 1e9, 3), "forward_TFLOPs": round(achieved, 2),
+            "forward_frac_of_bf16_peak": round(achieved / BF16_PEAK_TFLOPS, 4),
+            "train_step_ms": round(tr_ms, 4),
+            "note": "3x3 convolutions of 32 channels at 1/2 to 1/8 resolution: memory- and latency-bound, "
+                    "about 40 FLOP per byte of activations"}
 
 
 def bench_batch(args, ff, prs, torch, dev, steps=None):

@@ -211,7 +211,8 @@ def main(argv=None):
     del data
     torch.cuda.empty_cache()
     meta = dict(pairs=a.pairs, epochs=a.epochs, batch=a.batch, lr=a.lr, init_seed=a.init_seed,
-                train_seed0=TRAIN_SEED0, final_loss=hist[-1][1], seconds=round(time.time() - t0, 1))
+                train_seed0=TRAIN_SEED0, final_loss=hist[-1][1], seconds=round(time.time() - t0, 1),
+                recipe="layered 1024x436, 6 layers, translations U(+-200) px (synth.gpu_pairs, motion=uniform)")
     if a.out:
         save(net, a.out, meta)
         log(f"saved {a.out}")
