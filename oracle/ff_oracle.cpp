@@ -402,9 +402,15 @@ struct MatchParams {
   uint32_t seed_lo, seed_hi, field_id, pair_id;
 };
 
+// The search is written once for any data term: Cost is the cost type
+// (int32 census sums; double for the SIFT-flow term), inf its "infinity",
+// and cost(lev, px, py, fx, fy) evaluates E^n at grid point (px, py) for
+// flow (fx, fy).
+template <class Cost>
 struct Grid {
   int n, Gw, Gh;
-  std::vector<int32_t> F, C;
+  std::vector<int32_t> F;
+  std::vector<Cost> C;
 };
 
 // Sweep directions (Fig. 3c is not in the text): sweep 1 goes right and
@@ -418,7 +424,8 @@ struct Counters {
   void add(int lev) { if (c) { c[0]++; c[1 + lev]++; } }
 };
 
-void propagate(const Desc& s, const Desc& d, int lev, int r, Grid& g, int dir, const MatchParams& P, Counters& cnt) {
+template <class Cost, class CostFn>
+void propagate(const CostFn& cost, int lev, Grid<Cost>& g, int dir, const MatchParams& P, Counters& cnt) {
   const int sx = kSweepX[dir & 3], sy = kSweepY[dir & 3];
   const int n = g.n;
   for (int iy = 0; iy < g.Gh; ++iy) {
@@ -436,7 +443,7 @@ void propagate(const Desc& s, const Desc& d, int lev, int r, Grid& g, int dir, c
         if (fq == kEmpty) continue;
         if (P.skip_dup && fq == g.F[pi]) continue;
         cnt.add(lev);
-        int32_t e = cost_at(s, d, lev, r, gx * n, gy * n, unpack_x(fq), unpack_y(fq));
+        Cost e = cost(lev, gx * n, gy * n, unpack_x(fq), unpack_y(fq));
         if (e < g.C[pi]) { g.F[pi] = fq; g.C[pi] = e; }
       }
     }
@@ -447,10 +454,11 @@ void propagate(const Desc& s, const Desc& d, int lev, int r, Grid& g, int dir, c
 // offset per point, per axis an integer in [-nRQ, nRQ] (1/Q px), drawn with
 // Philox4x32-10 keyed by the seed; counter = (pixel index y W + x, log2 n,
 // step, field | pair << 2).
-void random_search(const Desc& s, const Desc& d, int lev, int r, Grid& g, int step, const MatchParams& P,
+template <class Cost, class CostFn>
+void random_search(const CostFn& cost, int W, int Q, int lev, Grid<Cost>& g, int step, const MatchParams& P,
                    Counters& cnt) {
   const int n = g.n;
-  const int64_t rad = (int64_t)n * P.R * d.Q;
+  const int64_t rad = (int64_t)n * P.R * Q;
   const uint64_t span = (uint64_t)(2 * rad + 1);
   const uint32_t key[2] = {P.seed_lo, P.seed_hi};
   for (int gy = 0; gy < g.Gh; ++gy)
@@ -459,20 +467,21 @@ void random_search(const Desc& s, const Desc& d, int lev, int r, Grid& g, int st
       int32_t f = g.F[pi];
       if (f == kEmpty) continue;
       int px = gx * n, py = gy * n;
-      uint32_t ctr[4] = {(uint32_t)(py * s.W + px), (uint32_t)lev, (uint32_t)step, P.field_id | (P.pair_id << 2)};
+      uint32_t ctr[4] = {(uint32_t)(py * W + px), (uint32_t)lev, (uint32_t)step, P.field_id | (P.pair_id << 2)};
       uint32_t u[4];
       philox4x32_10(ctr, key, u);
       int ox = (int)((int64_t)(((uint64_t)u[0] * span) >> 32) - rad);
       int oy = (int)((int64_t)(((uint64_t)u[1] * span) >> 32) - rad);
       int fx = unpack_x(f) + ox, fy = unpack_y(f) + oy;
       cnt.add(lev);
-      int32_t e = cost_at(s, d, lev, r, px, py, fx, fy);
+      Cost e = cost(lev, px, py, fx, fy);
       if (e < g.C[pi]) { g.F[pi] = pack(fx, fy); g.C[pi] = e; }
     }
 }
 
-void write_grid(const Grid& g, int W, int H, int32_t* flow, int32_t* cost) {
-  for (int i = 0; i < W * H; ++i) { flow[i] = kEmpty; cost[i] = kInf; }
+template <class Cost>
+void write_grid(const Grid<Cost>& g, int W, int H, Cost inf, int32_t* flow, Cost* cost) {
+  for (int i = 0; i < W * H; ++i) { flow[i] = kEmpty; cost[i] = inf; }
   for (int gy = 0; gy < g.Gh; ++gy)
     for (int gx = 0; gx < g.Gw; ++gx) {
       flow[(size_t)gy * g.n * W + gx * g.n] = g.F[(size_t)gy * g.Gw + gx];
@@ -480,24 +489,26 @@ void write_grid(const Grid& g, int W, int H, int32_t* flow, int32_t* cost) {
     }
 }
 
-// The whole search for one field (src -> dst, patch radius r).
+// The whole search for one field (src -> dst, patch radius r) with data
+// term `cost` (section 3.3 allows either term; the search does not change).
 //
 // Steps, counted for max_steps: seeding (1); at the coarsest level P1 RS1 P2
 // RS2 P3 RS3 P4 (section 3.1: 4 propagations and 3 random searches,
 // alternating); at every finer level one level-entry step (carried points
 // re-costed with the new patch, new points empty) and the same seven.
-int match_field(const Desc& s, const Desc& d, int r, const MatchParams& P, const int32_t* proposal,
-                int32_t* flow, int32_t* cost, int64_t* counters) {
+template <class Cost, class CostFn>
+int match_field_t(const Desc& s, const Desc& d, int r, const MatchParams& P, const int32_t* proposal,
+                  const CostFn& cost, Cost inf, int32_t* flow, Cost* out_cost, int64_t* counters) {
   Counters cnt{counters};
   const int K = 1 << P.k;
   int steps = 0;
   auto stop = [&]() { return P.max_steps >= 0 && steps >= P.max_steps; };
-  Grid g;
+  Grid<Cost> g;
   g.n = K;
   g.Gw = (s.W + K - 1) / K;
   g.Gh = (s.H + K - 1) / K;
   g.F.assign((size_t)g.Gw * g.Gh, kEmpty);
-  g.C.assign((size_t)g.Gw * g.Gh, kInf);
+  g.C.assign((size_t)g.Gw * g.Gh, inf);
   // Eq. 1 / Eq. 4: seeds on the coarsest grid from the kd-tree leaf of the
   // source patch's WHT vector, re-ranked by the data term on P^K_r.
   {
@@ -507,7 +518,8 @@ int match_field(const Desc& s, const Desc& d, int r, const MatchParams& P, const
     for (int gy = 0; gy < g.Gh; ++gy)
       for (int gx = 0; gx < g.Gw; ++gx) {
         int px = gx * K, py = gy * K;
-        int32_t bestF = kEmpty, bestC = kInf;
+        int32_t bestF = kEmpty;
+        Cost bestC = inf;
         if (P.use_kdtree) {
           int st, c;
           query_tree(T, Vs + ((size_t)py * s.W + px) * 9 * s.C, st, c);
@@ -515,7 +527,7 @@ int match_field(const Desc& s, const Desc& d, int r, const MatchParams& P, const
             int q = T.perm[st + i];
             int fx = (q % d.W - px) * d.Q, fy = (q / d.W - py) * d.Q;
             cnt.add(P.k);
-            int32_t e = cost_at(s, d, P.k, r, px, py, fx, fy);
+            Cost e = cost(P.k, px, py, fx, fy);
             if (e < bestC) { bestC = e; bestF = pack(fx, fy); }
           }
         }
@@ -523,7 +535,7 @@ int match_field(const Desc& s, const Desc& d, int r, const MatchParams& P, const
           int32_t fp = proposal[(size_t)gy * g.Gw + gx];
           if (fp != kEmpty) {
             cnt.add(P.k);
-            int32_t e = cost_at(s, d, P.k, r, px, py, unpack_x(fp), unpack_y(fp));
+            Cost e = cost(P.k, px, py, unpack_x(fp), unpack_y(fp));
             if (e < bestC) { bestC = e; bestF = fp; }
           }
         }
@@ -532,42 +544,49 @@ int match_field(const Desc& s, const Desc& d, int r, const MatchParams& P, const
       }
   }
   ++steps;
-  if (stop()) { write_grid(g, s.W, s.H, flow, cost); return steps; }
+  if (stop()) { write_grid(g, s.W, s.H, inf, flow, out_cost); return steps; }
   for (int lev = P.k; lev >= 0; --lev) {
     const int n = 1 << lev;
     if (lev < P.k) {
       // Section 3.2: the coarser level's flows seed this level; points that
       // are new on this grid get their first value in the first propagation.
-      Grid ng;
+      Grid<Cost> ng;
       ng.n = n;
       ng.Gw = (s.W + n - 1) / n;
       ng.Gh = (s.H + n - 1) / n;
       ng.F.assign((size_t)ng.Gw * ng.Gh, kEmpty);
-      ng.C.assign((size_t)ng.Gw * ng.Gh, kInf);
+      ng.C.assign((size_t)ng.Gw * ng.Gh, inf);
       for (int gy = 0; gy < ng.Gh; gy += 2)
         for (int gx = 0; gx < ng.Gw; gx += 2) {
           int32_t f = g.F[(size_t)(gy / 2) * g.Gw + gx / 2];
           if (f == kEmpty) continue;
           ng.F[(size_t)gy * ng.Gw + gx] = f;
-          ng.C[(size_t)gy * ng.Gw + gx] = cost_at(s, d, lev, r, gx * n, gy * n, unpack_x(f), unpack_y(f));
+          ng.C[(size_t)gy * ng.Gw + gx] = cost(lev, gx * n, gy * n, unpack_x(f), unpack_y(f));
         }
       g = std::move(ng);
       ++steps;
-      if (stop()) { write_grid(g, s.W, s.H, flow, cost); return steps; }
+      if (stop()) { write_grid(g, s.W, s.H, inf, flow, out_cost); return steps; }
     }
     for (int i = 0; i < P.n_prop; ++i) {
-      propagate(s, d, lev, r, g, i, P, cnt);
+      propagate(cost, lev, g, i, P, cnt);
       ++steps;
-      if (stop()) { write_grid(g, s.W, s.H, flow, cost); return steps; }
+      if (stop()) { write_grid(g, s.W, s.H, inf, flow, out_cost); return steps; }
       if (i < P.n_rs) {
-        random_search(s, d, lev, r, g, i, P, cnt);
+        random_search(cost, s.W, d.Q, lev, g, i, P, cnt);
         ++steps;
-        if (stop()) { write_grid(g, s.W, s.H, flow, cost); return steps; }
+        if (stop()) { write_grid(g, s.W, s.H, inf, flow, out_cost); return steps; }
       }
     }
   }
-  write_grid(g, s.W, s.H, flow, cost);
+  write_grid(g, s.W, s.H, inf, flow, out_cost);
   return steps;
+}
+
+// The census data term of section 3.3 (cost_at above).
+int match_field(const Desc& s, const Desc& d, int r, const MatchParams& P, const int32_t* proposal,
+                int32_t* flow, int32_t* cost, int64_t* counters) {
+  auto census = [&](int lev, int px, int py, int fx, int fy) { return cost_at(s, d, lev, r, px, py, fx, fy); };
+  return match_field_t<int32_t>(s, d, r, P, proposal, census, kInf, flow, cost, counters);
 }
 
 // ---------------------------------------------------------------------------
