@@ -9,7 +9,9 @@
 // no code, header, table or constant generator with it.
 //
 // Everything here is integer arithmetic except the one-time generation of
-// three small tables (sRGB gamma, Lab f(t), Lanczos weights) in double.
+// three small tables (sRGB gamma, Lab f(t), Lanczos weights) in double and
+// the dense SIFT vectors of the second data term (double; the PCA that turns
+// them into integer colour codes is in oracle/ffo.py, NumPy float64).
 // Patch costs are direct sums over the whole patch -- no sliding windows, no
 // blocking, no reordering.  Propagation runs in plain raster order in the
 // sweep direction.  Where the paper is silent, this file takes one reading
@@ -147,10 +149,13 @@ LanczosTable lanczos_table(int n) {
 
 int ilog2(int n) { int l = 0; while ((1 << l) < n) ++l; return l; }
 
-// plane: H x W uint8, out: H x W int16 (Q4)
-void smooth_plane(const uint8_t* J, int W, int H, int n, int16_t* out) {
+// plane: H x W samples, out: H x W int16 with `frac` fractional bits (the
+// census path: uint8 in, Q4 out; the SIFT colours of section 3.3: int16 codes
+// in, the same units out)
+template <class Px>
+void smooth_plane_t(const Px* J, int W, int H, int n, int frac, int16_t* out) {
   if (n == 1) {
-    for (int i = 0; i < W * H; ++i) out[i] = (int16_t)(16 * J[i]);
+    for (int i = 0; i < W * H; ++i) out[i] = (int16_t)(J[i] * (1 << frac));
     return;
   }
   const int Wc = (W + n - 1) / n, Hc = (H + n - 1) / n;
@@ -170,7 +175,7 @@ void smooth_plane(const uint8_t* J, int W, int H, int n, int16_t* out) {
       for (int k = -3; k <= 3; ++k) s += (int64_t)lt.w[x % n][k + 3] * A[(size_t)i * Wc + clampi(x / n + k, 0, Wc - 1)];
       T[(size_t)i * W + x] = floordiv(s + 8192, 16384);
     }
-  const int sh = 14 + 2 * ilog2(n) - 4;
+  const int sh = 14 + 2 * ilog2(n) - frac;
   for (int y = 0; y < H; ++y)
     for (int x = 0; x < W; ++x) {
       int64_t s = 0;
@@ -178,6 +183,8 @@ void smooth_plane(const uint8_t* J, int W, int H, int n, int16_t* out) {
       out[(size_t)y * W + x] = (int16_t)floordiv(s + (1LL << (sh - 1)), 1LL << sh);
     }
 }
+
+void smooth_plane(const uint8_t* J, int W, int H, int n, int16_t* out) { smooth_plane_t(J, W, H, n, 4, out); }
 
 // ---------------------------------------------------------------------------
 // Section 3.3 census data term on the subsampled patches of section 3.2, with
@@ -725,6 +732,144 @@ void sparsify(const int32_t* F, int W1, int H1, const int32_t* const* B, int n_b
     }
 }
 
+// ---------------------------------------------------------------------------
+// Section 3.3, the second data term: patch-based SIFT flow.  Every pixel gets
+// a 128-dimensional SIFT vector (Lowe, IJCV 2004, computed densely and
+// upright as in Liu et al.'s SIFT flow), PCA reduces the vectors to S
+// "colours" (done in Python, oracle/ffo.py), the colour images are smoothed
+// per level as in section 3.2, and the data term sums L2 colour distances
+// over the subsampled patch.  WHTs (the kd-tree seeds) stay on CIELab.
+//
+// Readings (dense SIFT):
+//  - input: the lightness plane of the 8-bit CIELab image (gray passes
+//    through);
+//  - gradient by central differences, coordinates clamped to the image:
+//    gx = (L(x+1,y) - L(x-1,y)) / 2, gy = (L(x,y+1) - L(x,y-1)) / 2, y down;
+//  - orientation atan2(gy, gx) in [0, 2 pi); 8 bins centred at o pi/4, the
+//    magnitude split linearly between the two nearest bins;
+//  - 4 x 4 cells of c = 3 px (SIFT flow's default cell size), cell (i, j)
+//    (i the column) centred at p + ((i - 1.5) c, (j - 1.5) c);
+//  - every sample q = p + (dx, dy) with |dx|, |dy| < 2.5 c (the support of the
+//    bilinear cell weights) inside the image adds its binned magnitude with
+//    weight exp(-(dx^2 + dy^2) / (2 sigma^2)), sigma = 2 c (half the window),
+//    times max(0, 1 - |dx / c - (i - 1.5)|) max(0, 1 - |dy / c - (j - 1.5)|);
+//    samples outside the image add nothing;
+//  - element (4 j + i) 8 + o; the vector is scaled to unit length, clamped at
+//    0.2 and scaled to unit length again (a zero vector stays zero).
+constexpr int kSiftCell = 3;
+constexpr int kSiftReach = 7;   // largest |dx| with a non-zero cell weight: < 2.5 c
+
+void dense_sift(const uint8_t* L, int W, int H, double* out /* N x 128 */) {
+  const double pi = 3.14159265358979323846;
+  const size_t N = (size_t)W * H;
+  std::vector<double> mag(N), tbin(N);
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      auto at = [&](int xx, int yy) { return (double)L[(size_t)clampi(yy, 0, H - 1) * W + clampi(xx, 0, W - 1)]; };
+      double gx = (at(x + 1, y) - at(x - 1, y)) / 2.0, gy = (at(x, y + 1) - at(x, y - 1)) / 2.0;
+      double th = std::atan2(gy, gx);
+      if (th < 0) th += 2 * pi;
+      mag[(size_t)y * W + x] = std::sqrt(gx * gx + gy * gy);
+      tbin[(size_t)y * W + x] = th / (pi / 4);
+    }
+  const double c = kSiftCell, sig = 2.0 * c;
+  for (int py = 0; py < H; ++py)
+    for (int px = 0; px < W; ++px) {
+      double v[128] = {0};
+      for (int dy = -kSiftReach; dy <= kSiftReach; ++dy)
+        for (int dx = -kSiftReach; dx <= kSiftReach; ++dx) {
+          int qx = px + dx, qy = py + dy;
+          if (qx < 0 || qy < 0 || qx >= W || qy >= H) continue;
+          double m = mag[(size_t)qy * W + qx];
+          if (m == 0.0) continue;
+          double t = tbin[(size_t)qy * W + qx];
+          int o0 = (int)std::floor(t);
+          double w1 = t - o0;
+          o0 %= 8;
+          int o1 = (o0 + 1) % 8;
+          double g = std::exp(-(dx * dx + dy * dy) / (2 * sig * sig));
+          for (int j = 0; j < 4; ++j) {
+            double wy = 1.0 - std::fabs(dy / c - (j - 1.5));
+            if (wy <= 0) continue;
+            for (int i = 0; i < 4; ++i) {
+              double wx = 1.0 - std::fabs(dx / c - (i - 1.5));
+              if (wx <= 0) continue;
+              double w = g * wx * wy * m;
+              v[(4 * j + i) * 8 + o0] += w * (1.0 - w1);
+              v[(4 * j + i) * 8 + o1] += w * w1;
+            }
+          }
+        }
+      double nn = 0;
+      for (int e = 0; e < 128; ++e) nn += v[e] * v[e];
+      if (nn > 0) {
+        double s = 1.0 / std::sqrt(nn);
+        nn = 0;
+        for (int e = 0; e < 128; ++e) { v[e] = std::min(v[e] * s, 0.2); nn += v[e] * v[e]; }
+        s = 1.0 / std::sqrt(nn);
+        for (int e = 0; e < 128; ++e) v[e] *= s;
+      }
+      std::copy(v, v + 128, out + ((size_t)py * W + px) * 128);
+    }
+}
+
+// Smoothed colour images of one image: (k+1) levels x S planes of int16
+// codes (the PCA colours quantised in oracle/ffo.py), level j smoothed with
+// n = 2^j by smooth_plane_t (section 3.2's smoothing on integer codes, output
+// in code units).
+struct SiftLevels {
+  int W = 0, H = 0, S = 0, k = 0;
+  std::vector<std::vector<int16_t>> lev;   // [level] S planes of H x W
+  const int16_t* plane(int l, int s) const { return lev[l].data() + (size_t)s * W * H; }
+};
+
+// Readings (data term): E^n_r(p, f) is the sum over the (2r+1)^2 samples at
+// stride n of the L2 distance of the S colours (the first S of the stored
+// channels).  The target colour at the subpixel centre m = pQ + f is bilinear
+// in the four neighbours of floor(m / Q) + n delta (weights (Q-a)(Q-b),
+// a(Q-b), (Q-a)b, ab for the phase (a, b) = m mod Q; the +1 neighbours clamp
+// to the image), the source colour is scaled by Q^2 to the same units, and a
+// sample's distance is floor(sqrt(sum_s d_s^2 * 256 / Q^4)) (1/16 code units
+// at every Q; exact integer square root, floor division for Q = 8).  Validity
+// of f and lookup clamping as cost_at.
+int32_t sift_cost_at(const SiftLevels& s, const SiftLevels& d, int Q, int lev, int r, int S, int px, int py, int fx,
+                     int fy) {
+  const int n = 1 << lev;
+  int64_t mx = (int64_t)px * Q + fx, my = (int64_t)py * Q + fy;
+  if (mx < 0 || my < 0 || mx > (int64_t)(d.W - 1) * Q || my > (int64_t)(d.H - 1) * Q) return kInf;
+  int Mx = (int)floordiv(mx, Q), My = (int)floordiv(my, Q);
+  int a = (int)(mx - (int64_t)Mx * Q), b = (int)(my - (int64_t)My * Q);
+  const int64_t Q4 = (int64_t)Q * Q * Q * Q;
+  int64_t total = 0;
+  for (int dy = -r; dy <= r; ++dy)
+    for (int dx = -r; dx <= r; ++dx) {
+      size_t ps = (size_t)clampi(py + n * dy, 0, s.H - 1) * s.W + clampi(px + n * dx, 0, s.W - 1);
+      int X = clampi(Mx + n * dx, 0, d.W - 1), Y = clampi(My + n * dy, 0, d.H - 1);
+      int X1 = std::min(X + 1, d.W - 1), Y1 = std::min(Y + 1, d.H - 1);
+      int64_t ss = 0;
+      for (int ch = 0; ch < S; ++ch) {
+        const int16_t* P1 = s.plane(lev, ch);
+        const int16_t* P2 = d.plane(lev, ch);
+        int64_t t = (int64_t)(Q - a) * (Q - b) * P2[(size_t)Y * d.W + X] + (int64_t)a * (Q - b) * P2[(size_t)Y * d.W + X1] +
+                    (int64_t)(Q - a) * b * P2[(size_t)Y1 * d.W + X] + (int64_t)a * b * P2[(size_t)Y1 * d.W + X1];
+        int64_t e = (int64_t)Q * Q * P1[ps] - t;
+        ss += e * e;
+      }
+      total += (int64_t)isqrt64((uint64_t)(Q <= 4 ? ss * (256 / Q4) : ss / (Q4 / 256)));
+    }
+  return (int32_t)total;
+}
+
+// The search of match_field_t with the SIFT-flow data term: seeds from the
+// kd-tree over the CIELab WHTs of s / d (census descriptors), costs from the
+// colour levels ss / sd.
+int match_field_sift(const Desc& s, const Desc& d, const SiftLevels& ss, const SiftLevels& sd, int r, int S,
+                     const MatchParams& P, int32_t* flow, int32_t* cost, int64_t* counters) {
+  const int Q = d.Q;
+  auto sift = [&](int lev, int px, int py, int fx, int fy) { return sift_cost_at(ss, sd, Q, lev, r, S, px, py, fx, fy); };
+  return match_field_t<int32_t>(s, d, r, P, nullptr, sift, kInf, flow, cost, counters);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -954,4 +1099,75 @@ int ffo_brute_nnf(void* hs, void* hd, int lev, int r, int32_t* flow, int32_t* co
   return 0;
 }
 
+// ---------------------------------------------------------------------------
+// SIFT-flow data term (section 3.3, see dense_sift and sift_cost_at above).
+
+// L: H x W lightness plane; out: H x W x 128 doubles.
+int ffo_dense_sift(const uint8_t* L, int W, int H, double* out) {
+  if (!L || !out || W <= 0 || H <= 0) return -1;
+  dense_sift(L, W, H, out);
+  return 0;
+}
+
+// One int16 plane smoothed with n (power of two, <= 16), output in the
+// input's units.
+int ffo_smooth_codes(const int16_t* plane, int W, int H, int n, int16_t* out) {
+  if (!plane || !out || W <= 0 || H <= 0 || n < 1 || n > 16 || (n & (n - 1))) return -1;
+  smooth_plane_t(plane, W, H, n, 0, out);
+  return 0;
+}
+
+// codes: H x W x S int16 (channels last).  Levels 0..k.
+void* ffo_sift_levels_create(const int16_t* codes, int W, int H, int S, int k) {
+  if (!codes || W <= 0 || H <= 0 || S < 1 || S > 128 || k < 0 || k > 4) return nullptr;
+  SiftLevels* L = new SiftLevels;
+  L->W = W; L->H = H; L->S = S; L->k = k;
+  const size_t N = (size_t)W * H;
+  std::vector<int16_t> pl(N);
+  L->lev.resize(k + 1);
+  for (int l = 0; l <= k; ++l) {
+    L->lev[l].resize(N * S);
+    for (int ch = 0; ch < S; ++ch) {
+      for (size_t i = 0; i < N; ++i) pl[i] = codes[i * S + ch];
+      smooth_plane_t(pl.data(), W, H, 1 << l, 0, L->lev[l].data() + ch * N);
+    }
+  }
+  return L;
+}
+
+void ffo_sift_levels_free(void* h) { delete static_cast<SiftLevels*>(h); }
+
+// out: S x H x W int16
+int ffo_sift_levels_get(void* h, int lev, int16_t* out) {
+  SiftLevels* L = static_cast<SiftLevels*>(h);
+  if (lev < 0 || lev > L->k) return -1;
+  std::copy(L->lev[lev].begin(), L->lev[lev].end(), out);
+  return 0;
+}
+
+int32_t ffo_sift_cost(void* ss, void* sd, int Q, int lev, int r, int S, int px, int py, int fx, int fy) {
+  return sift_cost_at(*static_cast<SiftLevels*>(ss), *static_cast<SiftLevels*>(sd), Q, lev, r, S, px, py, fx, fy);
+}
+
+// hs / hd: census descriptors (dimensions, Q, WHT vectors for the kd-tree);
+// ss / sd: colour levels; params as ffo_match_field (the proposal is not
+// used with this data term).
+int ffo_match_field_sift(void* hs, void* hd, void* ss, void* sd, int r, int S, const int64_t* params, int32_t* flow,
+                         int32_t* cost, int64_t* counters) {
+  const Desc& s = *static_cast<Desc*>(hs);
+  const Desc& d = *static_cast<Desc*>(hd);
+  const SiftLevels& cs = *static_cast<SiftLevels*>(ss);
+  const SiftLevels& cd = *static_cast<SiftLevels*>(sd);
+  MatchParams P;
+  P.k = (int)params[0]; P.R = (int)params[1]; P.leaf = (int)params[2]; P.n_prop = (int)params[3];
+  P.n_rs = (int)params[4]; P.use_kdtree = (int)params[5]; P.skip_dup = (int)params[6];
+  P.max_steps = (int)params[7]; P.seed_lo = (uint32_t)params[8]; P.seed_hi = (uint32_t)params[9];
+  P.field_id = (uint32_t)params[10]; P.pair_id = (uint32_t)params[11];
+  if (P.k < 0 || P.k > s.k || P.k > d.k || P.k > cs.k || P.k > cd.k || s.Q != d.Q || r < 1) return -1;
+  if (cs.W != s.W || cs.H != s.H || cd.W != d.W || cd.H != d.H || S < 1 || S > cs.S || S > cd.S) return -1;
+  if (!P.use_kdtree || !s.wht_for(r) || !d.wht_for(r)) return -2;
+  return match_field_sift(s, d, cs, cd, r, S, P, flow, cost, counters);
+}
+
 }  // extern "C"
+

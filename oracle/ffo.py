@@ -55,6 +55,15 @@ def lib():
         L.ffo_sparsify.argtypes = [P, i32, i32, P, i32, i32, i32, i32, i32, P, P]
         L.ffo_isqrt64.argtypes = [C.c_uint64]
         L.ffo_isqrt64.restype = C.c_uint64
+        L.ffo_dense_sift.argtypes = [P, i32, i32, P]
+        L.ffo_smooth_codes.argtypes = [P, i32, i32, i32, P]
+        L.ffo_sift_levels_create.argtypes = [P, i32, i32, i32, i32]
+        L.ffo_sift_levels_create.restype = P
+        L.ffo_sift_levels_free.argtypes = [P]
+        L.ffo_sift_levels_free.restype = None
+        L.ffo_sift_levels_get.argtypes = [P, i32, P]
+        L.ffo_sift_cost.argtypes = [P, P, i32, i32, i32, i32, i32, i32, i32, i32]
+        L.ffo_match_field_sift.argtypes = [P, P, P, P, i32, i32, P, P, P, P]
         _lib = L
     return _lib
 
@@ -303,5 +312,142 @@ def match_pair(img1, img2, r: int = 8, r2: int = 6, k: int = 3, Q: int = 4, eps:
         out.update(region_label=lab, keep_region=kr, filtered_region=fr)
         if sparse_e is not None:
             pick, sp = sparsify(fr, Bs, Q, sparse_e)
+            out.update(pick=pick, sparse=sp)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Section 3.3, the SIFT-flow data term: dense SIFT on the CIELab lightness,
+# PCA to S colours, per-level smoothing of the quantised colours, L2 patch
+# distances; the search itself is the census one with this cost.
+
+SIFT_DIM = 128
+CODE_SCALE = 1024.0     # colours are stored as round-half-even(1024 c) int16
+CODE_MAX = 2047         # |c| <= |d - mean| <= 2 for unit-length d; clamped to +-2047
+
+
+def dense_sift(L: np.ndarray) -> np.ndarray:
+    """H x W uint8 lightness plane -> H x W x 128 float64 SIFT vectors."""
+    L = np.ascontiguousarray(L, np.uint8)
+    H, W = L.shape
+    out = np.empty((H, W, SIFT_DIM), np.float64)
+    assert lib().ffo_dense_sift(_p(L), W, H, _p(out)) == 0
+    return out
+
+
+def sift_pca(D1: np.ndarray, D2: np.ndarray):
+    """PCA over the SIFT vectors of both images of a pair (the reading: one
+    basis per pair, from every pixel of both images).  Returns (mean,
+    eigenvalues descending, eigenvectors as columns in that order); each
+    eigenvector's largest-magnitude component (the first on ties) is made
+    positive."""
+    X = np.concatenate([D1.reshape(-1, SIFT_DIM), D2.reshape(-1, SIFT_DIM)], 0).astype(np.float64)
+    mean = X.mean(axis=0)
+    Xc = X - mean
+    cov = Xc.T @ Xc / X.shape[0]
+    lam, V = np.linalg.eigh(cov)
+    lam, V = lam[::-1].copy(), V[:, ::-1].copy()
+    idx = np.argmax(np.abs(V), axis=0)
+    sgn = np.sign(V[idx, np.arange(SIFT_DIM)])
+    sgn[sgn == 0] = 1.0
+    return mean, lam, V * sgn
+
+
+def sift_codes(D: np.ndarray, mean: np.ndarray, V: np.ndarray, S: int) -> np.ndarray:
+    """Project H x W x 128 vectors on the first S eigenvectors and quantise:
+    round-half-even(1024 c), clamped to +-2047; H x W x S int16."""
+    c = (D.reshape(-1, SIFT_DIM) - mean) @ V[:, :S]
+    q = np.clip(np.rint(c * CODE_SCALE), -CODE_MAX, CODE_MAX).astype(np.int16)
+    return q.reshape(D.shape[:-1] + (S,))
+
+
+def sift_colors(img1, img2, S: int = 18):
+    """Colours of both images of a pair: (codes1, codes2, (mean, eigenvalues,
+    eigenvectors))."""
+    L1 = lab8(img1)[0]
+    L2 = lab8(img2)[0]
+    D1, D2 = dense_sift(L1), dense_sift(L2)
+    mean, lam, V = sift_pca(D1, D2)
+    return sift_codes(D1, mean, V, S), sift_codes(D2, mean, V, S), (mean, lam, V)
+
+
+def smooth_codes(plane: np.ndarray, n: int) -> np.ndarray:
+    plane = np.ascontiguousarray(plane, np.int16)
+    H, W = plane.shape
+    out = np.empty((H, W), np.int16)
+    assert lib().ffo_smooth_codes(_p(plane), W, H, n, _p(out)) == 0
+    return out
+
+
+class SiftLevels:
+    """Per-level smoothed colour planes of one image (levels 0..k)."""
+
+    def __init__(self, codes: np.ndarray, k: int = 3):
+        codes = np.ascontiguousarray(codes, np.int16)
+        self.H, self.W, self.S = codes.shape
+        self.k = k
+        self.h = lib().ffo_sift_levels_create(_p(codes), self.W, self.H, self.S, k)
+        if not self.h:
+            raise ValueError("bad colour arguments")
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().ffo_sift_levels_free(h)
+            self.h = None
+
+    def level(self, lev):
+        """S x H x W int16."""
+        out = np.empty((self.S, self.H, self.W), np.int16)
+        assert lib().ffo_sift_levels_get(self.h, lev, _p(out)) == 0
+        return out
+
+
+def sift_cost(src: SiftLevels, dst: SiftLevels, Q: int, lev: int, r: int, S: int, px: int, py: int, fx: int,
+              fy: int) -> int:
+    return lib().ffo_sift_cost(src.h, dst.h, Q, lev, r, S, px, py, fx, fy)
+
+
+def match_field_sift(src: Desc, dst: Desc, ssrc: SiftLevels, sdst: SiftLevels, r: int, S: int, k: int = 3,
+                     R: int = 1, leaf: int = 8, n_prop: int = 4, n_rs: int = 3, skip_dup: bool = True,
+                     max_steps: int = -1, seed: int = 0, field_id: int = 0, pair_id: int = 0,
+                     counters: bool = False):
+    """One Flow Field src -> dst with the SIFT-flow data term on the first S
+    colours (kd-tree seeds from the CIELab WHTs of src / dst)."""
+    params = np.array([k, R, leaf, n_prop, n_rs, 1, int(skip_dup), max_steps,
+                       seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF, field_id, pair_id], np.int64)
+    flow = np.empty((src.H, src.W), np.int32)
+    cst = np.empty((src.H, src.W), np.int32)
+    cnt = np.zeros(8, np.int64)
+    rc = lib().ffo_match_field_sift(src.h, dst.h, ssrc.h, sdst.h, r, S, _p(params), _p(flow), _p(cst), _p(cnt))
+    if rc < 0:
+        raise ValueError(f"ffo_match_field_sift failed ({rc})")
+    if counters:
+        return flow, cst, cnt
+    return flow, cst
+
+
+def match_pair_sift(img1, img2, r: int = 3, r2: int = 2, S: int = 12, S2: int = 18, k: int = 3, Q: int = 4,
+                    eps: int = 1, seed: int = 0, pair_id: int = 0, region_s=150, sparse_e=9, **kw):
+    """The hot path with the SIFT-flow data term on one pair, with the
+    paper's KITTI settings by default (r = 3, r2 = 2, S = 12 for F and B1,
+    S2 = 18 for B2, epsilon = 1, s = 150, e = 9).  Returns a dict of arrays."""
+    codes1, codes2, pca = sift_colors(img1, img2, max(S, S2))
+    radii = (r, r2) if r2 != r else (r,)
+    d1 = Desc(img1, k, Q, radii)
+    d2 = Desc(img2, k, Q, radii)
+    c1 = SiftLevels(codes1, k)
+    c2 = SiftLevels(codes2, k)
+    F, CF = match_field_sift(d1, d2, c1, c2, r, S, k=k, seed=seed, field_id=0, pair_id=pair_id, **kw)
+    B1, CB1 = match_field_sift(d2, d1, c2, c1, r, S, k=k, seed=seed, field_id=1, pair_id=pair_id, **kw)
+    B2, CB2 = match_field_sift(d2, d1, c2, c1, r2, S2, k=k, seed=seed, field_id=2, pair_id=pair_id, **kw)
+    out = dict(codes1=codes1, codes2=codes2, eig=pca[1], F=F, CF=CF, B1=B1, CB1=CB1, B2=B2, CB2=CB2)
+    keep, filt = consistency(F, [B1, B2], Q, eps * Q)
+    out.update(keep=keep, filtered=filt)
+    if region_s is not None:
+        lab, kr, fr = region_filter(F, keep, Q, region_s)
+        out.update(region_label=lab, keep_region=kr, filtered_region=fr)
+        if sparse_e is not None:
+            pick, sp = sparsify(fr, [B1, B2], Q, sparse_e)
             out.update(pick=pick, sparse=sp)
     return out
