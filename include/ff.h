@@ -315,6 +315,109 @@ ff_status ff_proposal_train_step(float* params, float* adam_m, float* adam_v, in
                                  void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * Section 3.3, the second data term: patch-based SIFT flow.  Every pixel of
+ * both images gets a 128-dimensional SIFT vector (Lowe 2004, computed densely
+ * and upright as in Liu et al.'s SIFT flow), PCA over the pair reduces them
+ * to S "colours", the colour images are smoothed per level as the images of
+ * section 3.2, and the data term sums L2 colour distances over the subsampled
+ * patch.  The kd-tree seeds still come from the CIELab WHT vectors.
+ *
+ * Dense SIFT (the readings the library takes where the paper defers to SIFT
+ * flow): input the 8-bit CIELab lightness (plane 0 of a descriptor blob's
+ * lab planes, or a gray image); central-difference gradients with clamped
+ * coordinates; orientation bins o pi/4 (o = 0..7, y down), the magnitude
+ * split linearly between the two nearest; 4 x 4 cells of 3 px, cell (i, j)
+ * centred at p + ((i - 1.5) 3, (j - 1.5) 3); every pixel q = p + d with
+ * |dx|, |dy| <= 7 inside the image adds with weight exp(-|d|^2 / 72) times the
+ * bilinear cell weights; element (4 j + i) 8 + o; normalised, clamped at 0.2,
+ * normalised (a zero vector stays zero).  fp32 arithmetic.
+ */
+
+/* int16 values per pixel of a colour-level array with S colours (S rounded
+ * up to a multiple of 4; the extra channels are zero); 0 if S is not in 1..32. */
+int32_t ff_sift_pitch(int32_t S);
+
+/* Device workspace bytes that ff_dense_sift, ff_sift_colors (for a pair of
+ * these sizes) and ff_sift_levels (for either image) each need; 0 for sizes
+ * below 1, above 8191 or above 2^22 pixels. */
+size_t ff_sift_workspace_bytes(int32_t w1, int32_t h1, int32_t w2, int32_t h2);
+
+/* Inspection: the dense SIFT vectors of one lightness plane L (device, h*w
+ * uint8, rows packed) into desc (device, h*w*128 float32). */
+ff_status ff_dense_sift(const uint8_t* L, int32_t width, int32_t height, float* desc, void* workspace,
+                        size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * The colours of a pair.  L1, L2: device lightness planes (h*w uint8 each).
+ * The covariance of the two images' SIFT vectors together (every pixel of
+ * both; accumulated in fp64) is decomposed by a Jacobi eigen-solver (fp64);
+ * eigenvalues are sorted descending (ties by index) and each eigenvector's
+ * largest-magnitude component (the first on ties) is made positive.  codes1 /
+ * codes2 (device, h*w*S int16, colours last): the projections on the first S
+ * eigenvectors of the vectors minus the mean, round-half-even(1024 c),
+ * clamped to +-2047.  S in 1..32.
+ *  pca (device, nullable): 128 + 128 + 128*128 doubles: the mean, the
+ *      eigenvalues (descending), the basis, element [k*128 + s] = component k
+ *      of eigenvector s;
+ *  desc1, desc2 (device, nullable): the SIFT vectors, h*w*128 float32 each.
+ * Errors: FF_ERR_ARG for null pointers, sizes below 1 or S outside 1..32;
+ * FF_ERR_SIZE beyond 8191 per side or 2^22 pixels; FF_ERR_WORKSPACE below
+ * ff_sift_workspace_bytes.
+ */
+ff_status ff_sift_colors(const uint8_t* L1, int32_t w1, int32_t h1, const uint8_t* L2, int32_t w2, int32_t h2,
+                         int32_t S, int16_t* codes1, int16_t* codes2, double* pca, float* desc1, float* desc2,
+                         void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Per-level colour images of one image: levels (device, (k+1) x h x w x
+ * ff_sift_pitch(S) int16): level j is the codes smoothed with n = 2^j as in
+ * section 3.2 (n x n block sums, replicate-padded; the two Q14 Lanczos-3
+ * passes of ff_compute_descriptors; output in code units, rounded half up);
+ * level 0 is the codes.  codes: device h*w*S int16.  k in 0..4. */
+ff_status ff_sift_levels(const int16_t* codes, int32_t width, int32_t height, int32_t S, int32_t k, int16_t* levels,
+                         void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Only the Lab8 planes and WHT vectors of ff_compute_descriptors (all the
+ * SIFT-flow search reads of a descriptor blob); the other regions of blob are
+ * left as they are. */
+ff_status ff_compute_lab_wht(const ff_desc* d, const ff_image* img, const uint8_t* pixels, void* blob,
+                             size_t blob_bytes, hipStream_t stream);
+
+/*
+ * Flow Fields with the SIFT-flow data term (sections 3.1-3.3), a batch of
+ * fields in one call; the search is ff_match_field's (kd-tree seeds on the
+ * 2^k grid, per level four propagation sweeps and three random searches,
+ * R_n = R n) with E^n_r(p, f) = sum over the (2r+1)^2 samples at stride n of
+ * floor(sqrt(sum_{s < S} d_s^2 * 256 / Q^4)): d_s = Q^2 c1_s(p + n delta) - the
+ * target colour bilinear at the subpixel centre (weights (Q-a)(Q-b), a(Q-b),
+ * (Q-a)b, ab of the four neighbours of floor(m/Q) + n delta, the +1
+ * neighbours clamped; m = pQ + f, (a, b) = m mod Q); lookups clamp to the
+ * image; f counts only if m lies in the image.  Costs are exact integers.
+ * The paper's KITTI setting: r = 3 with S = 12 for F and B1, r2 = 2 with
+ * S2 = 18 for B2.  p->use_kdtree must be 1 (FF_ERR_UNSUPPORTED otherwise);
+ * p->band_rows and p->pipeline are ignored; all jobs share subpel.
+ */
+typedef struct {
+  const ff_desc* src;        /* host: dimensions, subpel, WHT layout */
+  const void* src_blob;      /* device: holds the WHT vectors of `radius` */
+  const ff_desc* dst;        /* host */
+  const void* dst_blob;      /* device */
+  const int16_t* src_levels; /* device: ff_sift_levels of the source */
+  const int16_t* dst_levels; /* device: ff_sift_levels of the target */
+  int32_t pitch;             /* int16 per pixel of both level arrays (4..32, multiple of 4) */
+  int32_t channels;          /* S: colours used, 1..pitch */
+  int32_t levels;            /* k of both level arrays (>= p->k) */
+  int32_t radius;
+  uint32_t field_id, pair_id;
+  uint64_t seed;
+  int32_t* flow;             /* device, src h*w */
+  int32_t* cost;             /* device, src h*w */
+} ff_sift_job;
+
+size_t ff_match_sift_workspace_bytes(const ff_sift_job* jobs, int32_t n_jobs, const ff_match_params* p);
+ff_status ff_match_sift(const ff_sift_job* jobs, int32_t n_jobs, const ff_match_params* p, void* workspace,
+                        size_t workspace_bytes, hipStream_t stream);
+
+/*
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * search as ff_match_field, with the same arguments minus the workspace, and
@@ -373,7 +476,12 @@ typedef enum {
   FF_PROF_LAB = 12,          /* descriptor stages: Lab8 */
   FF_PROF_SMOOTH = 13,       /*   smoothed images I^n (all levels) */
   FF_PROF_CENSUS = 14,       /*   census planes (all levels and phases, both layouts) */
-  FF_PROF_WHT = 15           /*   WHT vectors (all radii) */
+  FF_PROF_WHT = 15,          /*   WHT vectors (all radii) */
+  FF_PROF_SIFT_COLORS = 16,  /* the whole ff_sift_colors (or ff_dense_sift) sequence */
+  FF_PROF_SIFT_PCA = 17,     /*   its covariance and eigen-decomposition */
+  FF_PROF_SIFT_LEVELS = 18,  /* ff_sift_levels */
+  FF_PROF_SIFT_MATCH = 19,   /* the whole ff_match_sift_batch sequence */
+  FF_PROF_SIFT_PROPAGATE = 20 /*   one of its propagation sweeps */
 } ff_prof_class;
 ff_status ff_profile_begin(int32_t kernel_class, int32_t max_launches);
 ff_status ff_profile_end(double* total_ms, int32_t* launches);

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libff.so")
-SOURCES = ["ff_desc.hip", "ff_tree.hip", "ff_match.hip", "ff_filter.hip", "ff_net.hip", "ff_api.cpp"]
+SOURCES = ["ff_desc.hip", "ff_tree.hip", "ff_match.hip", "ff_filter.hip", "ff_net.hip", "ff_sift.hip",
+           "ff_sift_match.hip", "ff_api.cpp"]
 ARCH = os.environ.get("FF_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -47,7 +47,7 @@ extern "C" {
 
 ff_status ff_profile_begin(int32_t kernel_class, int32_t max_launches) {
   using namespace ff;
-  if (kernel_class < 1 || kernel_class > 15 || max_launches < 1 || max_launches > 1 << 20) return FF_ERR_ARG;
+  if (kernel_class < 1 || kernel_class > 20 || max_launches < 1 || max_launches > 1 << 20) return FF_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   g_prof_class = 0;
   destroy_events();

@@ -357,6 +357,86 @@ __global__ void k_wht_v(const int32_t* __restrict__ h, int W, int H, int C, int 
   for (int j = 9 * C; j < stride; ++j) out[j] = 0;
 }
 
+// ---------------------------------------------------------------- SIFT colour levels
+// The SIFT-flow colours (section 3.3) are smoothed per level as the images
+// of section 3.2: the same block sums and Q14 Lanczos passes, on int16 codes
+// (channels last), in 64-bit sums, the output in code units.  Level 0 is the
+// codes themselves; channels S..P-1 of every level are zero.
+__global__ void k_code_copy(const int16_t* __restrict__ codes, int N, int S, int P, int16_t* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)N * P) return;
+  const int c = (int)(i % P);
+  out[i] = c < S ? codes[(i / P) * S + c] : (int16_t)0;
+}
+
+// block sums of channel c (grid z) over n x n, replicate-padded
+__global__ void k_code_blocksum(const int16_t* __restrict__ codes, int W, int H, int S, int n, int Wc, int Hc,
+                                int32_t* __restrict__ A) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y, c = blockIdx.z;
+  if (j >= Wc) return;
+  int32_t s = 0;
+  for (int u = 0; u < n; ++u) {
+    const int16_t* row = codes + (size_t)min(i * n + u, H - 1) * W * S + c;
+    for (int v = 0; v < n; ++v) s += row[(size_t)min(j * n + v, W - 1) * S];
+  }
+  A[((size_t)c * Hc + i) * Wc + j] = s;
+}
+
+__global__ void k_code_lanczos_h(const int32_t* __restrict__ A, int W, int n, int li, int Wc, int Hc,
+                                 int32_t* __restrict__ T) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y, c = blockIdx.z;
+  if (x >= W) return;
+  const int32_t* row = A + ((size_t)c * Hc + i) * Wc;
+  const int ph = x % n, base = x / n;
+  int64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) s += (int64_t)c_lanczos[li][ph][k] * row[clampi(base + k - 3, 0, Wc - 1)];
+  T[((size_t)c * Hc + i) * W + x] = (int32_t)((s + 8192) >> 14);
+}
+
+// vertical pass: divide by 2^14 n^2 (shift = 14 + 2 log2 n), round half up;
+// grid z covers all P channels (the padding ones are written zero)
+__global__ void k_code_lanczos_v(const int32_t* __restrict__ T, int W, int H, int n, int li, int Hc, int shift, int S,
+                                 int P, int16_t* __restrict__ out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y, c = blockIdx.z;
+  if (x >= W) return;
+  int16_t v = 0;
+  if (c < S) {
+    const int32_t* Pl = T + (size_t)c * Hc * W;
+    const int ph = y % n, base = y / n;
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) s += (int64_t)c_lanczos[li][ph][k] * Pl[(size_t)clampi(base + k - 3, 0, Hc - 1) * W + x];
+    v = (int16_t)((s + ((int64_t)1 << (shift - 1))) >> shift);
+  }
+  out[((size_t)y * W + x) * P + c] = v;
+}
+
+size_t sift_levels_scratch_bytes(int W, int H, int S) {
+  const int Wc = (W + 1) / 2, Hc = (H + 1) / 2;
+  return (size_t)S * ((size_t)Hc * Wc + (size_t)Hc * W) * 4;
+}
+
+void enqueue_sift_levels(const int16_t* codes, int W, int H, int S, int P, int k, int16_t* levels, int32_t* scratch,
+                         hipStream_t stream) {
+  const size_t N = (size_t)W * H;
+  k_code_copy<<<(unsigned)((N * P + 255) / 256), 256, 0, stream>>>(codes, (int)N, S, P, levels);
+  const unsigned gx = (unsigned)((W + 255) / 256);
+  for (int lev = 1; lev <= k; ++lev) {
+    const int n = 1 << lev;
+    const int Wc = (W + n - 1) / n, Hc = (H + n - 1) / n;
+    int32_t* A = scratch;
+    int32_t* T = scratch + (size_t)S * Hc * Wc;
+    k_code_blocksum<<<dim3((unsigned)((Wc + 255) / 256), Hc, S), 256, 0, stream>>>(codes, W, H, S, n, Wc, Hc, A);
+    k_code_lanczos_h<<<dim3(gx, Hc, S), 256, 0, stream>>>(A, W, n, lev - 1, Wc, Hc, T);
+    k_code_lanczos_v<<<dim3(gx, H, P), 256, 0, stream>>>(T, W, H, n, lev - 1, Hc, 14 + 2 * lev, S, P,
+                                                         levels + (size_t)lev * N * P);
+  }
+}
+
 }  // namespace ff
 
 using namespace ff;
@@ -488,6 +568,36 @@ ff_status ff_compute_descriptors(const ff_desc* d, const ff_image* img, const ui
   }
   prof_mark(FF_PROF_CENSUS, stream, false);
   prof_mark(FF_PROF_DESCRIPTORS, stream, false);
+  return launch_status();
+}
+
+
+ff_status ff_compute_lab_wht(const ff_desc* d, const ff_image* img, const uint8_t* pixels, void* blob,
+                             size_t blob_bytes, hipStream_t stream) {
+  if (!d || !img || !pixels || !blob) return FF_ERR_ARG;
+  if (img->width != d->width || img->height != d->height || img->channels != d->channels ||
+      img->row_stride < img->width * img->channels)
+    return FF_ERR_ARG;
+  if (blob_bytes < d->bytes) return FF_ERR_WORKSPACE;
+  ff_status st = ensure_init();
+  if (st != FF_OK) return st;
+  const int W = d->width, H = d->height, C = d->channels;
+  const size_t N = (size_t)W * H;
+  char* base = static_cast<char*>(blob);
+  uint8_t* lab = reinterpret_cast<uint8_t*>(base + d->off_lab);
+  int32_t* scratch = reinterpret_cast<int32_t*>(base + d->off_census);
+  const dim3 tb(256);
+  const unsigned gx = (unsigned)((W + 255) / 256);
+  prof_mark(FF_PROF_LAB, stream, true);
+  k_lab8<<<dim3(gx, H), tb, 0, stream>>>(pixels, W, H, C, img->row_stride, lab);
+  prof_mark(FF_PROF_LAB, stream, false);
+  prof_mark(FF_PROF_WHT, stream, true);
+  for (int i = 0; i < d->n_radii; ++i) {
+    int32_t* V = reinterpret_cast<int32_t*>(base + d->off_wht + (size_t)i * N * d->wht_stride * 4);
+    k_wht_h<<<dim3(gx, H, C), tb, 0, stream>>>(lab, W, H, d->radii[i], scratch);
+    k_wht_v<<<dim3(gx, H), tb, 0, stream>>>(scratch, W, H, C, d->radii[i], d->wht_stride, V);
+  }
+  prof_mark(FF_PROF_WHT, stream, false);
   return launch_status();
 }
 

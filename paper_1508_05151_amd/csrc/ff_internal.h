@@ -92,6 +92,12 @@ inline const int32_t* wht_block(const ff_desc* d, const void* blob, int radius) 
   return nullptr;
 }
 
+// SIFT colour levels (section 3.3 smoothed as section 3.2): scratch bytes
+// and the enqueue (ff_desc.hip holds the Lanczos table)
+size_t sift_levels_scratch_bytes(int W, int H, int S);
+void enqueue_sift_levels(const int16_t* codes, int W, int H, int S, int P, int k, int16_t* levels, int32_t* scratch,
+                         hipStream_t stream);
+
 ff_status ensure_init();
 ff_status launch_status();   // maps hipGetLastError to FF_ERR_HIP
 

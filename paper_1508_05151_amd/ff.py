@@ -60,6 +60,14 @@ class ff_field_job(C.Structure):
 _lib = None
 
 
+class ff_sift_job(C.Structure):
+    _fields_ = [("src", C.POINTER(ff_desc)), ("src_blob", C.c_void_p), ("dst", C.POINTER(ff_desc)),
+                ("dst_blob", C.c_void_p), ("src_levels", C.c_void_p), ("dst_levels", C.c_void_p),
+                ("pitch", C.c_int32), ("channels", C.c_int32), ("levels", C.c_int32), ("radius", C.c_int32),
+                ("field_id", C.c_uint32), ("pair_id", C.c_uint32), ("seed", C.c_uint64),
+                ("flow", C.c_void_p), ("cost", C.c_void_p)]
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -119,6 +127,22 @@ def lib():
         L.ff_proposal_train_step.argtypes = [P, P, P, i32, C.c_float, P, P, P, i32, i32, i32, i32, P, P, P,
                                              C.c_size_t, P]
         L.ff_proposal_train_step.restype = i32
+        L.ff_sift_pitch.argtypes = [i32]
+        L.ff_sift_pitch.restype = i32
+        L.ff_sift_workspace_bytes.argtypes = [i32, i32, i32, i32]
+        L.ff_sift_workspace_bytes.restype = C.c_size_t
+        L.ff_dense_sift.argtypes = [P, i32, i32, P, P, C.c_size_t, P]
+        L.ff_dense_sift.restype = i32
+        L.ff_sift_colors.argtypes = [P, i32, i32, P, i32, i32, i32, P, P, P, P, P, P, C.c_size_t, P]
+        L.ff_sift_colors.restype = i32
+        L.ff_sift_levels.argtypes = [P, i32, i32, i32, i32, P, P, C.c_size_t, P]
+        L.ff_sift_levels.restype = i32
+        L.ff_compute_lab_wht.argtypes = [C.POINTER(ff_desc), C.POINTER(ff_image), P, P, C.c_size_t, P]
+        L.ff_compute_lab_wht.restype = i32
+        L.ff_match_sift_workspace_bytes.argtypes = [C.POINTER(ff_sift_job), i32, C.POINTER(ff_match_params)]
+        L.ff_match_sift_workspace_bytes.restype = C.c_size_t
+        L.ff_match_sift.argtypes = [C.POINTER(ff_sift_job), i32, C.POINTER(ff_match_params), P, C.c_size_t, P]
+        L.ff_match_sift.restype = i32
         _lib = L
     return _lib
 
@@ -322,7 +346,8 @@ def ff_build_kdtree(d: ff_desc, blob, radius, leaf, node_dim, node_split, perm, 
 
 
 PROF = {"descriptors": 1, "tree": 2, "seed": 3, "level_entry": 4, "propagate": 5, "random_search": 6, "filter": 7,
-        "proposal": 8, "train": 9, "region": 10, "sparsify": 11, "lab": 12, "smooth": 13, "census": 14, "wht": 15}
+        "proposal": 8, "train": 9, "region": 10, "sparsify": 11, "lab": 12, "smooth": 13, "census": 14, "wht": 15,
+        "sift_colors": 16, "sift_pca": 17, "sift_levels": 18, "sift_match": 19, "sift_propagate": 20}
 
 
 def ff_profile_begin(kernel_class: str, max_launches: int):
@@ -343,6 +368,201 @@ def ff_read_status(workspace) -> int:
     s = C.c_int32(0)
     _check(lib().ff_read_status(_ptr(workspace), C.byref(s)), "ff_read_status")
     return s.value
+
+
+# ------------------------------------------------------------------ SIFT-flow data term (section 3.3)
+SIFT_DIM = 128
+
+
+def ff_sift_pitch(S: int) -> int:
+    return lib().ff_sift_pitch(S)
+
+
+def ff_sift_workspace_bytes(w1, h1, w2, h2) -> int:
+    n = lib().ff_sift_workspace_bytes(w1, h1, w2, h2)
+    if n == 0:
+        raise FFError(-1, "ff_sift_workspace_bytes")
+    return n
+
+
+def _check_dev(t, dtype, numel, what):
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != numel or not t.is_cuda:
+        raise FFError(-1, f"{what}: expected a contiguous {dtype} CUDA tensor of {numel} elements")
+
+
+def ff_dense_sift(L, desc, workspace, stream=None):
+    """L: H x W uint8 lightness plane; desc: H x W x 128 float32."""
+    h, w = L.shape
+    _check_dev(L, torch.uint8, w * h, "L")
+    _check_dev(desc, torch.float32, w * h * SIFT_DIM, "desc")
+    _check(lib().ff_dense_sift(_ptr(L), w, h, _ptr(desc), _ptr(workspace), workspace.numel(), _stream(stream)),
+           "ff_dense_sift")
+
+
+def ff_sift_colors(L1, L2, S, codes1, codes2, workspace, pca=None, desc1=None, desc2=None, stream=None):
+    """L1, L2: lightness planes; codes: H x W x S int16 each; pca (optional):
+    128 + 128 + 128 * 128 float64 (mean, eigenvalues, basis)."""
+    h1, w1 = L1.shape
+    h2, w2 = L2.shape
+    _check_dev(L1, torch.uint8, w1 * h1, "L1")
+    _check_dev(L2, torch.uint8, w2 * h2, "L2")
+    _check_dev(codes1, torch.int16, w1 * h1 * S, "codes1")
+    _check_dev(codes2, torch.int16, w2 * h2 * S, "codes2")
+    if pca is not None:
+        _check_dev(pca, torch.float64, 2 * SIFT_DIM + SIFT_DIM * SIFT_DIM, "pca")
+    if desc1 is not None:
+        _check_dev(desc1, torch.float32, w1 * h1 * SIFT_DIM, "desc1")
+    if desc2 is not None:
+        _check_dev(desc2, torch.float32, w2 * h2 * SIFT_DIM, "desc2")
+    _check(lib().ff_sift_colors(_ptr(L1), w1, h1, _ptr(L2), w2, h2, S, _ptr(codes1), _ptr(codes2), _ptr(pca),
+                                _ptr(desc1), _ptr(desc2), _ptr(workspace), workspace.numel(), _stream(stream)),
+           "ff_sift_colors")
+
+
+def ff_sift_levels(codes, k, levels, workspace, stream=None):
+    """codes: H x W x S int16; levels: (k+1) x H x W x ff_sift_pitch(S) int16."""
+    h, w, S = codes.shape
+    _check_dev(codes, torch.int16, w * h * S, "codes")
+    _check_dev(levels, torch.int16, (k + 1) * w * h * ff_sift_pitch(S), "levels")
+    _check(lib().ff_sift_levels(_ptr(codes), w, h, S, k, _ptr(levels), _ptr(workspace), workspace.numel(),
+                                _stream(stream)), "ff_sift_levels")
+
+
+def ff_compute_lab_wht(d: ff_desc, pixels: torch.Tensor, blob: torch.Tensor, stream=None):
+    assert pixels.is_cuda and pixels.dtype == torch.uint8 and pixels.is_contiguous()
+    H, W = pixels.shape[:2]
+    Cc = 1 if pixels.dim() == 2 else pixels.shape[2]
+    img = ff_image(W, H, Cc, W * Cc)
+    _check(lib().ff_compute_lab_wht(C.byref(d), C.byref(img), _ptr(pixels), _ptr(blob), blob.numel(),
+                                    _stream(stream)), "ff_compute_lab_wht")
+
+
+def make_sift_job(src: ff_desc, src_blob, dst: ff_desc, dst_blob, src_levels, dst_levels, S, levels_k, radius,
+                  flow, cost, field_id=0, pair_id=0, seed=0) -> ff_sift_job:
+    _check_i32(flow, src.width * src.height, "flow")
+    _check_i32(cost, src.width * src.height, "cost")
+    P = src_levels.shape[-1]
+    j = ff_sift_job()
+    j.src = C.pointer(src)
+    j.src_blob = src_blob.data_ptr()
+    j.dst = C.pointer(dst)
+    j.dst_blob = dst_blob.data_ptr()
+    j.src_levels = src_levels.data_ptr()
+    j.dst_levels = dst_levels.data_ptr()
+    j.pitch = P
+    j.channels = S
+    j.levels = levels_k
+    j.radius = radius
+    j.field_id = field_id
+    j.pair_id = pair_id
+    j.seed = seed
+    j.flow = flow.data_ptr()
+    j.cost = cost.data_ptr()
+    return j
+
+
+def ff_match_sift_workspace_bytes(jobs, p: ff_match_params) -> int:
+    arr = (ff_sift_job * len(jobs))(*jobs)
+    n = lib().ff_match_sift_workspace_bytes(arr, len(jobs), C.byref(p))
+    if n == 0:
+        raise FFError(-1, "ff_match_sift_workspace_bytes")
+    return n
+
+
+def ff_match_sift(jobs, p: ff_match_params, workspace, stream=None):
+    arr = (ff_sift_job * len(jobs))(*jobs)
+    _check(lib().ff_match_sift(arr, len(jobs), C.byref(p), _ptr(workspace), workspace.numel(), _stream(stream)),
+           "ff_match_sift")
+
+
+class SiftPairMatcher:
+    """The hot path with the SIFT-flow data term for one pair (the paper's
+    KITTI setting by default): Lab8 and WHT vectors of both images, the pair's
+    SIFT colours (S2 = max(S, S2) channels) and their levels, one
+    ff_match_sift call for F (r, S), B1 (r, S) and B2 (r2, S2), the
+    consistency check (epsilon), the region filter (s) and the sparsification
+    (e).  Buffers are allocated once for the given sizes and reused."""
+
+    def __init__(self, width, height, channels=3, r=3, r2=2, S=12, S2=18, k=3, subpel=4, eps=1, region_s=150,
+                 sparse_e=9, device="cuda", **params):
+        self.W, self.H = width, height
+        self.r, self.r2, self.S, self.S2, self.k, self.Q, self.eps = r, r2, S, S2, k, subpel, eps
+        self.region_s, self.sparse_e = region_s, sparse_e
+        self.Sc = max(S, S2)
+        self.P = ff_sift_pitch(self.Sc)
+        radii = (r, r2) if r2 != r else (r,)
+        self.desc = ff_desc_init(width, height, channels, k, subpel, radii)
+        dev = device
+        self.blob1 = torch.empty(self.desc.bytes, dtype=torch.uint8, device=dev)
+        self.blob2 = torch.empty(self.desc.bytes, dtype=torch.uint8, device=dev)
+        self.codes1 = torch.empty((height, width, self.Sc), dtype=torch.int16, device=dev)
+        self.codes2 = torch.empty_like(self.codes1)
+        self.pca = torch.empty(2 * SIFT_DIM + SIFT_DIM * SIFT_DIM, dtype=torch.float64, device=dev)
+        self.levels1 = torch.empty((k + 1, height, width, self.P), dtype=torch.int16, device=dev)
+        self.levels2 = torch.empty_like(self.levels1)
+        self.sift_ws = torch.empty(ff_sift_workspace_bytes(width, height, width, height), dtype=torch.uint8,
+                                   device=dev)
+        self.params = ff_default_params(k=k, **params)
+        self.flow = {n: torch.empty((height, width), dtype=torch.int32, device=dev) for n in ("F", "B1", "B2")}
+        self.cost = {n: torch.empty((height, width), dtype=torch.int32, device=dev) for n in ("F", "B1", "B2")}
+        self.match_ws = torch.empty(ff_match_sift_workspace_bytes(self.jobs(0, 0), self.params), dtype=torch.uint8,
+                                    device=dev)
+        self.keep = torch.empty((height, width), dtype=torch.uint8, device=dev)
+        self.filtered = torch.empty((height, width), dtype=torch.int32, device=dev)
+        self.keep_region = torch.empty_like(self.keep)
+        self.filtered_region = torch.empty_like(self.filtered)
+        self.region_label = torch.empty_like(self.filtered)
+        self.region_ws = torch.empty(ff_region_filter_workspace_bytes(width, height), dtype=torch.uint8, device=dev)
+        self.pick = torch.empty(((height + 2) // 3, (width + 2) // 3), dtype=torch.int32, device=dev)
+        self.sparse = torch.empty_like(self.filtered)
+
+    def jobs(self, seed, pair_id):
+        d, b1, b2, l1, l2 = self.desc, self.blob1, self.blob2, self.levels1, self.levels2
+        return [make_sift_job(d, b1, d, b2, l1, l2, self.S, self.k, self.r, self.flow["F"], self.cost["F"], 0,
+                              pair_id, seed),
+                make_sift_job(d, b2, d, b1, l2, l1, self.S, self.k, self.r, self.flow["B1"], self.cost["B1"], 1,
+                              pair_id, seed),
+                make_sift_job(d, b2, d, b1, l2, l1, self.S2, self.k, self.r2, self.flow["B2"], self.cost["B2"], 2,
+                              pair_id, seed)]
+
+    def colors(self, img1, img2, codes=None, stream=None):
+        """Lab8 / WHT of both images, then their colours -- computed here, or
+        given as codes = (H x W x S2 int16, H x W x S2 int16) device tensors
+        -- and the colour levels."""
+        ff_compute_lab_wht(self.desc, img1, self.blob1, stream)
+        ff_compute_lab_wht(self.desc, img2, self.blob2, stream)
+        N = self.W * self.H
+        L1 = self.blob1[self.desc.off_lab:self.desc.off_lab + N].view(self.H, self.W)
+        L2 = self.blob2[self.desc.off_lab:self.desc.off_lab + N].view(self.H, self.W)
+        if codes is None:
+            ff_sift_colors(L1, L2, self.Sc, self.codes1, self.codes2, self.sift_ws, pca=self.pca, stream=stream)
+        else:
+            self.codes1.copy_(codes[0])
+            self.codes2.copy_(codes[1])
+        ff_sift_levels(self.codes1, self.k, self.levels1, self.sift_ws, stream)
+        ff_sift_levels(self.codes2, self.k, self.levels2, self.sift_ws, stream)
+
+    def run(self, img1, img2, seed=0, pair_id=0, codes=None, stream=None):
+        self.colors(img1, img2, codes, stream)
+        ff_match_sift(self.jobs(seed, pair_id), self.params, self.match_ws, stream)
+        Q = self.Q
+        bwd = [self.flow["B1"], self.flow["B2"]]
+        ff_consistency_filter(self.flow["F"], bwd, Q, self.eps * Q, self.keep, self.filtered, stream)
+        out = dict(codes1=self.codes1, codes2=self.codes2, pca=self.pca, F=self.flow["F"], CF=self.cost["F"],
+                   B1=self.flow["B1"], CB1=self.cost["B1"], B2=self.flow["B2"], CB2=self.cost["B2"], keep=self.keep,
+                   filtered=self.filtered)
+        if self.region_s is not None:
+            ff_region_filter(self.flow["F"], self.keep, Q, self.region_s, self.keep_region, self.filtered_region,
+                             self.region_ws, label=self.region_label, stream=stream)
+            out.update(keep_region=self.keep_region, filtered_region=self.filtered_region,
+                       region_label=self.region_label)
+            if self.sparse_e is not None:
+                ff_sparsify(self.filtered_region, bwd, Q, self.sparse_e, self.pick, self.sparse, stream=stream)
+                out.update(pick=self.pick, sparse=self.sparse)
+        return out
+
+    def status(self):
+        return ff_read_status(self.match_ws)
 
 
 # ------------------------------------------------------------------ helpers

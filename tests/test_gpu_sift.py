@@ -1,0 +1,262 @@
+"""GPU parity of the SIFT-flow data term (section 3.3) against the oracle.
+
+* Dense SIFT (fp32 on the GPU, fp64 in the oracle): element-wise within
+  1e-5.  Every element is a normalised sum of non-negative terms (at most
+  225 gradient samples through two 15-tap passes), so the fp32 sums carry a
+  relative error of a few 2^-24 times the tap count, under 4e-6 of an element
+  that is at most 1; atan2f / sqrtf add a few ulps.
+* PCA: eigenvalues within Weyl's bound 4 sqrt(128) max|d_gpu - d_oracle| (the
+  covariance moves by at most that much when every vector moves by at most
+  sqrt(128) max|dd|); codes within 1 of the oracle's wherever the eigenvalue
+  gaps around the component exceed 1e-3 of it (the projections carry
+  1024 |dd| plus the basis error there), and equal almost everywhere.
+* Colour levels and the search: exact integers, bit-exact on identical
+  inputs (the oracle's codes fed to both sides), at several sizes with
+  ragged tails, every Q, intermediate stops, and the whole pair path
+  (three fields, consistency check, region filter, sparsification).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ffo
+from synth import pairs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ff():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1508_05151_amd import ff as _ff
+    _ff.ff_init()
+    return _ff
+
+
+def _texture(W, H, seed):
+    rng = np.random.default_rng(seed)
+    base = rng.integers(0, 256, (H // 4 + 2, W // 4 + 2)).astype(np.float64)
+    up = np.kron(base, np.ones((4, 4)))[:H, :W]
+    k = np.ones(3) / 3
+    up = np.apply_along_axis(lambda r: np.convolve(r, k, "same"), 1, up)
+    up = np.apply_along_axis(lambda r: np.convolve(r, k, "same"), 0, up)
+    return np.clip(up + rng.normal(0, 3, (H, W)), 0, 255).astype(np.uint8)
+
+
+def _gpu_desc(ff, L):
+    H, W = L.shape
+    Lg = torch.from_numpy(np.ascontiguousarray(L)).cuda()
+    d = torch.empty((H, W, 128), dtype=torch.float32, device="cuda")
+    ws = torch.empty(ff.ff_sift_workspace_bytes(W, H, W, H), dtype=torch.uint8, device="cuda")
+    ff.ff_dense_sift(Lg, d, ws)
+    torch.cuda.synchronize()
+    return d.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("W,H,seed", [(97, 61, 1), (64, 64, 2), (200, 37, 3), (15, 9, 4), (1, 1, 5), (3, 40, 6)])
+def test_dense_sift_elementwise(ff, W, H, seed):
+    _say(f"dense sift {W}x{H} seed {seed}")
+    L = _texture(max(W, 8), max(H, 8), seed)[:H, :W].copy()
+    got = _gpu_desc(ff, L)
+    ref = ffo.dense_sift(L)
+    err = np.abs(got - ref).max()
+    assert err <= 1e-5, err
+    # unit length wherever the oracle's vector is non-zero
+    nz = np.linalg.norm(ref, axis=-1) > 0
+    assert np.allclose(np.linalg.norm(got, axis=-1)[nz], 1.0, atol=1e-5)
+    assert np.all(got[~nz] == 0)
+
+
+def test_dense_sift_special_images(ff):
+    # constant: zero; ramp and step edge: the oracle's pinned closed forms
+    for L in (np.full((30, 40), 90, np.uint8),
+              (2 * np.mgrid[0:40, 0:48][1] + np.mgrid[0:40, 0:48][0] + 10).astype(np.uint8),
+              np.where(np.arange(40)[None, :] >= 20, 200, 0).repeat(40, 0).astype(np.uint8)):
+        got = _gpu_desc(ff, L)
+        ref = ffo.dense_sift(L)
+        assert np.abs(got - ref).max() <= 1e-5
+
+
+def _colors_gpu(ff, L1, L2, S):
+    H1, W1 = L1.shape
+    H2, W2 = L2.shape
+    a = torch.from_numpy(L1).cuda()
+    b = torch.from_numpy(L2).cuda()
+    c1 = torch.empty((H1, W1, S), dtype=torch.int16, device="cuda")
+    c2 = torch.empty((H2, W2, S), dtype=torch.int16, device="cuda")
+    pca = torch.empty(2 * 128 + 128 * 128, dtype=torch.float64, device="cuda")
+    d1 = torch.empty((H1, W1, 128), dtype=torch.float32, device="cuda")
+    d2 = torch.empty((H2, W2, 128), dtype=torch.float32, device="cuda")
+    ws = torch.empty(ff.ff_sift_workspace_bytes(W1, H1, W2, H2), dtype=torch.uint8, device="cuda")
+    ff.ff_sift_colors(a, b, S, c1, c2, ws, pca=pca, desc1=d1, desc2=d2)
+    torch.cuda.synchronize()
+    P = pca.cpu().numpy()
+    return (c1.cpu().numpy(), c2.cpu().numpy(), P[:128], P[128:256], P[256:].reshape(128, 128),
+            d1.cpu().numpy().astype(np.float64), d2.cpu().numpy().astype(np.float64))
+
+
+def _check_colors(got, L1, L2, S):
+    c1, c2, mean, lam, V, d1, d2 = got
+    D1, D2 = ffo.dense_sift(L1), ffo.dense_sift(L2)
+    rmean, rlam, rV = ffo.sift_pca(D1, D2)
+    dd = max(np.abs(d1 - D1).max(), np.abs(d2 - D2).max())
+    assert dd <= 1e-5
+    weyl = 4 * np.sqrt(128) * dd + 1e-12
+    assert np.abs(lam - rlam).max() <= weyl, (np.abs(lam - rlam).max(), weyl)
+    assert np.abs(mean - rmean).max() <= dd + 1e-12
+    # orthonormal basis
+    assert np.abs(V.T @ V - np.eye(128)).max() < 1e-10
+    r1 = ffo.sift_codes(D1, rmean, rV, S)
+    r2 = ffo.sift_codes(D2, rmean, rV, S)
+    exact = total = 0
+    for s in range(S):
+        lo = rlam[s + 1] if s + 1 < 128 else 0.0
+        hi = rlam[s - 1] if s > 0 else np.inf
+        if min(rlam[s] - lo, hi - rlam[s]) < 1e-3 * rlam[s]:
+            continue   # a near-degenerate component: its direction is not determined to this precision
+        # the sign rule picks the same sign unless the largest components tie
+        sg = 1 if V[:, s] @ rV[:, s] > 0 else -1
+        for g, r in ((c1, r1), (c2, r2)):
+            d = np.abs(sg * g[..., s].astype(np.int64) - r[..., s])
+            assert d.max() <= 1, (s, d.max())
+            exact += int((d == 0).sum())
+            total += d.size
+    assert total > 0 and exact / total >= 0.99, exact / max(total, 1)
+    return exact / total
+
+
+def test_colors_pair(ff):
+    p = pairs.layered_pair(seed=5, W=96, H=64)
+    L1, L2 = ffo.lab8(p.img1)[0], ffo.lab8(p.img2)[0]
+    rate = _check_colors(_colors_gpu(ff, L1, L2, 18), L1, L2, 18)
+    _say(f"codes exact {rate:.5f}")
+
+
+def test_colors_different_sizes_and_S(ff):
+    L1 = _texture(131, 47, 7)
+    L2 = _texture(88, 70, 8)
+    for S in (1, 5, 12, 32):
+        _check_colors(_colors_gpu(ff, L1, L2, S), L1, L2, S)
+
+
+@pytest.mark.parametrize("W,H,S,k", [(97, 61, 18, 3), (64, 40, 5, 2), (33, 17, 12, 4), (8, 3, 1, 3)])
+def test_levels_bit_exact(ff, W, H, S, k):
+    rng = np.random.default_rng(W * 100 + H)
+    codes = rng.integers(-2047, 2048, (H, W, S)).astype(np.int16)
+    ref = ffo.SiftLevels(codes, k)
+    P = ff.ff_sift_pitch(S)
+    lv = torch.empty((k + 1, H, W, P), dtype=torch.int16, device="cuda")
+    ws = torch.empty(ff.ff_sift_workspace_bytes(W, H, W, H), dtype=torch.uint8, device="cuda")
+    ff.ff_sift_levels(torch.from_numpy(codes).cuda(), k, lv, ws)
+    torch.cuda.synchronize()
+    got = lv.cpu().numpy()
+    for lev in range(k + 1):
+        want = ref.level(lev).transpose(1, 2, 0)
+        assert np.array_equal(got[lev, :, :, :S], want), lev
+        assert np.all(got[lev, :, :, S:] == 0)
+
+
+def _search_case(ff, img1, img2, r, S, Sc, k=3, Q=4, max_steps=-1, seed=0, field_id=0, pair_id=0):
+    """One field img1 -> img2 on both sides, the oracle's codes (Sc colours,
+    the first S used) given to both."""
+    H1, W1 = img1.shape[:2]
+    H2, W2 = img2.shape[:2]
+    c1, c2, _ = ffo.sift_colors(img1, img2, Sc)
+    d1 = ffo.Desc(img1, k, Q, (r,))
+    d2 = ffo.Desc(img2, k, Q, (r,))
+    l1, l2 = ffo.SiftLevels(c1, k), ffo.SiftLevels(c2, k)
+    rf, rc = ffo.match_field_sift(d1, d2, l1, l2, r, S, k=k, max_steps=max_steps, seed=seed, field_id=field_id,
+                                  pair_id=pair_id)
+    Cc = img1.shape[2] if img1.ndim == 3 else 1
+    g1, g2 = ff.ff_desc_init(W1, H1, Cc, k, Q, (r,)), ff.ff_desc_init(W2, H2, Cc, k, Q, (r,))
+    b1 = torch.empty(g1.bytes, dtype=torch.uint8, device="cuda")
+    b2 = torch.empty(g2.bytes, dtype=torch.uint8, device="cuda")
+    ff.ff_compute_lab_wht(g1, torch.from_numpy(np.ascontiguousarray(img1)).cuda(), b1)
+    ff.ff_compute_lab_wht(g2, torch.from_numpy(np.ascontiguousarray(img2)).cuda(), b2)
+    P = ff.ff_sift_pitch(Sc)
+    lv1 = torch.empty((k + 1, H1, W1, P), dtype=torch.int16, device="cuda")
+    lv2 = torch.empty((k + 1, H2, W2, P), dtype=torch.int16, device="cuda")
+    ws = torch.empty(ff.ff_sift_workspace_bytes(W1, H1, W2, H2), dtype=torch.uint8, device="cuda")
+    ff.ff_sift_levels(torch.from_numpy(c1).cuda(), k, lv1, ws)
+    ff.ff_sift_levels(torch.from_numpy(c2).cuda(), k, lv2, ws)
+    flow = torch.empty((H1, W1), dtype=torch.int32, device="cuda")
+    cost = torch.empty((H1, W1), dtype=torch.int32, device="cuda")
+    p = ff.ff_default_params(k=k, max_steps=max_steps)
+    job = ff.make_sift_job(g1, b1, g2, b2, lv1, lv2, S, k, r, flow, cost, field_id, pair_id, seed)
+    mws = torch.empty(ff.ff_match_sift_workspace_bytes([job], p), dtype=torch.uint8, device="cuda")
+    ff.ff_match_sift([job], p, mws)
+    torch.cuda.synchronize()
+    assert ff.ff_read_status(mws) == 0
+    return flow.cpu().numpy(), cost.cpu().numpy(), rf, rc
+
+
+@pytest.mark.parametrize("W,H,r,S,seed", [(96, 64, 3, 12, 11), (77, 53, 2, 18, 12), (130, 41, 3, 5, 13),
+                                          (40, 97, 4, 18, 14)])
+def test_search_bit_exact(ff, W, H, r, S, seed):
+    _say(f"sift search {W}x{H} r={r} S={S}")
+    p = pairs.layered_pair(seed=seed, W=W, H=H)
+    f, c, rf, rc = _search_case(ff, p.img1, p.img2, r, S, 18, seed=seed, field_id=1, pair_id=3)
+    assert np.array_equal(f, rf), int((f != rf).sum())
+    assert np.array_equal(c, rc), int((c != rc).sum())
+
+
+@pytest.mark.parametrize("steps", [1, 2, 3, 4, 8, 9, 16])
+def test_search_intermediate_stops(ff, steps):
+    p = pairs.layered_pair(seed=21, W=72, H=40)
+    f, c, rf, rc = _search_case(ff, p.img1, p.img2, 3, 12, 12, max_steps=steps, seed=21)
+    assert np.array_equal(f, rf) and np.array_equal(c, rc), steps
+
+
+@pytest.mark.parametrize("Q", [1, 2, 8])
+def test_search_other_subpel(ff, Q):
+    p = pairs.layered_pair(seed=31, W=64, H=48)
+    f, c, rf, rc = _search_case(ff, p.img1, p.img2, 3, 12, 12, Q=Q, seed=31)
+    assert np.array_equal(f, rf) and np.array_equal(c, rc), Q
+
+
+def test_search_gray_and_different_sizes(ff):
+    a = _texture(70, 50, 41)
+    b = _texture(58, 63, 42)
+    f, c, rf, rc = _search_case(ff, a, b, 3, 12, 12, k=2, seed=41)
+    assert np.array_equal(f, rf) and np.array_equal(c, rc)
+
+
+def test_pair_path_bit_exact_on_oracle_codes(ff):
+    """The whole pair path of SiftPairMatcher (KITTI setting) given the
+    oracle's colours: every output equal to the oracle's."""
+    p = pairs.layered_pair(seed=51, W=120, H=72)
+    ref = ffo.match_pair_sift(p.img1, p.img2, seed=51, pair_id=2)
+    m = ff.SiftPairMatcher(120, 72)
+    codes = (torch.from_numpy(ref["codes1"]).cuda(), torch.from_numpy(ref["codes2"]).cuda())
+    out = m.run(torch.from_numpy(p.img1).cuda(), torch.from_numpy(p.img2).cuda(), seed=51, pair_id=2, codes=codes)
+    torch.cuda.synchronize()
+    assert m.status() == 0
+    for key in ("F", "CF", "B1", "CB1", "B2", "CB2", "keep", "filtered", "region_label", "keep_region",
+                "filtered_region", "pick", "sparse"):
+        g = out[key].cpu().numpy()
+        assert np.array_equal(g, ref[key]), (key, int((g != ref[key]).sum()))
+
+
+def test_pair_path_own_colors(ff):
+    """With the GPU's own colours (codes within 1 of the oracle's), the fields
+    agree with the oracle's almost everywhere and are as accurate."""
+    p = pairs.layered_pair(seed=61, W=128, H=80)
+    ref = ffo.match_pair_sift(p.img1, p.img2, seed=61)
+    m = ff.SiftPairMatcher(128, 80)
+    out = m.run(torch.from_numpy(p.img1).cuda(), torch.from_numpy(p.img2).cuda(), seed=61)
+    torch.cuda.synchronize()
+    assert m.status() == 0
+    F = out["F"].cpu().numpy()
+    agree = (F == ref["F"]).mean()
+    _say(f"own colours: F agrees at {agree:.4f}")
+    assert agree >= 0.95
+    ig, ir = pairs.inlier_rate(F, p, 4), pairs.inlier_rate(ref["F"], p, 4)
+    assert abs(ig - ir) <= 0.02, (ig, ir)
