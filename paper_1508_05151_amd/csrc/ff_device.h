@@ -25,4 +25,51 @@ __device__ __forceinline__ void philox2(uint32_t c0, uint32_t c1, uint32_t c2, u
   o1 = c1;
 }
 
+// sum over a 16-lane DPP row, left in every lane of the row: swap adjacent
+// lanes, swap lane pairs, mirror within half-rows (quad 0 <-> quad 1), mirror
+// within the row (half 0 <-> half 1)
+__device__ __forceinline__ int32_t row16_sum(int32_t v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);  // row_mirror
+  return v;
+}
+
+// the same for a double (each 32-bit half moved by the same DPP pattern);
+// every lane of the row ends with the bitwise same sum
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double row16_sum_f64(double v) {
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  v += dpp_f64<0x141>(v);
+  v += dpp_f64<0x140>(v);
+  return v;
+}
+
+// sum over the 64 lanes of a wavefront (uniform result)
+__device__ __forceinline__ int32_t wave_sum(int32_t v) {
+  v = row16_sum(v);
+  return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) + __builtin_amdgcn_readlane(v, 32) +
+         __builtin_amdgcn_readlane(v, 48);
+}
+
+
+// Workgroup barrier for LDS handoffs only: waits for this wavefront's LDS
+// operations, not for its outstanding global loads (the next step's target
+// words stay in flight across it); the workgroup runs on
+// one CU, so completed LDS writes are visible to every wavefront after it.
+__device__ __forceinline__ void lds_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt and expcnt not waited
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 }  // namespace ff

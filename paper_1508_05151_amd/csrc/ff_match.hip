@@ -145,16 +145,6 @@ __device__ __forceinline__ int32_t rows_sum_n1(SP sb, int spw, int sy0, int syma
   return sum;
 }
 
-// sum over a 16-lane DPP row, left in every lane of the row: swap adjacent
-// lanes, swap lane pairs, mirror within half-rows (quad 0 <-> quad 1), mirror
-// within the row (half 0 <-> half 1)
-__device__ __forceinline__ int32_t row16_sum(int32_t v) {
-  v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
-  v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
-  v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
-  v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);  // row_mirror
-  return v;
-}
 
 // ---------------------------------------------------------------- field table
 struct RecChunk {
@@ -429,16 +419,6 @@ constexpr int kBatch = 32;
 
 typedef __attribute__((address_space(1))) const char g_byte;
 
-// Workgroup barrier for LDS handoffs only: waits for this wavefront's LDS
-// operations, not for its outstanding global loads (the next step's target
-// words stay in flight across it); the workgroup runs on
-// one CU, so completed LDS writes are visible to every wavefront after it.
-__device__ __forceinline__ void lds_barrier() {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt and expcnt not waited
-  __builtin_amdgcn_s_barrier();
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
 
 __device__ __forceinline__ int med3i(int v, int lo, int hi) { return min(max(v, lo), hi); }
 // clamp to [0, hi] in one instruction (the compiler emits max then min when

@@ -10,8 +10,8 @@
 // windows (32 values per pixel), a second pass filters along y with the four
 // cell-row windows and normalises (fp32 throughout).  The PCA basis of a
 // pair comes from the fp64 covariance of both images' vectors: per-workgroup
-// fp64 Gram partials, a fixed-order reduction, and a cyclic Jacobi
-// eigen-solver in one workgroup whose matrix stays in LDS (128 x 129
+// fp64 Gram partials, a fixed-order reduction, and a one-sided Jacobi
+// eigen-solver in one workgroup whose matrix stays in LDS (128 x 130
 // doubles).  The projection on the first S eigenvectors is fp64 and is
 // quantised to int16 codes, round-half-even(1024 c).
 //
@@ -28,6 +28,7 @@
 #include <mutex>
 #include <vector>
 
+#include "ff_device.h"
 #include "ff_internal.h"
 
 namespace ff {
@@ -255,20 +256,27 @@ __global__ void k_sift_gram_reduce(const double* __restrict__ part, int nparts, 
   out[e] = s / (double)N;
 }
 
-// ---------------------------------------------------------------- PCA: Jacobi eigen-solver
-// Cyclic Jacobi on the 128 x 128 covariance in LDS (pitch 129 doubles: the
-// column walks of a rotation fall in different banks).  A sweep is 127
-// rounds of the round-robin tournament, each 64 disjoint rotations: the
-// angles (Golub & Van Loan's symmetric Schur step, zeroing a_pq), then the
-// row update A <- J^T A, then the column update A <- A J together with the
-// eigenvector update Vt <- J^T Vt (Vt = V transposed, in global memory,
-// rows contiguous).  Sweeps stop once the off-diagonal squares fall below
-// 1e-24 of the total (or after 20).  Then eigenvalues are ranked descending
-// (ties by index), each eigenvector's largest-magnitude component (the first
-// on ties) is made positive, and out receives mean (128), eigenvalues (128)
-// and the basis (128 x 128, element [k][s] = component k of eigenvector s).
-constexpr int kJP = kSiftDim + 1;
-constexpr int kJacobiSweeps = 20;
+// ---------------------------------------------------------------- PCA: one-sided Jacobi eigen-solver
+// The covariance C (128 x 128, positive semi-definite) is orthogonalised by
+// one-sided (Hestenes) Jacobi rotations of its columns, M <- M J with M = C
+// at the start: a pair of columns (p, q) with norms a = |m_p|^2, b = |m_q|^2
+// and product g = m_p . m_q is rotated by the angle that makes them
+// orthogonal (zeta = (b - a) / (2 g), t = sign(zeta) / (|zeta| +
+// sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2), s = t c).  At convergence M = C V
+// with orthogonal columns, so C^2 is diagonal in V and column i is
+// lambda_i v_i: the eigenvalues are the column norms and the eigenvectors
+// the normalised columns -- no rotation product is accumulated, and the
+// whole matrix stays in LDS.  A sweep is 127 rounds of the round-robin
+// tournament, 64 disjoint pairs per round, 16 lanes per pair (dot products
+// by DPP row sums, one barrier per round).  Pairs whose columns are already
+// orthogonal to 1e-13 of their norms are left alone; sweeps stop when none
+// is rotated (or after 30).  Eigenvalues are then ranked descending (ties by
+// index), each eigenvector's largest-magnitude component (the first on
+// ties) is made positive, and out receives mean (128), eigenvalues (128) and
+// the basis (128 x 128, element [k][s] = component k of eigenvector s).
+constexpr int kMP = kSiftDim + 2;   // LDS row pitch (doubles): the 4 pairs of a wavefront in different banks
+constexpr int kJacobiSweeps = 30;
+constexpr double kOrthTol = 1e-13;
 
 __device__ __forceinline__ void tourney(int round, int k, int& p, int& q) {
   // circle method: player 0 fixed, players 1..127 rotate
@@ -282,102 +290,72 @@ __device__ __forceinline__ void tourney(int round, int k, int& p, int& q) {
   }
 }
 
-__global__ __launch_bounds__(1024) void k_sift_eig(const double* __restrict__ raw, double* __restrict__ Vt,
-                                                   double* __restrict__ out) {
-  __shared__ double A[kSiftDim * kJP];
-  __shared__ int rp[64], rq[64];
-  __shared__ double rc[64], rs[64];
-  __shared__ double red[32], red2[32];
+__global__ __launch_bounds__(1024) void k_sift_eig(const double* __restrict__ raw, double* __restrict__ out) {
+  __shared__ double Mt[kSiftDim * kMP];   // row i = column i of M
+  __shared__ int s_rot[16];
+  __shared__ double s_norm[kSiftDim];
   __shared__ int s_rank[kSiftDim];
   const int t = threadIdx.x;
   const double* mean = raw + kSiftDim * kSiftDim;
   for (int e = t; e < kSiftDim * kSiftDim; e += 1024) {
     const int i = e >> 7, j = e & 127;
-    A[i * kJP + j] = raw[e] - mean[i] * mean[j];
-    Vt[e] = i == j ? 1.0 : 0.0;
+    Mt[i * kMP + j] = raw[e] - mean[i] * mean[j];
   }
   __syncthreads();
+  const int g = t >> 4, l = t & 15;
   for (int sweep = 0; sweep < kJacobiSweeps; ++sweep) {
-    // convergence: off-diagonal and total sums of squares
-    double off = 0.0, tot = 0.0;
-    for (int e = t; e < kSiftDim * kSiftDim; e += 1024) {
-      const int i = e >> 7, j = e & 127;
-      const double v = A[i * kJP + j];
-      tot += v * v;
-      if (i != j) off += v * v;
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      off += __shfl_xor(off, o);
-      tot += __shfl_xor(tot, o);
-    }
-    if ((t & 63) == 0) {
-      red[t >> 6] = off;
-      red2[t >> 6] = tot;
-    }
-    __syncthreads();
-    off = 0.0;
-    tot = 0.0;
-    for (int w = 0; w < 16; ++w) {
-      off += red[w];
-      tot += red2[w];
-    }
-    __syncthreads();
-    if (!(off > 1e-24 * tot)) break;   // uniform across the workgroup
+    int rotated = 0;
     for (int round = 0; round < 127; ++round) {
-      if (t < 64) {
-        int p, q;
-        tourney(round, t, p, q);
-        const double app = A[p * kJP + p], aqq = A[q * kJP + q], apq = A[p * kJP + q];
-        double c = 1.0, s = 0.0;
-        if (apq != 0.0) {
-          const double tau = (aqq - app) / (2.0 * apq);
-          const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + tt * tt);
-          s = tt * c;
+      int p, q;
+      tourney(round, g, p, q);
+      double* mp = Mt + p * kMP;
+      double* mq = Mt + q * kMP;
+      double x[8], y[8];
+      double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        x[i] = mp[l + 16 * i];
+        y[i] = mq[l + 16 * i];
+        a = fma(x[i], x[i], a);
+        b = fma(y[i], y[i], b);
+        c = fma(x[i], y[i], c);
+      }
+      a = row16_sum_f64(a);   // the pair's 16 lanes are one DPP row
+      b = row16_sum_f64(b);
+      c = row16_sum_f64(c);
+      if (fabs(c) > kOrthTol * sqrt(a * b)) {   // the same in all 16 lanes of the pair
+        const double zeta = (b - a) / (2.0 * c);
+        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = tt * cs;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          mp[l + 16 * i] = cs * x[i] - sn * y[i];
+          mq[l + 16 * i] = sn * x[i] + cs * y[i];
         }
-        rp[t] = p;
-        rq[t] = q;
-        rc[t] = c;
-        rs[t] = s;
-      }
-      __syncthreads();
-      // rows p, q of A (and of Vt): 64 pairs x 128 columns
-#pragma unroll
-      for (int it = 0; it < 8; ++it) {
-        const int idx = t + it * 1024;
-        const int k = idx >> 7, j = idx & 127;
-        const int p = rp[k], q = rq[k];
-        const double c = rc[k], s = rs[k];
-        const double apj = A[p * kJP + j], aqj = A[q * kJP + j];
-        A[p * kJP + j] = c * apj - s * aqj;
-        A[q * kJP + j] = s * apj + c * aqj;
-        const double vpj = Vt[p * kSiftDim + j], vqj = Vt[q * kSiftDim + j];
-        Vt[p * kSiftDim + j] = c * vpj - s * vqj;
-        Vt[q * kSiftDim + j] = s * vpj + c * vqj;
-      }
-      __syncthreads();
-      // columns p, q of A
-#pragma unroll
-      for (int it = 0; it < 8; ++it) {
-        const int idx = t + it * 1024;
-        const int k = idx >> 7, j = idx & 127;
-        const int p = rp[k], q = rq[k];
-        const double c = rc[k], s = rs[k];
-        const double ajp = A[j * kJP + p], ajq = A[j * kJP + q];
-        A[j * kJP + p] = c * ajp - s * ajq;
-        A[j * kJP + q] = s * ajp + c * ajq;
+        rotated = 1;
       }
       __syncthreads();
     }
+    // any rotation in this sweep?
+    const int any = __any(rotated) ? 1 : 0;
+    if ((t & 63) == 0) s_rot[t >> 6] = any;
+    __syncthreads();
+    int tot = 0;
+    for (int w = 0; w < 16; ++w) tot |= s_rot[w];
+    __syncthreads();
+    if (!tot) break;
   }
-  // every thread's Vt stores complete and visible before the ranking reads
-  __threadfence_block();
+  if (t < kSiftDim) {
+    double nn = 0.0;
+    for (int k = 0; k < kSiftDim; ++k) nn = fma(Mt[t * kMP + k], Mt[t * kMP + k], nn);
+    s_norm[t] = sqrt(nn);
+  }
   __syncthreads();
   if (t < kSiftDim) {
-    const double li = A[t * kJP + t];
+    const double li = s_norm[t];
     int rank = 0;
     for (int j = 0; j < kSiftDim; ++j) {
-      const double lj = A[j * kJP + j];
+      const double lj = s_norm[j];
       rank += (lj > li || (lj == li && j < t)) ? 1 : 0;
     }
     s_rank[t] = rank;
@@ -386,8 +364,8 @@ __global__ __launch_bounds__(1024) void k_sift_eig(const double* __restrict__ ra
   }
   __syncthreads();
   if (t < kSiftDim) {
-    // eigenvector t (row t of Vt) becomes basis column s_rank[t]
-    const double* v = Vt + (size_t)t * kSiftDim;
+    // column t of M becomes basis column s_rank[t]
+    const double* v = Mt + t * kMP;
     int m = 0;
     double best = fabs(v[0]);
     for (int k = 1; k < kSiftDim; ++k)
@@ -395,9 +373,9 @@ __global__ __launch_bounds__(1024) void k_sift_eig(const double* __restrict__ ra
         best = fabs(v[k]);
         m = k;
       }
-    const double sg = v[m] < 0.0 ? -1.0 : 1.0;
+    const double inv = s_norm[t] > 0.0 ? (v[m] < 0.0 ? -1.0 : 1.0) / s_norm[t] : 0.0;
     const int s = s_rank[t];
-    for (int k = 0; k < kSiftDim; ++k) out[2 * kSiftDim + k * kSiftDim + s] = sg * v[k];
+    for (int k = 0; k < kSiftDim; ++k) out[2 * kSiftDim + k * kSiftDim + s] = v[k] * inv;
   }
 }
 
@@ -458,7 +436,7 @@ static void enqueue_project(const float* D, int N, const double* pca, int S, int
 
 // ---------------------------------------------------------------- colour-stage layout
 struct SiftColorLayout {
-  size_t off_A, off_D1, off_D2, off_part, off_raw, off_vt, off_pca;
+  size_t off_A, off_D1, off_D2, off_part, off_raw, off_pca;
   int nparts, rows_per_wg;
   size_t bytes;
 };
@@ -482,8 +460,6 @@ static SiftColorLayout sift_color_layout(int w1, int h1, int w2, int h2) {
   off = align_up(off + (size_t)L.nparts * kPartDoubles * 8, 256);
   L.off_raw = off;
   off = align_up(off + (size_t)kPartDoubles * 8, 256);
-  L.off_vt = off;
-  off = align_up(off + (size_t)kSiftDim * kSiftDim * 8, 256);
   L.off_pca = off;
   off = align_up(off + (size_t)(2 * kSiftDim + kSiftDim * kSiftDim) * 8, 256);
   L.bytes = off;
@@ -545,7 +521,6 @@ ff_status ff_sift_colors(const uint8_t* L1, int32_t w1, int32_t h1, const uint8_
   float* D2 = desc2 ? desc2 : reinterpret_cast<float*>(ws + Lo.off_D2);
   double* part = reinterpret_cast<double*>(ws + Lo.off_part);
   double* raw = reinterpret_cast<double*>(ws + Lo.off_raw);
-  double* vt = reinterpret_cast<double*>(ws + Lo.off_vt);
   double* P = pca ? pca : reinterpret_cast<double*>(ws + Lo.off_pca);
   const int N1 = w1 * h1, N2 = w2 * h2;
   prof_mark(FF_PROF_SIFT_COLORS, stream, true);
@@ -554,7 +529,7 @@ ff_status ff_sift_colors(const uint8_t* L1, int32_t w1, int32_t h1, const uint8_
   prof_mark(FF_PROF_SIFT_PCA, stream, true);
   k_sift_gram<<<Lo.nparts, 256, 0, stream>>>(D1, N1, D2, N2, Lo.rows_per_wg, part);
   k_sift_gram_reduce<<<(kPartDoubles + 255) / 256, 256, 0, stream>>>(part, Lo.nparts, N1 + N2, raw);
-  k_sift_eig<<<1, 1024, 0, stream>>>(raw, vt, P);
+  k_sift_eig<<<1, 1024, 0, stream>>>(raw, P);
   prof_mark(FF_PROF_SIFT_PCA, stream, false);
   enqueue_project(D1, N1, P, S, codes1, stream);
   enqueue_project(D2, N2, P, S, codes2, stream);

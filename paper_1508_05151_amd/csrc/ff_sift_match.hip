@@ -15,13 +15,16 @@
 // (Eq. 4); per level the alternating propagation sweeps (Eq. 2) and random
 // searches (R_n = R n), coarse flows seeding the next level.
 //
-// Propagation: one workgroup per band of 16 grid rows, 16 lanes per point.
+// Propagation: one workgroup per band of 16 grid rows, one wavefront per row.
 // At step t, row i of the band handles column u = t - i (sweep-transformed
 // coordinates): its vertical candidate is row i - 1's result of step t - 1
 // (LDS), its horizontal candidate its own result of step t - 1; row 0 takes
-// the band above's last-row result from a 64-bit word (launch tag | flow)
-// that the band above stores with an agent-scope atomic.  Bands are numbered
-// by a ticket, so a band only ever waits on a band that started before it.
+// the band above's last-row result from a 64-bit word (cost | flow) that the
+// band above stores with an agent-scope atomic.  A candidate is costed with
+// a sliding window: its predecessor's cost minus the row (column) leaving
+// the patch plus the one entering it, 2 (2r+1) samples, all loaded at once.
+// Bands are numbered by a ticket, so a band only ever waits on a band that
+// started before it.
 #include <algorithm>
 #include <vector>
 
@@ -31,7 +34,7 @@
 namespace ff {
 
 constexpr int kSBand = 16;    // grid rows per propagation band
-constexpr int kSLanes = 16;   // lanes per point (propagation, entry, random search)
+constexpr int kSLanes = 16;   // lanes per point (entry, random search): one DPP row
 constexpr int kSiftRecsPerWrite = 16;
 constexpr int kSiftStatusBytes = 256;
 
@@ -85,9 +88,11 @@ __device__ __forceinline__ bool svalid(const SCtx& c, int px, int py, int32_t f)
   return mx >= 0 && my >= 0 && mx <= (c.Wd - 1) * c.Q && my <= (c.Hd - 1) * c.Q;
 }
 
-// floor(sqrt(v)) for v < 2^46: a float estimate, corrected exactly
+// floor(sqrt(v)) for v < 2^46: a float estimate (from the two 32-bit
+// halves), corrected exactly
 __device__ __forceinline__ uint32_t isqrt_u64(uint64_t v) {
-  uint32_t k = (uint32_t)sqrtf((float)v);
+  const float fv = fmaf((float)(uint32_t)(v >> 32), 4294967296.0f, (float)(uint32_t)v);
+  uint32_t k = (uint32_t)sqrtf(fv);
   while ((uint64_t)k * k > v) --k;
   while ((uint64_t)(k + 1) * (k + 1) <= v) ++k;
   return k;
@@ -113,72 +118,82 @@ __device__ __forceinline__ Tgt tgt_of(const SCtx& c, int px, int py, int32_t f) 
   return t;
 }
 
-// distance of one sample: source colour at (sx, sy), target bilinear at
-// (X, Y) (already clamped)
-__device__ __forceinline__ int32_t sample_dist(const SCtx& c, const short4_t* __restrict__ ps, const Tgt& t, int X,
-                                               int Y) {
+// The colours of one pixel as SG groups of 4 int16 (8-byte loads).  Groups
+// at or past the field's ceil(S/4) are not loaded (zero, and masked out by
+// the channel test).
+template <int SG>
+struct Px {
+  short4_t v[SG];
+};
+
+template <int SG>
+__device__ __forceinline__ Px<SG> load_px(const int16_t* p, int sgf) {
+  Px<SG> r;
+  const short4_t* q = reinterpret_cast<const short4_t*>(p);
+#pragma unroll
+  for (int g = 0; g < SG; ++g) {
+    if (g < sgf)   // uniform: a field's channel count
+      r.v[g] = q[g];
+    else
+      r.v[g] = short4_t{0, 0, 0, 0};
+  }
+  return r;
+}
+
+// the target's four neighbours of (X, Y) (already clamped)
+template <int SG>
+struct Quad {
+  Px<SG> p00, p10, p01, p11;
+};
+
+template <int SG>
+__device__ __forceinline__ Quad<SG> load_quad(const SCtx& c, int X, int Y, int sgf) {
   const int X1 = min(X + 1, c.Wd - 1), Y1 = min(Y + 1, c.Hd - 1);
   const int16_t* r0 = c.dst + (size_t)Y * c.Wd * c.P;
   const int16_t* r1 = c.dst + (size_t)Y1 * c.Wd * c.P;
-  const short4_t* p00 = reinterpret_cast<const short4_t*>(r0 + (size_t)X * c.P);
-  const short4_t* p10 = reinterpret_cast<const short4_t*>(r0 + (size_t)X1 * c.P);
-  const short4_t* p01 = reinterpret_cast<const short4_t*>(r1 + (size_t)X * c.P);
-  const short4_t* p11 = reinterpret_cast<const short4_t*>(r1 + (size_t)X1 * c.P);
+  Quad<SG> q;
+  q.p00 = load_px<SG>(r0 + (size_t)X * c.P, sgf);
+  q.p10 = load_px<SG>(r0 + (size_t)X1 * c.P, sgf);
+  q.p01 = load_px<SG>(r1 + (size_t)X * c.P, sgf);
+  q.p11 = load_px<SG>(r1 + (size_t)X1 * c.P, sgf);
+  return q;
+}
+
+// floor(sqrt(sum_s d_s^2 * 256 / Q^4)) of one sample
+template <int SG>
+__device__ __forceinline__ int32_t dist_of(const SCtx& c, const Px<SG>& a, const Quad<SG>& q, const Tgt& t) {
   const int QQ = c.Q * c.Q;
   uint64_t ss = 0;
-  for (int g = 0; g * 4 < c.S; ++g) {
-    const short4_t a = ps[g], b00 = p00[g], b10 = p10[g], b01 = p01[g], b11 = p11[g];
+#pragma unroll
+  for (int g = 0; g < SG; ++g)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int e = QQ * (int)a[i] - (t.w00 * (int)b00[i] + t.w10 * (int)b10[i] + t.w01 * (int)b01[i] +
-                                      t.w11 * (int)b11[i]);
+      const int e = QQ * (int)a.v[g][i] - (t.w00 * (int)q.p00.v[g][i] + t.w10 * (int)q.p10.v[g][i] +
+                                           t.w01 * (int)q.p01.v[g][i] + t.w11 * (int)q.p11.v[g][i]);
       const int em = g * 4 + i < c.S ? e : 0;
       ss += (uint64_t)((int64_t)em * em);
     }
-  }
   const uint64_t v = c.qshift <= 2 ? ss << (8 - 4 * c.qshift) : ss >> 4;
   return (int32_t)isqrt_u64(v);
 }
 
 // this lane's share (samples lane, lane + L, ...) of E for candidate f
+template <int SG>
 __device__ __forceinline__ int32_t sift_partial(const SCtx& c, int px, int py, int32_t f, int lane, int L) {
   const Tgt t = tgt_of(c, px, py, f);
-  const int Sd = 2 * c.r + 1;
+  const int Sd = 2 * c.r + 1, sgf = (c.S + 3) >> 2;
   int32_t sum = 0;
   for (int k = lane; k < Sd * Sd; k += L) {
     const int iy = k / Sd, ix = k - iy * Sd;
     const int dx = (ix - c.r) * c.n, dy = (iy - c.r) * c.n;
     const int sx = clampi(px + dx, 0, c.Ws - 1), sy = clampi(py + dy, 0, c.Hs - 1);
-    const short4_t* ps = reinterpret_cast<const short4_t*>(c.src + ((size_t)sy * c.Ws + sx) * c.P);
-    sum += sample_dist(c, ps, t, clampi(t.Mx + dx, 0, c.Wd - 1), clampi(t.My + dy, 0, c.Hd - 1));
+    const Px<SG> a = load_px<SG>(c.src + ((size_t)sy * c.Ws + sx) * c.P, sgf);
+    const Quad<SG> q = load_quad<SG>(c, clampi(t.Mx + dx, 0, c.Wd - 1), clampi(t.My + dy, 0, c.Hd - 1), sgf);
+    sum += dist_of<SG>(c, a, q, t);
   }
   return sum;
 }
 
-// both propagation candidates of one point in one walk (the source sample
-// is shared); a disabled candidate adds nothing
-__device__ __forceinline__ void sift_partial2(const SCtx& c, int px, int py, bool useA, int32_t fA, bool useB,
-                                              int32_t fB, int lane, int L, int32_t& sA, int32_t& sB) {
-  const Tgt ta = tgt_of(c, px, py, useA ? fA : 0), tb = tgt_of(c, px, py, useB ? fB : 0);
-  const int Sd = 2 * c.r + 1;
-  sA = 0;
-  sB = 0;
-  for (int k = lane; k < Sd * Sd; k += L) {
-    const int iy = k / Sd, ix = k - iy * Sd;
-    const int dx = (ix - c.r) * c.n, dy = (iy - c.r) * c.n;
-    const int sx = clampi(px + dx, 0, c.Ws - 1), sy = clampi(py + dy, 0, c.Hs - 1);
-    const short4_t* ps = reinterpret_cast<const short4_t*>(c.src + ((size_t)sy * c.Ws + sx) * c.P);
-    if (useA) sA += sample_dist(c, ps, ta, clampi(ta.Mx + dx, 0, c.Wd - 1), clampi(ta.My + dy, 0, c.Hd - 1));
-    if (useB) sB += sample_dist(c, ps, tb, clampi(tb.Mx + dx, 0, c.Wd - 1), clampi(tb.My + dy, 0, c.Hd - 1));
-  }
-}
-
-template <int L>
-__device__ __forceinline__ int32_t lane_sum(int32_t v) {
-#pragma unroll
-  for (int o = L / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, L);
-  return v;
-}
 
 // ---------------------------------------------------------------- table, clears
 struct SiftChunk {
@@ -195,18 +210,20 @@ __global__ void k_tree_write_table(TreeChunk chunk, int n, FieldRec* __restrict_
   if ((int)threadIdx.x < n) out[threadIdx.x] = chunk.r[threadIdx.x];
 }
 
-// zero every field's handoff words (grid: chunks x fields)
+// mark every field's first handoff buffer empty (grid: chunks x fields)
 __global__ void k_sift_clear_xch(const SiftRec* __restrict__ table) {
   const SiftRec& f = table[blockIdx.y];
   uint64_t* x = reinterpret_cast<uint64_t*>(f.ws + f.o_xch);
   const size_t nw = (size_t)((f.Hs + kSBand - 1) / kSBand) * f.Ws;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += (size_t)gridDim.x * blockDim.x) x[i] = 0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += (size_t)gridDim.x * blockDim.x)
+    x[i] = ~0ull;
 }
 
 // ---------------------------------------------------------------- seeds (Eq. 1 / Eq. 4)
 // One wavefront per coarse grid point: descend the kd-tree with the source
 // WHT vector, re-rank the leaf (ascending pixel index) by the data term;
 // the first minimum wins.  grid: (points / 4, fields)
+template <int SG>
 __global__ __launch_bounds__(256) void k_sift_seed(const SiftRec* __restrict__ table, int lev, int qshift) {
   const SiftRec& f = table[blockIdx.y];
   const SCtx c = sctx_of(f, lev, qshift);
@@ -239,7 +256,7 @@ __global__ __launch_bounds__(256) void k_sift_seed(const SiftRec* __restrict__ t
   for (int i = 0; i < cnt && start + i < Nd; ++i) {
     const int id = perm[start + i];
     const int32_t fl = packf((id % f.Wd - px) * c.Q, (id / f.Wd - py) * c.Q);
-    const int32_t e = lane_sum<64>(sift_partial(c, px, py, fl, lane, 64));
+    const int32_t e = wave_sum(sift_partial<SG>(c, px, py, fl, lane, 64));
     if (e < bestC) {
       bestC = e;
       bestF = fl;
@@ -255,6 +272,7 @@ __global__ __launch_bounds__(256) void k_sift_seed(const SiftRec* __restrict__ t
 // Section 3.2: the coarser grid's points keep their flow, re-costed with
 // this level's patch; new points start empty.  16 lanes per coarse point,
 // which also write the three new points it covers.
+template <int SG>
 __global__ __launch_bounds__(256) void k_sift_entry(const SiftRec* __restrict__ table, int lev, int qshift) {
   const SiftRec& f = table[blockIdx.y];
   const SCtx c = sctx_of(f, lev, qshift);
@@ -266,7 +284,7 @@ __global__ __launch_bounds__(256) void k_sift_entry(const SiftRec* __restrict__ 
   const int gx = 2 * (cid % Gwc), gy = 2 * (cid / Gwc);
   const int32_t fl = sgrid_flow(f, lev + 1)[cid];
   int32_t e = kInf;
-  if (fl != kEmpty) e = lane_sum<kSLanes>(sift_partial(c, gx * c.n, gy * c.n, fl, lane, kSLanes));
+  if (fl != kEmpty) e = row16_sum(sift_partial<SG>(c, gx * c.n, gy * c.n, fl, lane, kSLanes));
   if (lane < 4) {
     const int x = gx + (lane & 1), y = gy + (lane >> 1);
     if (x < Gw && y < Gh) {
@@ -280,6 +298,7 @@ __global__ __launch_bounds__(256) void k_sift_entry(const SiftRec* __restrict__ 
 // One offset per point, per axis an integer in [-nRQ, nRQ] 1/Q px from
 // Philox keyed by the seed with counter (pixel, level, step, field | pair
 // << 2); replace only on a strictly lower cost.  16 lanes per point.
+template <int SG>
 __global__ __launch_bounds__(256) void k_sift_rs(const SiftRec* __restrict__ table, int lev, int qshift, int step,
                                                  int R) {
   const SiftRec& f = table[blockIdx.y];
@@ -299,7 +318,7 @@ __global__ __launch_bounds__(256) void k_sift_rs(const SiftRec* __restrict__ tab
   const uint64_t span = (uint64_t)(2 * rad + 1);
   const int32_t cand = packf(fx_of(fl) + (int)((u0 * span) >> 32) - rad, fy_of(fl) + (int)((u1 * span) >> 32) - rad);
   if (!svalid(c, px, py, cand)) return;
-  const int32_t e = lane_sum<kSLanes>(sift_partial(c, px, py, cand, lane, kSLanes));
+  const int32_t e = row16_sum(sift_partial<SG>(c, px, py, cand, lane, kSLanes));
   if (lane == 0 && e < C[pid]) {
     F[pid] = cand;
     C[pid] = e;
@@ -313,22 +332,61 @@ __global__ __launch_bounds__(256) void k_sift_rs(const SiftRec* __restrict__ tab
 // equal to the current flow is not evaluated (it cannot win).
 __device__ __forceinline__ uint64_t rt_now() { return __builtin_amdgcn_s_memrealtime(); }
 
-__global__ __launch_bounds__(kSBand * kSLanes) void k_sift_prop(const SiftRec* __restrict__ table, int nf, int lev,
-                                                                int qshift, int sx, int sy, uint32_t tag,
-                                                                int32_t* __restrict__ ticket,
-                                                                int32_t* __restrict__ status, uint64_t timeout) {
-  __shared__ int32_t s_field, s_band;
-  __shared__ int32_t res[2][kSBand];
+// One signed sliding-window term of a propagated candidate: lane k of
+// 4 (2r+1) covers group k / (2r+1) -- 0 / 1: the row leaving / entering the
+// patch of the vertical candidate, 2 / 3: the column leaving / entering for
+// the horizontal one -- at free offset k mod (2r+1) - r.  In the sweep
+// direction (sx, sy) the entering row is at sy r and the leaving one at
+// -sy (r + 1) (columns likewise with sx): E(p, F(q)) = C(q) - leaving +
+// entering, exact because every lookup clamps per coordinate.
+template <int SG>
+__device__ __forceinline__ void slide_terms(const SCtx& c, int px, int py, int sx, int sy, bool useV, const Tgt& tv,
+                                            bool useH, const Tgt& th, int lane, int32_t& sV, int32_t& sH) {
+  const int Sd = 2 * c.r + 1, sgf = (c.S + 3) >> 2;
+  sV = 0;
+  sH = 0;
+  for (int k = lane; k < 4 * Sd; k += 64) {
+    const int grp = k / Sd, o = k - grp * Sd - c.r;
+    const bool vert = grp < 2, enter = (grp & 1) != 0;
+    const int across = vert ? sy : sx;
+    const int a = enter ? across * c.r : -across * (c.r + 1);
+    const int dx = (vert ? o : a) * c.n, dy = (vert ? a : o) * c.n;
+    const Tgt& t = vert ? tv : th;
+    const int sxp = clampi(px + dx, 0, c.Ws - 1), syp = clampi(py + dy, 0, c.Hs - 1);
+    const Px<SG> pa = load_px<SG>(c.src + ((size_t)syp * c.Ws + sxp) * c.P, sgf);
+    const Quad<SG> q = load_quad<SG>(c, clampi(t.Mx + dx, 0, c.Wd - 1), clampi(t.My + dy, 0, c.Hd - 1), sgf);
+    const int32_t d = dist_of<SG>(c, pa, q, t);
+    const int32_t sd = enter ? d : -d;
+    if (vert)
+      sV += useV ? sd : 0;
+    else
+      sH += useH ? sd : 0;
+  }
+}
+
+// Handoff words between bands: (cost << 32) | flow, all ones while not yet
+// written (no cost is 0xFFFFFFFF).  Launch L of a call reads and writes
+// buffer L & 1 and clears buffer (L + 1) & 1 for the next launch.
+constexpr uint64_t kXchEmpty = ~0ull;
+
+template <int SG>
+__global__ __launch_bounds__(kSBand * 64) void k_sift_prop(const SiftRec* __restrict__ table, int nf, int lev,
+                                                           int qshift, int sx, int sy, int parity,
+                                                           int32_t* __restrict__ ticket,
+                                                           int32_t* __restrict__ status, uint64_t timeout) {
+  __shared__ int32_t s_field, s_band, s_nb;
+  __shared__ int32_t resF[2][kSBand], resC[2][kSBand];
   if (threadIdx.x == 0) {
-    int tk = atomicAdd(ticket, 1), fi = 0;
+    int tk = atomicAdd(ticket, 1), fi = 0, nb = 0;
     for (; fi < nf; ++fi) {
       const int gh = (table[fi].Hs + (1 << lev) - 1) >> lev;
-      const int nb = (gh + kSBand - 1) / kSBand;
+      nb = (gh + kSBand - 1) / kSBand;
       if (tk < nb) break;
       tk -= nb;
     }
     s_field = fi;
     s_band = tk;
+    s_nb = nb;
   }
   __syncthreads();
   if (s_field >= nf) return;
@@ -337,29 +395,54 @@ __global__ __launch_bounds__(kSBand * kSLanes) void k_sift_prop(const SiftRec* _
   const int n = c.n;
   const int Gw = (f.Ws + n - 1) >> lev, Gh = (f.Hs + n - 1) >> lev;
   const int band = s_band, v0 = band * kSBand;
+  const size_t xwords = (size_t)((f.Hs + kSBand - 1) / kSBand) * f.Ws;   // one buffer
+  uint64_t* const xbase = reinterpret_cast<uint64_t*>(f.ws + f.o_xch);
+  {
+    // this band's share of the next launch's buffer
+    uint64_t* nxt = xbase + (size_t)(parity ^ 1) * xwords;
+    const size_t per = (xwords + s_nb - 1) / s_nb;
+    const size_t e0 = (size_t)band * per, e1 = min(xwords, e0 + per);
+    for (size_t i = e0 + threadIdx.x; i < e1; i += blockDim.x) nxt[i] = kXchEmpty;
+  }
   if (v0 >= Gh) return;
   const int rows = min(kSBand, Gh - v0);
-  const int row = threadIdx.x / kSLanes, lane = threadIdx.x % kSLanes;
+  const int row = threadIdx.x >> 6, lane = threadIdx.x & 63;   // one wavefront per band row
   const bool rowok = row < rows;
   const int gy = sy > 0 ? v0 + row : Gh - 1 - (v0 + row);
   const int py = gy * n;
   int32_t* const F = sgrid_flow(f, lev);
   int32_t* const C = sgrid_cost(f, lev, Gw * Gh);
-  uint64_t* const xch = reinterpret_cast<uint64_t*>(f.ws + f.o_xch);
+  uint64_t* const xch = xbase + (size_t)parity * xwords;
   const uint64_t* const xin = xch + (size_t)(band > 0 ? band - 1 : 0) * Gw;
   uint64_t* const xout = xch + (size_t)band * Gw;
   const bool publish = rowok && row == rows - 1 && v0 + rows < Gh;
   const int nsteps = Gw + rows - 1;
-  int32_t hF = kEmpty;   // this row's result of the previous step (its horizontal candidate)
+  // this row's result of the previous step: its horizontal candidate
+  int32_t hF = kEmpty, hC = kInf;
   bool abandoned = false;
+  // prefetched for the row's next column: its own flow and cost and, for row
+  // 0, the band above's word (each loaded one step ahead, before the barrier)
+  auto own_idx = [&](int uu) { return (size_t)gy * Gw + (sx > 0 ? uu : Gw - 1 - uu); };
+  int32_t nF = kEmpty, nC = kInf;
+  uint64_t nW = kXchEmpty;
+  if (row == 0) {
+    nF = F[own_idx(0)];
+    nC = C[own_idx(0)];
+    if (band > 0) nW = __hip_atomic_load(&xin[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   for (int t = 0; t < nsteps; ++t) {
     const int u = t - row;
     const bool active = rowok && u >= 0 && u < Gw;
-    int32_t vF = kEmpty;
+    if (rowok && u == 0 && row > 0) {
+      nF = F[own_idx(0)];
+      nC = C[own_idx(0)];
+    }
+    const int32_t curF0 = nF, curC0 = nC;
+    int32_t vF = kEmpty, vC = kInf;
     if (row == 0) {
       if (band > 0 && active) {
-        uint64_t w = __hip_atomic_load(&xin[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((uint32_t)(w >> 32) != tag && !abandoned) {
+        uint64_t w = nW;
+        if (w == kXchEmpty && !abandoned) {
           const uint64_t t0 = rt_now();
           do {
             __builtin_amdgcn_s_sleep(1);
@@ -369,49 +452,62 @@ __global__ __launch_bounds__(kSBand * kSLanes) void k_sift_prop(const SiftRec* _
               abandoned = true;
               break;
             }
-          } while ((uint32_t)(w >> 32) != tag);
+          } while (w == kXchEmpty);
         }
-        vF = (uint32_t)(w >> 32) == tag ? (int32_t)(uint32_t)w : kEmpty;
+        if (w != kXchEmpty) {
+          vF = (int32_t)(uint32_t)w;
+          vC = (int32_t)(uint32_t)(w >> 32);
+        }
       }
     } else {
-      vF = res[(t - 1) & 1][row - 1];
+      vF = resF[(t - 1) & 1][row - 1];
+      vC = resC[(t - 1) & 1][row - 1];
     }
-    int32_t out = kEmpty;
+    int32_t outF = kEmpty, outC = kInf;
     if (active) {
-      const int gx = sx > 0 ? u : Gw - 1 - u;
-      const size_t pi = (size_t)gy * Gw + gx;
-      const int px = gx * n;
-      const int32_t curF0 = F[pi], curC0 = C[pi];
+      const size_t pi = own_idx(u);
+      const int px = (sx > 0 ? u : Gw - 1 - u) * n;
       const bool useV = vF != curF0 && svalid(c, px, py, vF);
       const bool useH = u > 0 && hF != curF0 && svalid(c, px, py, hF);
-      int32_t eV = 0, eH = 0;
-      if (useV || useH) {
-        int32_t pV, pH;
-        sift_partial2(c, px, py, useV, vF, useH, hF, lane, kSLanes, pV, pH);
-        eV = lane_sum<kSLanes>(pV);
-        eH = lane_sum<kSLanes>(pH);
-      }
       int32_t curF = curF0, curC = curC0;
-      if (useV && eV < curC) {
-        curF = vF;
-        curC = eV;
-      }
-      if (useH && eH < curC) {
-        curF = hF;
-        curC = eH;
+      if (useV || useH) {
+        const Tgt tv = tgt_of(c, px, py, useV ? vF : 0), th = tgt_of(c, px, py, useH ? hF : 0);
+        int32_t dV, dH;
+        slide_terms<SG>(c, px, py, sx, sy, useV, tv, useH, th, lane, dV, dH);
+        const int32_t eV = vC + wave_sum(dV), eH = hC + wave_sum(dH);
+        if (useV && eV < curC) {
+          curF = vF;
+          curC = eV;
+        }
+        if (useH && eH < curC) {
+          curF = hF;
+          curC = eH;
+        }
       }
       if (lane == 0 && curF != curF0) {
         F[pi] = curF;
         C[pi] = curC;
       }
-      out = curF;
+      outF = curF;
+      outC = curC;
       if (publish && lane == 0)
-        __hip_atomic_store(&xout[u], ((uint64_t)tag << 32) | (uint32_t)out, __ATOMIC_RELAXED,
+        __hip_atomic_store(&xout[u], ((uint64_t)(uint32_t)outC << 32) | (uint32_t)outF, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-      hF = out;
+      hF = outF;
+      hC = outC;
+      if (u + 1 < Gw) {
+        nF = F[own_idx(u + 1)];
+        nC = C[own_idx(u + 1)];
+        if (row == 0 && band > 0) nW = __hip_atomic_load(&xin[u + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
-    if (lane == 0 && row < kSBand) res[t & 1][row] = out;
-    __syncthreads();
+    if (lane == 0) {
+      resF[t & 1][row] = outF;
+      resC[t & 1][row] = outC;
+    }
+    // only the LDS results cross rows; each row's global stores touch its
+    // own points and the next column's prefetches stay in flight
+    lds_barrier();
   }
 }
 
@@ -456,7 +552,7 @@ static SiftFieldPlan sift_field_plan(const ff_sift_job& j, const ff_match_params
   }
   off = align_up(off, 256);
   P.off_xch = off;
-  off += (size_t)((Hs + kSBand - 1) / kSBand) * Ws * 8;
+  off += 2 * (size_t)((Hs + kSBand - 1) / kSBand) * Ws * 8;
   P.bytes = align_up(off, 256);
   return P;
 }
@@ -565,6 +661,7 @@ static FieldRec make_tree_rec(const ff_sift_job& j, const SiftFieldPlan& P, char
   return r;
 }
 
+template <int SG>
 static ff_status run_sift_batch(const ff_sift_job* jobs, int n, const ff_match_params* p, char* ws,
                                 const SiftBatchLayout& B, hipStream_t stream) {
   int32_t* status = reinterpret_cast<int32_t*>(ws);
@@ -611,7 +708,7 @@ static ff_status run_sift_batch(const ff_sift_job* jobs, int n, const ff_match_p
     if (cur_lev > 0) k_sift_write_grid<<<dim3((maxW + 255) / 256, maxH, n), 256, 0, stream>>>(table, cur_lev);
     return launch_status();
   };
-  k_sift_seed<<<dim3((pts(k) + 3) / 4, n), 256, 0, stream>>>(table, k, qshift);
+  k_sift_seed<SG><<<dim3((pts(k) + 3) / 4, n), 256, 0, stream>>>(table, k, qshift);
   ++steps;
   if (stop()) return finish();
   const uint64_t timeout = p->watchdog_us > 0 ? (uint64_t)p->watchdog_us * 100u : 200000000ull;
@@ -621,7 +718,7 @@ static ff_status run_sift_batch(const ff_sift_job* jobs, int n, const ff_match_p
   for (int lev = k; lev >= 0; --lev) {
     cur_lev = lev;
     if (lev < k) {
-      k_sift_entry<<<dim3(groups(pts(lev + 1)), n), 256, 0, stream>>>(table, lev, qshift);
+      k_sift_entry<SG><<<dim3(groups(pts(lev + 1)), n), 256, 0, stream>>>(table, lev, qshift);
       ++steps;
       if (stop()) return finish();
     }
@@ -629,14 +726,14 @@ static ff_status run_sift_batch(const ff_sift_job* jobs, int n, const ff_match_p
       int bands = 0;
       for (int g = 0; g < n; ++g) bands += (((recs[g].Hs + (1 << lev) - 1) >> lev) + kSBand - 1) / kSBand;
       prof_mark(FF_PROF_SIFT_PROPAGATE, stream, true);
-      k_sift_prop<<<bands, kSBand * kSLanes, 0, stream>>>(table, n, lev, qshift, sx_of(i), sy_of(i),
-                                                          (uint32_t)(launch + 1), tickets + launch, status, timeout);
+      k_sift_prop<SG><<<bands, kSBand * 64, 0, stream>>>(table, n, lev, qshift, sx_of(i), sy_of(i), launch & 1,
+                                                         tickets + launch, status, timeout);
       prof_mark(FF_PROF_SIFT_PROPAGATE, stream, false);
       ++launch;
       ++steps;
       if (stop()) return finish();
       if (i < p->n_rs) {
-        k_sift_rs<<<dim3(groups(pts(lev)), n), 256, 0, stream>>>(table, lev, qshift, i, p->R);
+        k_sift_rs<SG><<<dim3(groups(pts(lev)), n), 256, 0, stream>>>(table, lev, qshift, i, p->R);
         ++steps;
         if (stop()) return finish();
       }
@@ -674,7 +771,19 @@ ff_status ff_match_sift(const ff_sift_job* jobs, int32_t n_jobs, const ff_match_
   st = ensure_init();
   if (st != FF_OK) return st;
   prof_mark(FF_PROF_SIFT_MATCH, stream, true);
-  st = run_sift_batch(jobs, n_jobs, p, static_cast<char*>(workspace), B, stream);
+  int sg = 1;
+  for (int i = 0; i < n_jobs; ++i) sg = std::max(sg, (jobs[i].channels + 3) / 4);
+  char* w = static_cast<char*>(workspace);
+  switch (sg) {
+    case 1: st = run_sift_batch<1>(jobs, n_jobs, p, w, B, stream); break;
+    case 2: st = run_sift_batch<2>(jobs, n_jobs, p, w, B, stream); break;
+    case 3: st = run_sift_batch<3>(jobs, n_jobs, p, w, B, stream); break;
+    case 4: st = run_sift_batch<4>(jobs, n_jobs, p, w, B, stream); break;
+    case 5: st = run_sift_batch<5>(jobs, n_jobs, p, w, B, stream); break;
+    case 6: st = run_sift_batch<6>(jobs, n_jobs, p, w, B, stream); break;
+    case 7: st = run_sift_batch<7>(jobs, n_jobs, p, w, B, stream); break;
+    default: st = run_sift_batch<8>(jobs, n_jobs, p, w, B, stream); break;
+  }
   prof_mark(FF_PROF_SIFT_MATCH, stream, false);
   return st;
 }
