@@ -21,7 +21,7 @@
 // neighbours at the subpixel phase: floor(sqrt(sum_s d_s^2 * 256 / Q^4)) in
 // 1/16 code units.  Seeds, level entries and random searches are per-point
 // kernels; a propagation sweep (Eq. 2) is an anti-diagonal wavefront over
-// bands of 16 grid rows, one workgroup per band, the band's top row taking
+// bands of 4 grid rows, one workgroup per band, the band's top row taking
 // its vertical candidates from the band above through tagged 64-bit words.
 #include <algorithm>
 #include <cmath>
@@ -269,14 +269,16 @@ __global__ void k_sift_gram_reduce(const double* __restrict__ part, int nparts, 
 // whole matrix stays in LDS.  A sweep is 127 rounds of the round-robin
 // tournament, 64 disjoint pairs per round, 16 lanes per pair (dot products
 // by DPP row sums, one barrier per round).  Pairs whose columns are already
-// orthogonal to 1e-13 of their norms are left alone; sweeps stop when none
-// is rotated (or after 30).  Eigenvalues are then ranked descending (ties by
+// orthogonal to 1e-13 of their norms, or whose rotation angle is below
+// 1e-15 (no change beyond rounding), are left alone; sweeps stop when none is
+// rotated (or after 30).  Eigenvalues are then ranked descending (ties by
 // index), each eigenvector's largest-magnitude component (the first on
 // ties) is made positive, and out receives mean (128), eigenvalues (128) and
 // the basis (128 x 128, element [k][s] = component k of eigenvector s).
 constexpr int kMP = kSiftDim + 2;   // LDS row pitch (doubles): the 4 pairs of a wavefront in different banks
 constexpr int kJacobiSweeps = 30;
 constexpr double kOrthTol = 1e-13;
+constexpr double kMinAngle = 1e-15;
 
 __device__ __forceinline__ void tourney(int round, int k, int& p, int& q) {
   // circle method: player 0 fixed, players 1..127 rotate
@@ -326,13 +328,17 @@ __global__ __launch_bounds__(1024) void k_sift_eig(const double* __restrict__ ra
       if (fabs(c) > kOrthTol * sqrt(a * b)) {   // the same in all 16 lanes of the pair
         const double zeta = (b - a) / (2.0 * c);
         const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = tt * cs;
+        // a rotation by less than the rounding of the columns changes
+        // nothing (pairs with a column at rounding level stay there)
+        if (fabs(tt) > kMinAngle) {
+          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = tt * cs;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          mp[l + 16 * i] = cs * x[i] - sn * y[i];
-          mq[l + 16 * i] = sn * x[i] + cs * y[i];
+          for (int i = 0; i < 8; ++i) {
+            mp[l + 16 * i] = cs * x[i] - sn * y[i];
+            mq[l + 16 * i] = sn * x[i] + cs * y[i];
+          }
+          rotated = 1;
         }
-        rotated = 1;
       }
       __syncthreads();
     }

@@ -15,7 +15,9 @@
 // (Eq. 4); per level the alternating propagation sweeps (Eq. 2) and random
 // searches (R_n = R n), coarse flows seeding the next level.
 //
-// Propagation: one workgroup per band of 16 grid rows, one wavefront per row.
+// Propagation: one workgroup per band of 4 grid rows, one wavefront per row
+// (small bands: more of the chip at work, and each step waits on the
+// slowest of fewer memory round trips).
 // At step t, row i of the band handles column u = t - i (sweep-transformed
 // coordinates): its vertical candidate is row i - 1's result of step t - 1
 // (LDS), its horizontal candidate its own result of step t - 1; row 0 takes
@@ -33,7 +35,7 @@
 
 namespace ff {
 
-constexpr int kSBand = 16;    // grid rows per propagation band
+constexpr int kSBand = 4;     // grid rows per propagation band (one wavefront each)
 constexpr int kSLanes = 16;   // lanes per point (entry, random search): one DPP row
 constexpr int kSiftRecsPerWrite = 16;
 constexpr int kSiftStatusBytes = 256;
@@ -89,12 +91,17 @@ __device__ __forceinline__ bool svalid(const SCtx& c, int px, int py, int32_t f)
 }
 
 // floor(sqrt(v)) for v < 2^46: a float estimate (from the two 32-bit
-// halves), corrected exactly
+// halves), corrected exactly; the root is below 2^23, so its squares are
+// full-rate 24-bit products
+__device__ __forceinline__ uint64_t sq24(uint32_t x) {
+  const uint32_t y = x & 0xFFFFFFu;   // no-op here: x < 2^24
+  return (uint64_t)y * y;
+}
 __device__ __forceinline__ uint32_t isqrt_u64(uint64_t v) {
   const float fv = fmaf((float)(uint32_t)(v >> 32), 4294967296.0f, (float)(uint32_t)v);
-  uint32_t k = (uint32_t)sqrtf(fv);
-  while ((uint64_t)k * k > v) --k;
-  while ((uint64_t)(k + 1) * (k + 1) <= v) ++k;
+  uint32_t k = min((uint32_t)sqrtf(fv), 0x7FFFFFu);
+  while (sq24(k) > v) --k;
+  while (sq24(k + 1) <= v) ++k;
   return k;
 }
 
@@ -111,10 +118,12 @@ __device__ __forceinline__ Tgt tgt_of(const SCtx& c, int px, int py, int32_t f) 
   t.Mx = mx >> c.qshift;
   t.My = my >> c.qshift;
   const int a = mx & (c.Q - 1), b = my & (c.Q - 1);
-  t.w00 = (c.Q - a) * (c.Q - b);
-  t.w10 = a * (c.Q - b);
-  t.w01 = (c.Q - a) * b;
-  t.w11 = a * b;
+  // weights <= Q^2 <= 64: the masks (no-ops) let the products with the
+  // colours compile to full-rate 24-bit multiplies
+  t.w00 = ((c.Q - a) * (c.Q - b)) & 0x7F;
+  t.w10 = (a * (c.Q - b)) & 0x7F;
+  t.w01 = ((c.Q - a) * b) & 0x7F;
+  t.w11 = (a * b) & 0x7F;
   return t;
 }
 
@@ -146,32 +155,41 @@ struct Quad {
   Px<SG> p00, p10, p01, p11;
 };
 
+// int16 offset of pixel (x, y) in a plane of width w and pitch P: below
+// 2^27 (pixels < 2^22, P <= 32), so 32-bit full-rate 24-bit products
+__device__ __forceinline__ uint32_t pix_off(int x, int y, int w, int P) {
+  return __umul24(__umul24((uint32_t)y, (uint32_t)w) + (uint32_t)x, (uint32_t)P);
+}
+
 template <int SG>
 __device__ __forceinline__ Quad<SG> load_quad(const SCtx& c, int X, int Y, int sgf) {
   const int X1 = min(X + 1, c.Wd - 1), Y1 = min(Y + 1, c.Hd - 1);
-  const int16_t* r0 = c.dst + (size_t)Y * c.Wd * c.P;
-  const int16_t* r1 = c.dst + (size_t)Y1 * c.Wd * c.P;
   Quad<SG> q;
-  q.p00 = load_px<SG>(r0 + (size_t)X * c.P, sgf);
-  q.p10 = load_px<SG>(r0 + (size_t)X1 * c.P, sgf);
-  q.p01 = load_px<SG>(r1 + (size_t)X * c.P, sgf);
-  q.p11 = load_px<SG>(r1 + (size_t)X1 * c.P, sgf);
+  q.p00 = load_px<SG>(c.dst + pix_off(X, Y, c.Wd, c.P), sgf);
+  q.p10 = load_px<SG>(c.dst + pix_off(X1, Y, c.Wd, c.P), sgf);
+  q.p01 = load_px<SG>(c.dst + pix_off(X, Y1, c.Wd, c.P), sgf);
+  q.p11 = load_px<SG>(c.dst + pix_off(X1, Y1, c.Wd, c.P), sgf);
   return q;
 }
 
-// floor(sqrt(sum_s d_s^2 * 256 / Q^4)) of one sample
+// floor(sqrt(sum_s d_s^2 * 256 / Q^4)) of one sample.  Every factor fits 24
+// signed bits (weights and Q^2 <= 64, colours int16, |d_s| < 2^22), so the
+// products are full-rate 24-bit multiplies (the 64-bit square from its low
+// and high halves).
 template <int SG>
 __device__ __forceinline__ int32_t dist_of(const SCtx& c, const Px<SG>& a, const Quad<SG>& q, const Tgt& t) {
-  const int QQ = c.Q * c.Q;
+  const int QQ = (c.Q * c.Q) & 0x7F;
   uint64_t ss = 0;
 #pragma unroll
   for (int g = 0; g < SG; ++g)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int e = QQ * (int)a.v[g][i] - (t.w00 * (int)q.p00.v[g][i] + t.w10 * (int)q.p10.v[g][i] +
-                                           t.w01 * (int)q.p01.v[g][i] + t.w11 * (int)q.p11.v[g][i]);
+      const int e = __mul24(QQ, (int)a.v[g][i]) -
+                    (__mul24(t.w00, (int)q.p00.v[g][i]) + __mul24(t.w10, (int)q.p10.v[g][i]) +
+                     __mul24(t.w01, (int)q.p01.v[g][i]) + __mul24(t.w11, (int)q.p11.v[g][i]));
       const int em = g * 4 + i < c.S ? e : 0;
-      ss += (uint64_t)((int64_t)em * em);
+      const int e24 = (int)((uint32_t)em << 8) >> 8;   // no-op: |em| < 2^23
+      ss += (uint64_t)((int64_t)e24 * e24);
     }
   const uint64_t v = c.qshift <= 2 ? ss << (8 - 4 * c.qshift) : ss >> 4;
   return (int32_t)isqrt_u64(v);
@@ -187,7 +205,7 @@ __device__ __forceinline__ int32_t sift_partial(const SCtx& c, int px, int py, i
     const int iy = k / Sd, ix = k - iy * Sd;
     const int dx = (ix - c.r) * c.n, dy = (iy - c.r) * c.n;
     const int sx = clampi(px + dx, 0, c.Ws - 1), sy = clampi(py + dy, 0, c.Hs - 1);
-    const Px<SG> a = load_px<SG>(c.src + ((size_t)sy * c.Ws + sx) * c.P, sgf);
+    const Px<SG> a = load_px<SG>(c.src + pix_off(sx, sy, c.Ws, c.P), sgf);
     const Quad<SG> q = load_quad<SG>(c, clampi(t.Mx + dx, 0, c.Wd - 1), clampi(t.My + dy, 0, c.Hd - 1), sgf);
     sum += dist_of<SG>(c, a, q, t);
   }
@@ -353,7 +371,7 @@ __device__ __forceinline__ void slide_terms(const SCtx& c, int px, int py, int s
     const int dx = (vert ? o : a) * c.n, dy = (vert ? a : o) * c.n;
     const Tgt& t = vert ? tv : th;
     const int sxp = clampi(px + dx, 0, c.Ws - 1), syp = clampi(py + dy, 0, c.Hs - 1);
-    const Px<SG> pa = load_px<SG>(c.src + ((size_t)syp * c.Ws + sxp) * c.P, sgf);
+    const Px<SG> pa = load_px<SG>(c.src + pix_off(sxp, syp, c.Ws, c.P), sgf);
     const Quad<SG> q = load_quad<SG>(c, clampi(t.Mx + dx, 0, c.Wd - 1), clampi(t.My + dy, 0, c.Hd - 1), sgf);
     const int32_t d = dist_of<SG>(c, pa, q, t);
     const int32_t sd = enter ? d : -d;
