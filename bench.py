@@ -13,8 +13,10 @@ class against its own bound (algorithmic bytes per launch over the measured
 launch time); the level-1 propagation sweep's time per wavefront step;
 secondary workloads (the paper's fast variant, the skewed-motion recipe, the
 path through the region filter and sparsification of sections 3.4-3.5, 64
-mixed-size pairs in one batched call, the learned proposal); and the CPU
-oracle on the same pair, split by stage.
+mixed-size pairs in one batched call, the learned proposal); the path with
+the SIFT-flow data term (section 3.3, the KITTI setting) on the KITTI-shaped
+pair and the benchmark pair; and the CPU oracle on the same pair, split by
+stage (and on a bounded sample of the SIFT-flow workload).
 """
 import argparse
 import json
@@ -45,6 +47,10 @@ HEADLINE_SEED = 1000
 LEARNED_SEED0 = 4000
 OUTLIER_SEED0 = 1000
 WEIGHTS = os.path.join(ROOT, "paper_1508_05151_amd", "weights", "proposal_1024x436.safetensors")
+# the SIFT-flow data term with the paper's KITTI setting (section 4.2)
+SIFT_R, SIFT_R2, SIFT_S, SIFT_S2, SIFT_EPS, SIFT_REGION_S, SIFT_E = 3, 2, 12, 18, 1, 150, 9
+SIFT_SEED = 2000
+SIFT_CPU_SAMPLE = (621, 188)          # the oracle's bounded sample: the same recipe at 1/4 of the pixels
 
 
 def grid_points(W, H, k):
@@ -184,6 +190,80 @@ def cpu_baseline(pair, reps=3):
                      "cores_available": len(cores)}}
 
 
+def sift_cpu_baseline():
+    """The oracle's SIFT-flow path (colours, three fields, check, region
+    filter, sparsification) on one core, on a bounded sample: the
+    KITTI-shaped driving recipe (seed 2000) at 621x188 (1/4 of the pixels of
+    the GPU workload, the same motions in pixels; the full pair takes the
+    oracle about 100 s)."""
+    from oracle import ffo
+    from synth import pairs
+    W, H = SIFT_CPU_SAMPLE
+    p = pairs.driving_pair(SIFT_SEED, W=W, H=H)
+    g1, g2 = p.img1.reshape(H, W), p.img2.reshape(H, W)
+    t0 = time.perf_counter()
+    ffo.match_pair_sift(g1, g2, r=SIFT_R, r2=SIFT_R2, S=SIFT_S, S2=SIFT_S2, eps=SIFT_EPS, seed=SIFT_SEED,
+                        region_s=SIFT_REGION_S, sparse_e=SIFT_E)
+    sec = time.perf_counter() - t0
+    return {"value": round(W * H / sec / 1e6, 5), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+            "sample": f"the KITTI-shaped gray driving recipe (seed {SIFT_SEED}) at {W}x{H} (1/4 of the GPU "
+                      f"workload's pixels, the same motions in pixels): colours, F, B1, B2, check, region "
+                      f"filter, sparsification; one single-threaded run", "seconds": round(sec, 3)}
+
+
+def bench_sift(ff, torch, dev, workloads, steps):
+    """The SIFT-flow path (section 3.3) with the paper's KITTI setting: Lab8
+    and WHT vectors of both images, the pair's colours (dense SIFT, PCA to 18,
+    codes) and their levels, F (r = 3, S = 12), B1 (r = 3, S = 12), B2 (r2 = 2,
+    S2 = 18) in one batched call, consistency check (epsilon = 1), region
+    filter (s = 150) and sparsification (e = 9)."""
+    from synth import pairs
+    res = {}
+    for name, p in workloads.items():
+        H, W = p.img1.shape[:2]
+        C = p.img1.shape[2] if p.img1.ndim == 3 else 1
+        a = torch.from_numpy(p.img1.reshape(H, W) if C == 1 else p.img1).to(dev)
+        b = torch.from_numpy(p.img2.reshape(H, W) if C == 1 else p.img2).to(dev)
+        m = ff.SiftPairMatcher(W, H, channels=C, r=SIFT_R, r2=SIFT_R2, S=SIFT_S, S2=SIFT_S2, k=K, subpel=Q,
+                               eps=SIFT_EPS, region_s=SIFT_REGION_S, sparse_e=SIFT_E)
+        run = lambda: m.run(a, b, seed=p.seed)
+        run()
+        torch.cuda.synchronize()
+        ms, per, out = time_steps(run, torch, steps)
+        assert m.status() == 0, m.status()
+        classes = ["sift_colors", "sift_pca", "sift_levels", "sift_match", "tree", "filter", "region", "sparsify"]
+        t = class_times(ff, run, torch, classes, reps=3)
+        ff.ff_profile_begin("sift_propagate", 64)
+        run()
+        torch.cuda.synchronize()
+        ptot, pn, each = ff.ff_profile_end(each=16)
+        # level 0's four sweeps are the last launches; a sweep runs about
+        # Gw + Gh wavefront steps (4-row bands, each one step behind per row)
+        lvl0 = statistics.median(each[-4:])
+        wsteps = W + H
+        # bytes the sweep's loads request per point: per candidate the two
+        # sliding rows or columns of 2r+1 samples, 5 pixels each (source and
+        # the bilinear target quad) of 2S bytes, for F, B1 and B2
+        req = sum(2 * 2 * (2 * r + 1) * 5 * 2 * S for r, S in ((SIFT_R, SIFT_S), (SIFT_R, SIFT_S), (SIFT_R2, SIFT_S2)))
+        res[name] = {
+            "Mpixel_per_s": round(W * H / ms / 1e3, 3), "ms_per_pair": round(ms, 4),
+            "median_ms_per_pair": round(statistics.median(per), 4),
+            "stages_ms_per_pair": {c: round(t[c][0] * t[c][1], 4) for c in classes},
+            "propagation": {"kernel": "k_sift_prop", "launches_per_pair": pn, "ms_per_pair": round(ptot, 4),
+                            "level0_sweep_ms": round(lvl0, 4), "wavefront_steps_level0": wsteps,
+                            "ns_per_wavefront_step": round(lvl0 * 1e6 / wsteps, 1),
+                            "requested_bytes_per_point_three_fields": req,
+                            "requested_GBps_level0": round(req * W * H / (lvl0 / 1000.0) / 1e9, 1),
+                            "bound": "the sweep's dependency chain: one memory round trip per wavefront step"},
+            "quality": {"F_inlier_rate_epe_lt_3px": round(pairs.inlier_rate(out["F"].cpu().numpy(), p, Q), 4),
+                        "kept_after_filters": round(out["keep_region"].float().mean().item(), 4),
+                        "filtered_inlier_rate_epe_lt_3px": round(
+                            pairs.inlier_rate(out["filtered_region"].cpu().numpy(), p, Q), 4),
+                        "sparse_samples": int((out["pick"] >= 0).sum().item())}}
+        del m
+    return res
+
+
 # ------------------------------------------------------------------ GPU timing helpers
 def time_steps(run, torch, steps):
     """Wall time per step of `run` (K steps between synchronisations) and
@@ -224,15 +304,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-reps", type=int, default=3, help="CPU baseline: oracle runs (side by side)")
-    ap.add_argument("--mode", default="pair", choices=("pair", "batch", "outliers", "ablation"),
+    ap.add_argument("--mode", default="pair", choices=("pair", "batch", "outliers", "ablation", "sift"),
                     help="pair: one 1024x436 pair (headline, with every secondary block); batch: 64 mixed-size "
                          "pairs in one batched call alone; outliers: removed outliers vs removed inliers of the "
                          "filters over epsilon; ablation: the measures of Table 1 over k, l, R and the fast "
-                         "variant")
+                         "variant; sift: the SIFT-flow data term path alone (KITTI setting)")
     ap.add_argument("--pairs", type=int, default=64, help="batch block: number of mixed-size pairs")
     ap.add_argument("--gen-workers", type=int, default=16,
                     help="processes drawing the synthetic pairs (0 = in-process; use 0 under a profiler)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
+    ap.add_argument("--no-sift", action="store_true", help="skip the SIFT-flow data term block")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-pair batch block")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the per-kernel table and the secondary workloads")
@@ -280,6 +361,12 @@ def main():
     cpu = None
     if args.mode == "pair" and not args.no_cpu:
         cpu = cpu_baseline(pair, args.cpu_reps)
+    sift_workloads = sift_cpu = None
+    if args.mode == "sift" or (args.mode == "pair" and not args.no_sift):
+        sift_workloads = {"driving_1242x375_gray": pairs.driving_pair(SIFT_SEED),
+                          "layered_1024x436_rgb": pair}
+        if not args.no_cpu:
+            sift_cpu = sift_cpu_baseline()
 
     import torch
     from paper_1508_05151_amd import ff
@@ -294,6 +381,22 @@ def main():
         return bench_outliers(args, ff, outlier_pairs, torch, dev)
     if args.mode == "ablation":
         return bench_ablation(args, ff, outlier_pairs, torch, dev)
+    if args.mode == "sift":
+        res = bench_sift(ff, torch, dev, sift_workloads, args.steps)
+        d = res["driving_1242x375_gray"]
+        line = {"metric": "SIFT-flow data term path, Mpixel/s (KITTI setting, section 4.2)",
+                "value": d["Mpixel_per_s"], "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
+                "warmup": args.warmup, "ms_per_step": d["ms_per_pair"], "higher_is_better": True,
+                "scaling": "weak", "vs_baseline": None, "dtype": "int16/int32 (colours fp32/fp64)",
+                "data": "synthetic", "config": {"workload": "KITTI-shaped 1242x375 gray driving pair (seed 2000)",
+                                                "r": SIFT_R, "r2": SIFT_R2, "S": SIFT_S, "S2": SIFT_S2,
+                                                "eps": SIFT_EPS, "s": SIFT_REGION_S, "e": SIFT_E, "k": K,
+                                                "subpel": Q},
+                "workloads": res}
+        if sift_cpu is not None:
+            line["cpu_baseline"] = sift_cpu
+        print(json.dumps(line), flush=True)
+        return
     if args.calib_copy_mib:
         src = torch.ones(args.calib_copy_mib << 18, dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)
@@ -367,6 +470,10 @@ def main():
         line["batch"] = bench_batch(args, ff, batch_pairs, torch, dev, steps=5)
     if eval_pairs is not None:
         line["learned_proposal"] = bench_learned(ff, pair, img1, img2, eval_pairs, torch, dev, value, rate)
+    if sift_workloads is not None:
+        line["sift_flow"] = bench_sift(ff, torch, dev, sift_workloads, steps=5)
+        if sift_cpu is not None:
+            line["sift_flow"]["cpu_baseline"] = sift_cpu
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)

@@ -260,3 +260,31 @@ def test_pair_path_own_colors(ff):
     assert agree >= 0.95
     ig, ir = pairs.inlier_rate(F, p, 4), pairs.inlier_rate(ref["F"], p, 4)
     assert abs(ig - ir) <= 0.02, (ig, ir)
+
+
+@pytest.mark.timeout(600)
+def test_fullsize_driving_pair(ff):
+    """The KITTI-shaped gray pair (1242x375, the setting the paper uses the
+    SIFT-flow term for: r = 3, r2 = 2, S = 12 / 18, epsilon = 1, s = 150,
+    e = 9) at full size: the GPU's colours within 1 code of the oracle's, and
+    the whole pair path of SiftPairMatcher bit-exact on the oracle's colours.
+    The oracle needs about two minutes for this pair."""
+    p = pairs.driving_pair(2000)
+    H, W = p.img1.shape[:2]
+    g1 = np.ascontiguousarray(p.img1.reshape(H, W))
+    g2 = np.ascontiguousarray(p.img2.reshape(H, W))
+    _say("full-size sift: colours")
+    L1, L2 = ffo.lab8(g1)[0], ffo.lab8(g2)[0]
+    rate = _check_colors(_colors_gpu(ff, L1, L2, 18), L1, L2, 18)
+    _say(f"full-size sift: codes exact {rate:.5f}; oracle pair path")
+    ref = ffo.match_pair_sift(g1, g2, seed=2000, pair_id=1)
+    _say("full-size sift: GPU pair path")
+    m = ff.SiftPairMatcher(W, H, channels=1)
+    codes = (torch.from_numpy(ref["codes1"]).cuda(), torch.from_numpy(ref["codes2"]).cuda())
+    out = m.run(torch.from_numpy(g1).cuda(), torch.from_numpy(g2).cuda(), seed=2000, pair_id=1, codes=codes)
+    torch.cuda.synchronize()
+    assert m.status() == 0
+    for key in ("F", "CF", "B1", "CB1", "B2", "CB2", "keep", "filtered", "region_label", "keep_region",
+                "filtered_region", "pick", "sparse"):
+        g = out[key].cpu().numpy()
+        assert np.array_equal(g, ref[key]), (key, int((g != ref[key]).sum()))
