@@ -261,6 +261,17 @@ def bench_sift(ff, torch, dev, workloads, steps):
                             pairs.inlier_rate(out["filtered_region"].cpu().numpy(), p, Q), 4),
                         "sparse_samples": int((out["pick"] >= 0).sum().item())}}
         del m
+        # the census data term on the same pair (r = 8, r2 = 6; epsilon 1 on
+        # gray, as the KITTI setting), for the accuracy comparison
+        cm = ff.PairMatcher(W, H, C, r=R, r2=R2, k=K, subpel=Q, eps=EPS if C == 3 else SIFT_EPS)
+        crun = lambda: cm.run(a, b, seed=p.seed)
+        crun()
+        cms, _, cout = time_steps(crun, torch, steps)
+        assert cm.status() == [0, 0, 0], cm.status()
+        res[name]["census_same_pair"] = {
+            "Mpixel_per_s": round(W * H / cms / 1e3, 3),
+            "F_inlier_rate_epe_lt_3px": round(pairs.inlier_rate(cout["F"].cpu().numpy(), p, Q), 4)}
+        del cm
     return res
 
 
