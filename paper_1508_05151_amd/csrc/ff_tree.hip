@@ -374,12 +374,16 @@ __device__ __forceinline__ uint64_t cas_keep(uint64_t mine, uint64_t other, int 
   return lower == up ? lo : hi;
 }
 
-__device__ void bitonic_sort(uint64_t* key, int P) {
+// Sorts every aligned block of B keys (B a power of two <= P) ascending: the
+// network of a full sort stopped at merges of size B, the last merge taken
+// ascending in every block.
+__device__ void bitonic_sort(uint64_t* key, int P, int B) {
   const int t = threadIdx.x;
   uint64_t v[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) v[r] = key[4 * t + r];
-  for (int k = 2; k <= P; k <<= 1) {
+  for (int k = 2; k <= B; k <<= 1) {
+    const int kd = k == B ? 2 * P : k;   // direction bit: none in the last merge
     for (int j = k >> 1; j > 0; j >>= 1) {
       if (j >= 256) {
         __syncthreads();
@@ -389,15 +393,15 @@ __device__ void bitonic_sort(uint64_t* key, int P) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = 4 * t + r;
-          v[r] = cas_keep(v[r], key[i ^ j], i, j, k);
+          v[r] = cas_keep(v[r], key[i ^ j], i, j, kd);
         }
       } else if (j >= 4) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = cas_keep(v[r], __shfl_xor(v[r], j >> 2), 4 * t + r, j, k);
+        for (int r = 0; r < 4; ++r) v[r] = cas_keep(v[r], __shfl_xor(v[r], j >> 2), 4 * t + r, j, kd);
       } else {
         uint64_t w[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) w[r] = cas_keep(v[r], v[r ^ j], 4 * t + r, j, k);
+        for (int r = 0; r < 4; ++r) w[r] = cas_keep(v[r], v[r ^ j], 4 * t + r, j, kd);
 #pragma unroll
         for (int r = 0; r < 4; ++r) v[r] = w[r];
       }
@@ -420,11 +424,16 @@ __global__ __launch_bounds__(kSubTpb) void k_tree_subtree(const FieldRec* __rest
   int32_t* perm_out = t.perm;
   const int32_t* V = t.V;
   const int stride = t.stride, D = t.D, N = t.N;
-  __shared__ uint64_t key[kTreeLds];
-  __shared__ int32_t enode[kTreeLds];       // heap node of the segment holding position e
-  __shared__ uint16_t eseg[kTreeLds];       // local start of that segment
+  // Padded layout: at relative depth lvl the subtree's 2^lvl segments sit in
+  // aligned blocks of B = P >> lvl positions (segment s in [s B, s B + cnt),
+  // the rest +inf), so each level sorts every block on its own and a split
+  // keeps the left half in place and moves the right half to the second
+  // half of the block.  A segment that stops splitting is a leaf: its block,
+  // sorted by pixel index at that level, is written out at once.
+  __shared__ uint64_t keys[2][kTreeLds];
   __shared__ int32_t s_start[kTreeLds / 2], s_cnt[kTreeLds / 2];
   __shared__ int32_t s_best[kTreeLds / 2], s_dim[kTreeLds / 2], s_bmin[kTreeLds / 2];
+  __shared__ uint8_t s_alive[kTreeLds / 2], s_alive2[kTreeLds / 2];
   __shared__ int32_t s_pmin[kSubTpb / 64][32], s_pmax[kSubTpb / 64][32];
   __shared__ int s_any;
   const int root = (1 << t.top) - 1 + blockIdx.x;
@@ -432,20 +441,17 @@ __global__ __launch_bounds__(kSubTpb) void k_tree_subtree(const FieldRec* __rest
   heap_range(root, N, rstart, rcnt);
   int P = 1;
   while (P < rcnt) P <<= 1;
-  for (int e = threadIdx.x; e < P; e += kSubTpb) {
-    if (e < rcnt) {
-      key[e] = (uint64_t)perm_in[rstart + e];
-      enode[e] = root;
-      eseg[e] = 0;
-    } else {
-      key[e] = ~0ull;
-    }
-  }
+  int cur = 0;
+  for (int e = threadIdx.x; e < P; e += kSubTpb) keys[0][e] = e < rcnt ? (uint64_t)perm_in[rstart + e] : ~0ull;
+  if (threadIdx.x == 0) s_alive[0] = 1;
   __syncthreads();
   const uint64_t idmask = (1ull << 22) - 1;
   for (int lvl = 0;; ++lvl) {
     const int nslots = 1 << lvl;
+    const int B = P >> lvl;
+    const int lgB = 31 - __clz(B);
     const int base = (root + 1) * nslots - 1;    // first heap index at this relative depth
+    uint64_t* key = keys[cur];
     if (threadIdx.x == 0) s_any = 0;
     __syncthreads();
     for (int s = threadIdx.x; s < nslots; s += kSubTpb) {
@@ -456,27 +462,27 @@ __global__ __launch_bounds__(kSubTpb) void k_tree_subtree(const FieldRec* __rest
       s_best[s] = -1;
       s_dim[s] = 0;
       s_bmin[s] = 0;
-      if (c > leaf) s_any = 1;
+      if (s_alive[s] && c > leaf) s_any = 1;
     }
     __syncthreads();
-    if (!s_any) break;
-    // Split dimension of every splitting segment in one pass over its rows:
-    // 64 groups of 8 lanes, a lane holding 4 dimensions of a row.  With
-    // fewer than 64 segments, gps groups share a segment (partials merged by
-    // shuffles inside a wavefront, then through LDS across wavefronts); with
-    // more, each group walks spg segments.
-    {
+    const bool last = !s_any;
+    if (!last) {
+      // Split dimension of every splitting segment in one pass over its rows:
+      // 64 groups of 8 lanes, a lane holding 4 dimensions of a row.  With
+      // fewer than 64 segments, gps groups share a segment (partials merged by
+      // shuffles inside a wavefront, then through LDS across wavefronts); with
+      // more, each group walks spg segments.
       const int g = threadIdx.x >> 3, q = threadIdx.x & 7, wv = threadIdx.x >> 6;
       const int gps = nslots >= 64 ? 1 : 64 / nslots;
       const int spg = nslots >= 64 ? nslots / 64 : 1;
       for (int si = 0; si < spg; ++si) {
         const int s = nslots >= 64 ? g * spg + si : g / gps;
         const int part = nslots >= 64 ? 0 : g % gps;
-        const bool act = s_cnt[s] > leaf;
+        const bool act = s_alive[s] && s_cnt[s] > leaf;
         int mn[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
         int mx[4] = {INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN};
         if (act && 4 * q < D) {
-          const int c = s_cnt[s], st = s_start[s];
+          const int c = s_cnt[s], st = s << lgB;
           const int a = st + c * part / gps, b = st + c * (part + 1) / gps;
 #pragma unroll 8
           for (int e = a; e < b; ++e) {
@@ -527,48 +533,62 @@ __global__ __launch_bounds__(kSubTpb) void k_tree_subtree(const FieldRec* __rest
         }
         const bool owner = gps > 8 ? (g < nslots) : (part == 0);
         const int so = gps > 8 ? g : s;
-        if (owner && q == 0 && s_cnt[so] > leaf) { s_best[so] = bs; s_dim[so] = bd; s_bmin[so] = bm; }
+        if (owner && q == 0 && s_alive[so] && s_cnt[so] > leaf) { s_best[so] = bs; s_dim[so] = bd; s_bmin[so] = bm; }
       }
       __syncthreads();
     }
-    for (int e = threadIdx.x; e < rcnt; e += kSubTpb) {
-      const uint64_t id = key[e] & idmask;
-      const int s = enode[e] - base;
-      uint64_t sub = 0;
-      if (s >= 0 && s < nslots && s_cnt[s] > leaf)
-        sub = (uint64_t)(uint32_t)(V[(size_t)id * stride + s_dim[s]] - s_bmin[s]) << 22;
-      key[e] = ((uint64_t)eseg[e] << 42) | sub | id;
+    // keys: (split value - minimum) << 22 | pixel for a splitting segment,
+    // the pixel alone for a leaf, +inf outside the live segments
+    for (int e = threadIdx.x; e < P; e += kSubTpb) {
+      const int s = e >> lgB, j = e & (B - 1);
+      uint64_t kv = ~0ull;
+      if (s_alive[s] && j < s_cnt[s]) {
+        const uint64_t id = key[e] & idmask;
+        uint64_t sub = 0;
+        if (s_cnt[s] > leaf) sub = (uint64_t)(uint32_t)(V[(size_t)id * stride + s_dim[s]] - s_bmin[s]) << 22;
+        kv = sub | id;
+      }
+      key[e] = kv;
     }
     __syncthreads();
-    bitonic_sort(key, P);
+    bitonic_sort(key, P, B);
+    // split nodes; leaves written out (their blocks are in pixel order)
     for (int s = threadIdx.x; s < nslots; s += kSubTpb) {
-      if (s_cnt[s] > leaf) {
+      if (s_alive[s] && s_cnt[s] > leaf) {
         const int h = s_cnt[s] >> 1;
-        const uint64_t pid = key[s_start[s] + h] & idmask;
+        const uint64_t pid = key[(s << lgB) + h] & idmask;
         t.dim[base + s] = s_dim[s];
         t.split[base + s] = V[(size_t)pid * stride + s_dim[s]];
       }
     }
-    for (int e = threadIdx.x; e < rcnt; e += kSubTpb) {
-      const int s = enode[e] - base;
-      if (s >= 0 && s < nslots && s_cnt[s] > leaf) {
+    for (int e = threadIdx.x; e < P; e += kSubTpb) {
+      const int s = e >> lgB, j = e & (B - 1);
+      if (s_alive[s] && s_cnt[s] <= leaf && j < s_cnt[s]) perm_out[rstart + s_start[s] + j] = (int32_t)(key[e] & idmask);
+    }
+    if (last) break;
+    // the next level's layout: block 2s takes the first h of segment s, block
+    // 2s + 1 the rest, both of size B / 2
+    uint64_t* nkey = keys[cur ^ 1];
+    const int hB = B >> 1;
+    for (int e = threadIdx.x; e < P; e += kSubTpb) {
+      const int s2 = e >> (lgB - 1), j = e & (hB - 1), s = s2 >> 1;
+      uint64_t kv = ~0ull;
+      if (s_alive[s] && s_cnt[s] > leaf) {
         const int h = s_cnt[s] >> 1;
-        const int node = base + s;
-        if (e < s_start[s] + h) {
-          enode[e] = 2 * node + 1;
+        if (!(s2 & 1)) {
+          if (j < h) kv = key[(s << lgB) + j];
         } else {
-          enode[e] = 2 * node + 2;
-          eseg[e] = (uint16_t)(s_start[s] + h);
+          if (j < s_cnt[s] - h) kv = key[(s << lgB) + h + j];
         }
       }
+      nkey[e] = kv;
     }
+    for (int s2 = threadIdx.x; s2 < 2 * nslots; s2 += kSubTpb) s_alive2[s2] = s_alive[s2 >> 1] && s_cnt[s2 >> 1] > leaf;
+    __syncthreads();
+    for (int s2 = threadIdx.x; s2 < 2 * nslots; s2 += kSubTpb) s_alive[s2] = s_alive2[s2];
+    cur ^= 1;
     __syncthreads();
   }
-  // leaves: ascending pixel index inside every segment
-  for (int e = threadIdx.x; e < rcnt; e += kSubTpb) key[e] = ((uint64_t)eseg[e] << 42) | (key[e] & idmask);
-  __syncthreads();
-  bitonic_sort(key, P);
-  for (int e = threadIdx.x; e < rcnt; e += kSubTpb) perm_out[rstart + e] = (int32_t)(key[e] & idmask);
 }
 
 ff_status enqueue_tree_build(const FieldRec* table, int nf, int maxN, int maxTop, int leaf, hipStream_t stream) {
