@@ -61,6 +61,20 @@ __device__ __forceinline__ int32_t wave_sum(int32_t v) {
 }
 
 
+// inclusive prefix sum over the 64 lanes of a wavefront: shifts by 1, 2, 4
+// and 8 lanes inside each 16-lane DPP row (lanes shifted in from outside the
+// row add 0), then each row adds the totals of the rows before it
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);   // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);   // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);   // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);   // row_shr:8
+  const int32_t t0 = __builtin_amdgcn_readlane(v, 15), t1 = __builtin_amdgcn_readlane(v, 31),
+                t2 = __builtin_amdgcn_readlane(v, 47);
+  const int row = (int)(threadIdx.x & 63) >> 4;
+  return v + (row > 0 ? t0 : 0) + (row > 1 ? t1 : 0) + (row > 2 ? t2 : 0);
+}
+
 // Workgroup barrier for LDS handoffs only: waits for this wavefront's LDS
 // operations, not for its outstanding global loads (the next step's target
 // words stay in flight across it); the workgroup runs on

@@ -16,6 +16,7 @@
 //  * Below: one workgroup per subtree of <= kTreeLds points finishes every
 //    remaining level in LDS with a bitonic sort of (segment, key, pixel).
 #include "ff_internal.h"
+#include "ff_device.h"
 
 namespace ff {
 
@@ -183,43 +184,57 @@ __device__ __forceinline__ void node_split_dim(const int32_t* mm, int node, int 
 }
 
 // Radix-select state after `passes` completed passes: the known high digits
-// of the pivot key and its rank among the keys sharing them.  Whole-block
-// cooperative scan of each pass's histogram.
+// of the pivot key and its rank among the keys sharing them.  Thread t holds
+// bins [8t, 8t + 8) of every finished pass (all loaded at once); a pass's
+// digit is found with a wavefront scan of the threads' partial sums and the
+// four wavefront totals exchanged through LDS: two barriers per pass.
 __device__ void select_state(const int32_t* __restrict__ hist, int node, int passes, int rank0, uint64_t& prefix,
                              int& rank) {
-  __shared__ int32_t part[kTpb];
-  __shared__ int32_t s_bin, s_before;
+  constexpr int per = kSelBins / kTpb;
+  static_assert(per == 8 && kTpb % 64 == 0, "8 bins per thread");
+  __shared__ int32_t s_wtot[2][kTpb / 64];
+  __shared__ int32_t s_bin[2], s_before[2];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  v4i_t loc[kSelPasses][2];
+#pragma unroll
+  for (int p = 0; p < kSelPasses; ++p)
+    if (p < passes) {
+      const v4i_t* h = reinterpret_cast<const v4i_t*>(hist + ((size_t)node * kSelPasses + p) * kSelBins) + 2 * threadIdx.x;
+      loc[p][0] = h[0];
+      loc[p][1] = h[1];
+    }
   prefix = 0;
   rank = rank0;
-  constexpr int per = kSelBins / kTpb;
-  for (int p = 0; p < passes; ++p) {
-    const int32_t* h = hist + ((size_t)node * kSelPasses + p) * kSelBins;
-    int32_t loc[per];
+#pragma unroll
+  for (int p = 0; p < kSelPasses; ++p) {
+    if (p >= passes) break;
+    const int32_t b[per] = {loc[p][0].x, loc[p][0].y, loc[p][0].z, loc[p][0].w,
+                            loc[p][1].x, loc[p][1].y, loc[p][1].z, loc[p][1].w};
     int32_t s = 0;
 #pragma unroll
-    for (int i = 0; i < per; ++i) { loc[i] = h[threadIdx.x * per + i]; s += loc[i]; }
-    part[threadIdx.x] = s;
+    for (int i = 0; i < per; ++i) s += b[i];
+    int32_t incl = wave_incl_scan(s);
+    if (lane == 63) s_wtot[p & 1][wv] = incl;
     __syncthreads();
-    // inclusive scan over the block (Hillis-Steele)
-    for (int o = 1; o < kTpb; o <<= 1) {
-      const int32_t v = (int)threadIdx.x >= o ? part[threadIdx.x - o] : 0;
-      __syncthreads();
-      part[threadIdx.x] += v;
-      __syncthreads();
-    }
-    const int32_t incl = part[threadIdx.x];
+#pragma unroll
+    for (int w = 0; w < kTpb / 64; ++w)
+      if (w < wv) incl += s_wtot[p & 1][w];
     const int32_t excl = incl - s;
     if (rank >= excl && rank < incl) {
+      // the one bin of this thread whose key range holds the rank
       int32_t c = excl;
+      int bin = 0, before = excl;
+#pragma unroll
       for (int i = 0; i < per; ++i) {
-        if (rank < c + loc[i]) { s_bin = threadIdx.x * per + i; s_before = c; break; }
-        c += loc[i];
+        if (rank >= c && rank < c + b[i]) { bin = i; before = c; }
+        c += b[i];
       }
+      s_bin[p & 1] = threadIdx.x * per + bin;
+      s_before[p & 1] = before;
     }
     __syncthreads();
-    prefix = (prefix << 11) | (uint64_t)s_bin;
-    rank -= s_before;
-    __syncthreads();
+    prefix = (prefix << 11) | (uint64_t)s_bin[p & 1];
+    rank -= s_before[p & 1];
   }
 }
 
@@ -238,15 +253,9 @@ __global__ __launch_bounds__(kTpb) void k_tree_hist(const FieldRec* __restrict__
   int32_t mn;
   node_split_dim(t.mm, node, t.D, dim, mn);
   if (pass == 0 && blockIdx.x == 0 && threadIdx.x == 0) t.dim[node] = dim;
-  uint64_t prefix;
-  int rank;
-  select_state(t.hist, node, pass, cnt >> 1, prefix, rank);
-  __shared__ int32_t lh[kSelBins];
-  for (int i = threadIdx.x; i < kSelBins; i += kTpb) lh[i] = 0;
-  __syncthreads();
-  const int shift = 33 - 11 * pass;
-  // all of a thread's loads first (the element loop is unrolled), then the
-  // binning: a pass is a few round trips, not one per element
+  // all of a thread's element loads first (the element loop is unrolled), in
+  // flight during the select-state scan, then the binning: a pass is a few
+  // round trips, not one per element
   constexpr int EPT = kChunk / kTpb;
   int ids[EPT];
   uint32_t kvs[EPT];
@@ -262,6 +271,15 @@ __global__ __launch_bounds__(kTpb) void k_tree_hist(const FieldRec* __restrict__
       const int e = lo + threadIdx.x + i * kTpb;
       if (e < hi) kvs[i] = (uint32_t)(t.V[(size_t)ids[i] * t.stride + dim] - mn);
     }
+  }
+  uint64_t prefix;
+  int rank;
+  select_state(t.hist, node, pass, cnt >> 1, prefix, rank);
+  __shared__ int32_t lh[kSelBins];
+  for (int i = threadIdx.x; i < kSelBins; i += kTpb) lh[i] = 0;
+  __syncthreads();
+  const int shift = 33 - 11 * pass;
+  if (pass == 0) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int e = lo + threadIdx.x + i * kTpb;
@@ -295,46 +313,52 @@ __global__ __launch_bounds__(kTpb) void k_tree_partition(const FieldRec* __restr
   int dim;
   int32_t mn;
   node_split_dim(t.mm, node, t.D, dim, mn);
+  constexpr int EPT = kChunk / kTpb;
+  const int e0 = lo + threadIdx.x * EPT;
+  int ids[EPT];
+  uint32_t kv[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = e0 + i;
+    ids[i] = e < hi ? perm[start + e] : 0;
+    kv[i] = e < hi ? t.key[start + e] : 0u;
+  }
   uint64_t pivot;
   int rank;
   select_state(t.hist, node, kSelPasses, cnt >> 1, pivot, rank);
   if (blockIdx.x == 0 && threadIdx.x == 0) t.split[node] = (int32_t)(pivot >> 22) + mn;
-  constexpr int EPT = kChunk / kTpb;
-  int ids[EPT];
   uint32_t leftmask = 0;
   int nl = 0, nv = 0;
-  const int e0 = lo + threadIdx.x * EPT;
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = e0 + i;
-    if (e < hi) {
-      const int id = perm[start + e];
-      ids[i] = id;
-      const uint64_t ck = ((uint64_t)t.key[start + e] << 22) | (uint64_t)id;
+    if (e0 + i < hi) {
+      const uint64_t ck = ((uint64_t)kv[i] << 22) | (uint64_t)ids[i];
       if (ck < pivot) { leftmask |= 1u << i; ++nl; }
       ++nv;
     }
   }
-  __shared__ int32_t sl[kTpb], sr[kTpb];
+  // exclusive offsets of this thread's left and right elements in the chunk:
+  // wavefront scans, the wavefront totals through LDS
+  __shared__ int32_t wl[kTpb / 64], wr[kTpb / 64];
   __shared__ int32_t baseL, baseR;
-  sl[threadIdx.x] = nl;
-  sr[threadIdx.x] = nv - nl;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int32_t il = wave_incl_scan(nl), ir = wave_incl_scan(nv - nl);
+  if (lane == 63) { wl[wv] = il; wr[wv] = ir; }
   __syncthreads();
-  for (int o = 1; o < kTpb; o <<= 1) {
-    const int32_t a = (int)threadIdx.x >= o ? sl[threadIdx.x - o] : 0;
-    const int32_t b = (int)threadIdx.x >= o ? sr[threadIdx.x - o] : 0;
-    __syncthreads();
-    sl[threadIdx.x] += a;
-    sr[threadIdx.x] += b;
-    __syncthreads();
+  int32_t totL = 0, totR = 0;
+#pragma unroll
+  for (int w = 0; w < kTpb / 64; ++w) {
+    if (w < wv) { il += wl[w]; ir += wr[w]; }
+    totL += wl[w];
+    totR += wr[w];
   }
-  if (threadIdx.x == kTpb - 1) {
-    baseL = atomicAdd(&t.cnt[node * 2], sl[kTpb - 1]);
-    baseR = atomicAdd(&t.cnt[node * 2 + 1], sr[kTpb - 1]);
+  if (threadIdx.x == 0) {
+    baseL = atomicAdd(&t.cnt[node * 2], totL);
+    baseR = atomicAdd(&t.cnt[node * 2 + 1], totR);
   }
   __syncthreads();
-  int pl = start + baseL + sl[threadIdx.x] - nl;
-  int pr = start + (cnt >> 1) + baseR + sr[threadIdx.x] - (nv - nl);
+  int pl = start + baseL + il - nl;
+  int pr = start + (cnt >> 1) + baseR + ir - (nv - nl);
   // every write stays inside this node's range even if the counts were off
   const int lend = start + (cnt >> 1), rend = start + cnt;
 #pragma unroll
