@@ -9,10 +9,13 @@
 // node is free.
 //  * Top levels (nodes larger than kTreeLds points): level-synchronous passes
 //    over all nodes of a level at once --
-//      minmax    per-node per-dimension min/max (order-free atomics),
+//      minmax    per-node per-dimension min/max (order-free atomics), a pass
+//                of its own for the root only,
 //      hist x4   MSD radix select of the rank floor(cnt/2) element of the
 //                44-bit key ((key - min) << 22 | pixel), 11 bits per pass,
-//      partition strict-less-than-pivot to the left, others right.
+//      partition strict-less-than-pivot to the left, others right; each
+//                workgroup then reduces the two children's min/max over its
+//                chunk for the next level.
 //  * Below: one workgroup per subtree of <= kTreeLds points finishes every
 //    remaining level in LDS with a bitonic sort of (segment, key, pixel).
 #include "ff_internal.h"
@@ -116,6 +119,8 @@ __global__ void k_tree_init(const FieldRec* __restrict__ table) {
 // Rows are read whole: 8 lanes per row, each lane 4 consecutive dimensions
 // (one 16-byte load), so a wavefront reads 8 full rows per instruction.
 constexpr int kLpr = 8;
+// rows in flight per lane group in the min/max loops
+#define kMinmaxUnroll 16
 
 typedef int32_t v4i_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ v4i_t row_quad(const int32_t* V, int stride, int id, int j) {
@@ -143,7 +148,7 @@ __global__ __launch_bounds__(kTpb) void k_tree_minmax(const FieldRec* __restrict
   int mn[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
   int mx[4] = {INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN};
   if (on) {
-#pragma unroll 8
+#pragma unroll kMinmaxUnroll
     for (int e = lo + g; e < hi; e += kTpb / kLpr) {
       const v4i_t v = row_quad(t.V, t.stride, perm[start + e], q);
       mn[0] = min(mn[0], v.x); mx[0] = max(mx[0], v.x);
@@ -372,6 +377,72 @@ __global__ __launch_bounds__(kTpb) void k_tree_partition(const FieldRec* __restr
         ++pr;
       }
     }
+  }
+  if (d + 1 >= t.top) return;
+  // The children's per-dimension minimum and maximum (their split dimensions
+  // at the next level) over this chunk's points: the chunk's left points,
+  // then its right points, listed in LDS; rows read whole by groups of 8
+  // lanes as in k_tree_minmax; order-free atomics into the children's slots.
+  __shared__ int32_t sids[kChunk];
+  __shared__ int32_t cmin[2][32], cmax[2][32];
+  {
+    int ql = il - nl, qr = totL + ir - (nv - nl);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i)
+      if (e0 + i < hi) {
+        if ((leftmask >> i) & 1) sids[ql++] = ids[i];
+        else sids[qr++] = ids[i];
+      }
+  }
+  if (threadIdx.x < 64) {
+    cmin[threadIdx.x >> 5][threadIdx.x & 31] = INT32_MAX;
+    cmax[threadIdx.x >> 5][threadIdx.x & 31] = INT32_MIN;
+  }
+  __syncthreads();
+  const int g = threadIdx.x / kLpr, q = threadIdx.x % kLpr;
+  const bool on = 4 * q < t.D;
+  const int nvt = totL + totR;
+  int mnL[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX}, mxL[4] = {INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN};
+  int mnR[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX}, mxR[4] = {INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN};
+  if (on) {
+#pragma unroll kMinmaxUnroll
+    for (int e = g; e < nvt; e += kTpb / kLpr) {
+      const v4i_t v = row_quad(t.V, t.stride, sids[e], q);
+      const int vv[4] = {v.x, v.y, v.z, v.w};
+      const bool left = e < totL;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        mnL[i] = left ? min(mnL[i], vv[i]) : mnL[i];
+        mxL[i] = left ? max(mxL[i], vv[i]) : mxL[i];
+        mnR[i] = left ? mnR[i] : min(mnR[i], vv[i]);
+        mxR[i] = left ? mxR[i] : max(mxR[i], vv[i]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    for (int o = kLpr; o < 64; o <<= 1) {
+      mnL[i] = min(mnL[i], __shfl_xor(mnL[i], o));
+      mxL[i] = max(mxL[i], __shfl_xor(mxL[i], o));
+      mnR[i] = min(mnR[i], __shfl_xor(mnR[i], o));
+      mxR[i] = max(mxR[i], __shfl_xor(mxR[i], o));
+    }
+  if ((threadIdx.x & 63) < kLpr && on) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (4 * q + i < t.D) {
+        atomicMin(&cmin[0][4 * q + i], mnL[i]);
+        atomicMax(&cmax[0][4 * q + i], mxL[i]);
+        atomicMin(&cmin[1][4 * q + i], mnR[i]);
+        atomicMax(&cmax[1][4 * q + i], mxR[i]);
+      }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < 2 * t.D) {
+    const int side = threadIdx.x >= t.D ? 1 : 0, k = threadIdx.x - side * t.D;
+    const size_t child = (size_t)2 * node + 1 + side;
+    atomicMin(&t.mm[(child * 32 + k) * 2], cmin[side][k]);
+    atomicMax(&t.mm[(child * 32 + k) * 2 + 1], cmax[side][k]);
   }
 }
 
@@ -621,7 +692,9 @@ ff_status enqueue_tree_build(const FieldRec* table, int nf, int maxN, int maxTop
   for (int d = 0; d < maxTop; ++d) {
     const int maxcnt = (int)(((int64_t)maxN + (1LL << d) - 1) >> d);
     const dim3 grid((maxcnt + kChunk - 1) / kChunk, 1 << d, nf);
-    k_tree_minmax<<<grid, kTpb, 0, stream>>>(table, d);
+    // below the root the previous level's partition has reduced each
+    // node's minimum and maximum
+    if (d == 0) k_tree_minmax<<<grid, kTpb, 0, stream>>>(table, d);
     for (int p = 0; p < kSelPasses; ++p) k_tree_hist<<<grid, kTpb, 0, stream>>>(table, d, p);
     k_tree_partition<<<grid, kTpb, 0, stream>>>(table, d);
   }
