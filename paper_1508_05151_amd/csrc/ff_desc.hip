@@ -196,105 +196,136 @@ __global__ void k_lanczos_v(const int32_t* __restrict__ T, int W, int H, int n, 
 }
 
 // ---------------------------------------------------------------- census
-// One thread per pixel computes all Q*Q subpixel phases of its census word:
-// the 2x2 neighbourhoods of the centre and of the 8 neighbours at stride n
-// are loaded once per channel; each phase mixes them with exact integer
-// bilinear weights.
-// One workgroup = a 64 x 4 tile of output pixels.  The smoothed input it
-// reads (the tile grown by n + 1, clamped to the image) is staged in LDS per
-// channel; the bilinear phase shift is done separably (horizontal phase a,
-// then vertical phase b), which gives the same integers as the 4-tap form.
-constexpr int kCensusTW = 64, kCensusTH = 4;
+// Every level in one launch (grid z = level).  A workgroup owns a 32 x 32
+// tile of output pixels, a thread four of them (one column, rows 8 apart).
+// The smoothed input of the tile grown by n + 1 (clamped to the image) is
+// staged in LDS for every channel.
+//
+// A census bit compares the bilinear phase-(a, b) interpolant at a
+// neighbour with the one at the centre; by linearity their difference is the
+// interpolant of the four corner differences D = s(neighbour) - s(centre),
+//   d(a, b) = (Q - b) ((Q - a) D00 + a D01) + b ((Q - a) D10 + a D11),
+// the same integers as interpolating each point first.  Along a it grows by
+// (Q - b)(D01 - D00) + b (D11 - D10), and that step and d(0, b) grow
+// linearly in b, so a neighbour's Q^2 differences cost one add each.  The
+// bit is the sign of d (|d| < 2^20): v_alignbit shifts it into the word, the
+// neighbours taken from the last bit to the first, so the word reads bit
+// 8c + i = neighbour i (raster order without the centre) of channel c.
+//
+// Each word is stored twice: row-major straight from the thread (a row of
+// 32 words is one 128-byte line), and transposed (plane[x][y]) through an
+// LDS buffer, so that a column of 32 words is one line as well.
+constexpr int kCensusTile = 32;
+constexpr int kCensusMaxN = 16;              // largest level stride (k <= 4)
+constexpr int kCensusPB = 16;                // phases held in registers at once
+constexpr int kCensusTP = 4;                 // phases per LDS transposition round
+constexpr int kCensusLW = kCensusTile + 2 * kCensusMaxN + 2;
 
 template <int Q>
-__global__ __launch_bounds__(256) void k_census(const int16_t* __restrict__ S, int W, int H, int C, int n,
-                                                uint32_t* __restrict__ out, size_t plane_words) {
-  constexpr int kMaxN = 16;   // largest level stride (k <= 4)
-  constexpr int LWmax = kCensusTW + 2 * kMaxN + 2, LHmax = kCensusTH + 2 * kMaxN + 2;
-  __shared__ int16_t tileS[LHmax * LWmax];
-  const int x0 = blockIdx.x * kCensusTW, y0 = blockIdx.y * kCensusTH;
-  const int tx = threadIdx.x % kCensusTW, ty = threadIdx.x / kCensusTW;
-  const int x = x0 + tx, y = y0 + ty;
-  // staged image window (already clamped coordinates)
-  const int sx0 = max(x0 - n, 0), sx1 = min(x0 + kCensusTW + n, W - 1);
-  const int sy0 = max(y0 - n, 0), sy1 = min(y0 + kCensusTH + n, H - 1);
-  const int LW = sx1 - sx0 + 1, LH = sy1 - sy0 + 1;
-  const int xc = min(x, W - 1), yc = min(y, H - 1);   // lanes past the edge compute a valid pixel, store nothing
-  uint32_t word[Q * Q];
-#pragma unroll
-  for (int i = 0; i < Q * Q; ++i) word[i] = 0;
+__global__ __launch_bounds__(256) void k_census(const int16_t* __restrict__ Sall, int W, int H, int C,
+                                                uint32_t* __restrict__ outRM, uint32_t* __restrict__ outT) {
+  constexpr int QQ = Q * Q, PB = QQ < kCensusPB ? QQ : kCensusPB, TP = PB < kCensusTP ? PB : kCensusTP;
+  static_assert(QQ % PB == 0 && PB % TP == 0 && PB % Q == 0, "phase blocks");
+  __shared__ int16_t tileS[3][kCensusLW * kCensusLW];
+  __shared__ uint32_t tbuf[TP][kCensusTile][kCensusTile + 1];
+  const int lev = blockIdx.z, n = 1 << lev;
   const size_t N = (size_t)W * H;
-  // LDS offsets of the 9 taps' top-left samples and their right/down steps
-  int o00[9], dxs[9], dys[9];
-#pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const int dx = t % 3 - 1, dy = t / 3 - 1;
-    const int X = clampi(xc + n * dx, 0, W - 1), Y = clampi(yc + n * dy, 0, H - 1);
-    o00[t] = (Y - sy0) * LW + (X - sx0);
-    dxs[t] = X + 1 <= W - 1 ? 1 : 0;
-    dys[t] = Y + 1 <= H - 1 ? LW : 0;
-  }
-  for (int c = 0; c < C; ++c) {
-    const int16_t* P = S + c * N;
-    __syncthreads();
-    for (int e = threadIdx.x; e < LW * LH; e += 256) {
-      const int yy = e / LW, xx = e - yy * LW;
-      tileS[e] = P[(size_t)(sy0 + yy) * W + sx0 + xx];
-    }
-    __syncthreads();
-    // horizontal phase first: h0[t][a] (row Y), h1[t][a] (row Y + 1)
-    int32_t h0[9][Q], h1[9][Q];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int32_t s00 = tileS[o00[t]], s01 = tileS[o00[t] + dxs[t]];
-      const int32_t s10 = tileS[o00[t] + dys[t]], s11 = tileS[o00[t] + dys[t] + dxs[t]];
-#pragma unroll
-      for (int a = 0; a < Q; ++a) {
-        h0[t][a] = (Q - a) * s00 + a * s01;
-        h1[t][a] = (Q - a) * s10 + a * s11;
-      }
-    }
-#pragma unroll
-    for (int b = 0; b < Q; ++b)
-#pragma unroll
-      for (int a = 0; a < Q; ++a) {
-        int32_t B[9];
-#pragma unroll
-        for (int t = 0; t < 9; ++t) B[t] = (Q - b) * h0[t][a] + b * h1[t][a];
-        // neighbours in raster order, skipping the centre (t = 4); bit i
-        // set when the neighbour is darker than the centre
-        uint32_t bits = 0;
-        int bit = 0;
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-          if (t == 4) continue;
-          bits |= (uint32_t)(B[t] < B[4]) << bit;
-          ++bit;
-        }
-        word[b * Q + a] |= bits << (8 * c);
-      }
-  }
-  if (x >= W || y >= H) return;
-  const size_t o = (size_t)y * W + x;
-#pragma unroll
-  for (int i = 0; i < Q * Q; ++i) out[i * plane_words + o] = word[i];
-}
-
-// 32x32 tiled transpose of every census plane (LDS tile, padded against
-// bank conflicts): out[p][x][y] = in[p][y][x]
-__global__ __launch_bounds__(256) void k_transpose(const uint32_t* __restrict__ in, int W, int H,
-                                                   uint32_t* __restrict__ out) {
-  __shared__ uint32_t tile[32][33];
-  const size_t plane = (size_t)blockIdx.z * W * H;
-  const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
-  for (int i = threadIdx.y; i < 32; i += 8) {
-    const int x = x0 + threadIdx.x, y = y0 + i;
-    if (x < W && y < H) tile[i][threadIdx.x] = in[plane + (size_t)y * W + x];
+  const int16_t* S = Sall + (size_t)lev * C * N;
+  uint32_t* rm = outRM + (size_t)lev * QQ * N;
+  uint32_t* tr = outT + (size_t)lev * QQ * N;
+  const int x0 = blockIdx.x * kCensusTile, y0 = blockIdx.y * kCensusTile;
+  const int sx0 = max(x0 - n, 0), sx1 = min(x0 + kCensusTile + n, W - 1);
+  const int sy0 = max(y0 - n, 0), sy1 = min(y0 + kCensusTile + n, H - 1);
+  const int LW = sx1 - sx0 + 1, LH = sy1 - sy0 + 1;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  // stage the window of every channel: rows over the 8 row groups, columns
+  // over the 32 lanes
+  for (int r = ty; r < C * LH; r += 8) {
+    const int c = r / LH, yy = r - c * LH;
+    const int16_t* src = S + (size_t)c * N + (size_t)(sy0 + yy) * W + sx0;
+    for (int xx = tx; xx < LW; xx += 32) tileS[c][yy * LW + xx] = src[xx];
   }
   __syncthreads();
-  for (int i = threadIdx.y; i < 32; i += 8) {
-    const int y = y0 + threadIdx.x, x = x0 + i;
-    if (x < W && y < H) out[plane + (size_t)x * H + y] = tile[threadIdx.x][i];
+  const int x = x0 + tx, xc = min(x, W - 1);
+  for (int pb = 0; pb < QQ; pb += PB) {
+    const int b0 = pb / Q;
+    uint32_t acc[4][PB];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int ph = 0; ph < PB; ++ph) acc[k][ph] = 0;
+    for (int c = C - 1; c >= 0; --c) {
+      const int16_t* T = tileS[c];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int yc = min(y0 + ty + 8 * k, H - 1);
+        // the four samples at tap (dx, dy) of this pixel, clamped as the
+        // images are: (X, Y), (X + 1, Y), (X, Y + 1), (X + 1, Y + 1)
+        auto corners = [&](int dx, int dy, int32_t& s00, int32_t& s01, int32_t& s10, int32_t& s11) {
+          const int X = clampi(xc + n * dx, 0, W - 1), Y = clampi(yc + n * dy, 0, H - 1);
+          const int o = (Y - sy0) * LW + (X - sx0);
+          const int ox = X + 1 <= W - 1 ? 1 : 0, oy = Y + 1 <= H - 1 ? LW : 0;
+          s00 = T[o];
+          s01 = T[o + ox];
+          s10 = T[o + oy];
+          s11 = T[o + oy + ox];
+        };
+        int32_t c00, c01, c10, c11;
+        corners(0, 0, c00, c01, c10, c11);
+#pragma unroll
+        for (int i = 7; i >= 0; --i) {
+          const int t = i < 4 ? i : i + 1;
+          int32_t s00, s01, s10, s11;
+          corners(t % 3 - 1, t / 3 - 1, s00, s01, s10, s11);
+          const int32_t D00 = s00 - c00, D01 = s01 - c01, D10 = s10 - c10, D11 = s11 - c11;
+          const int32_t E = (D11 - D10) - (D01 - D00);
+          // at b = b0: d(0, b) and the step along a
+          int32_t d0 = Q * ((Q - b0) * D00 + b0 * D10);
+          int32_t st = (Q - b0) * (D01 - D00) + b0 * (D11 - D10);
+#pragma unroll
+          for (int bb = 0; bb < PB / Q; ++bb) {
+            int32_t d = d0;
+#pragma unroll
+            for (int a = 0; a < Q; ++a) {
+              acc[k][bb * Q + a] = __builtin_amdgcn_alignbit(acc[k][bb * Q + a], (uint32_t)d, 31);
+              d += st;
+            }
+            d0 += Q * (D10 - D00);
+            st += E;
+          }
+        }
+      }
+    }
+    // row-major words
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int y = y0 + ty + 8 * k;
+      if (x < W && y < H) {
+#pragma unroll
+        for (int ph = 0; ph < PB; ++ph) rm[(size_t)(pb + ph) * N + (size_t)y * W + x] = acc[k][ph];
+      }
+    }
+    // transposed words: TP phases per round through LDS, read back with the
+    // lane on y
+#pragma unroll
+    for (int r = 0; r < PB / TP; ++r) {
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < TP; ++j)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) tbuf[j][tx][ty + 8 * k] = acc[k][r * TP + j];
+      __syncthreads();
+      const int yt = y0 + tx;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int xt = x0 + ty + 8 * k;
+        if (xt < W && yt < H) {
+#pragma unroll
+          for (int j = 0; j < TP; ++j)
+            tr[(size_t)(pb + r * TP + j) * N + (size_t)xt * H + yt] = tbuf[j][ty + 8 * k][tx];
+        }
+      }
+    }
   }
 }
 
@@ -548,23 +579,16 @@ ff_status ff_compute_descriptors(const ff_desc* d, const ff_image* img, const ui
   }
   prof_mark(FF_PROF_WHT, stream, false);
   prof_mark(FF_PROF_CENSUS, stream, true);
-  const size_t pw = N;
-  for (int lev = 0; lev <= d->k; ++lev) {
-    uint32_t* out = reinterpret_cast<uint32_t*>(base + d->off_census) + (size_t)lev * d->subpel * d->subpel * pw;
-    const int16_t* S = smooth + (size_t)lev * C * N;
-    const int n = 1 << lev;
-    const dim3 cg((W + kCensusTW - 1) / kCensusTW, (H + kCensusTH - 1) / kCensusTH);
-    switch (d->subpel) {
-      case 1: k_census<1><<<cg, tb, 0, stream>>>(S, W, H, C, n, out, pw); break;
-      case 2: k_census<2><<<cg, tb, 0, stream>>>(S, W, H, C, n, out, pw); break;
-      case 4: k_census<4><<<cg, tb, 0, stream>>>(S, W, H, C, n, out, pw); break;
-      default: k_census<8><<<cg, tb, 0, stream>>>(S, W, H, C, n, out, pw); break;
-    }
-  }
   {
-    const unsigned planes = (unsigned)((d->k + 1) * d->subpel * d->subpel);
-    k_transpose<<<dim3((W + 31) / 32, (H + 31) / 32, planes), dim3(32, 8), 0, stream>>>(
-        reinterpret_cast<const uint32_t*>(base + d->off_census), W, H, reinterpret_cast<uint32_t*>(base + d->off_census_t));
+    uint32_t* rm = reinterpret_cast<uint32_t*>(base + d->off_census);
+    uint32_t* tr = reinterpret_cast<uint32_t*>(base + d->off_census_t);
+    const dim3 cg((W + kCensusTile - 1) / kCensusTile, (H + kCensusTile - 1) / kCensusTile, d->k + 1);
+    switch (d->subpel) {
+      case 1: k_census<1><<<cg, tb, 0, stream>>>(smooth, W, H, C, rm, tr); break;
+      case 2: k_census<2><<<cg, tb, 0, stream>>>(smooth, W, H, C, rm, tr); break;
+      case 4: k_census<4><<<cg, tb, 0, stream>>>(smooth, W, H, C, rm, tr); break;
+      default: k_census<8><<<cg, tb, 0, stream>>>(smooth, W, H, C, rm, tr); break;
+    }
   }
   prof_mark(FF_PROF_CENSUS, stream, false);
   prof_mark(FF_PROF_DESCRIPTORS, stream, false);
