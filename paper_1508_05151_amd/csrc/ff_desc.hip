@@ -221,31 +221,75 @@ constexpr int kCensusPB = 16;                // phases held in registers at once
 constexpr int kCensusTP = 4;                 // phases per LDS transposition round
 constexpr int kCensusLW = kCensusTile + 2 * kCensusMaxN + 2;
 
-template <int Q>
-__global__ __launch_bounds__(256) void k_census(const int16_t* __restrict__ Sall, int W, int H, int C,
-                                                uint32_t* __restrict__ outRM, uint32_t* __restrict__ outT) {
-  constexpr int QQ = Q * Q, PB = QQ < kCensusPB ? QQ : kCensusPB, TP = PB < kCensusTP ? PB : kCensusTP;
-  static_assert(QQ % PB == 0 && PB % TP == 0 && PB % Q == 0, "phase blocks");
-  __shared__ int16_t tileS[3][kCensusLW * kCensusLW];
-  __shared__ uint32_t tbuf[TP][kCensusTile][kCensusTile + 1];
-  const int lev = blockIdx.z, n = 1 << lev;
-  const size_t N = (size_t)W * H;
-  const int16_t* S = Sall + (size_t)lev * C * N;
-  uint32_t* rm = outRM + (size_t)lev * QQ * N;
-  uint32_t* tr = outT + (size_t)lev * QQ * N;
-  const int x0 = blockIdx.x * kCensusTile, y0 = blockIdx.y * kCensusTile;
-  const int sx0 = max(x0 - n, 0), sx1 = min(x0 + kCensusTile + n, W - 1);
-  const int sy0 = max(y0 - n, 0), sy1 = min(y0 + kCensusTile + n, H - 1);
-  const int LW = sx1 - sx0 + 1, LH = sy1 - sy0 + 1;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  // stage the window of every channel: rows over the 8 row groups, columns
-  // over the 32 lanes
-  for (int r = ty; r < C * LH; r += 8) {
-    const int c = r / LH, yy = r - c * LH;
-    const int16_t* src = S + (size_t)c * N + (size_t)(sy0 + yy) * W + sx0;
-    for (int xx = tx; xx < LW; xx += 32) tileS[c][yy * LW + xx] = src[xx];
+// One channel's comparison bits for the thread's four pixels and the PB
+// phases from row b0 on.  INTERIOR: the tile grown by n + 1 lies inside the
+// image, so every tap is the centre plus n (dy LW + dx) and no sample is
+// clamped.
+template <int Q, int PB, bool INTERIOR>
+__device__ __forceinline__ void census_channel(const int16_t* __restrict__ T, int LW, int n, int W, int H, int sx0,
+                                               int sy0, int xc, int ybase, int b0, uint32_t (&acc)[4][PB]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int yc = INTERIOR ? ybase + 8 * k : min(ybase + 8 * k, H - 1);
+    // the four samples at tap (dx, dy): (X, Y), (X + 1, Y), (X, Y + 1),
+    // (X + 1, Y + 1), clamped to the image as the smoothed images are
+    auto corners = [&](int dx, int dy, int32_t& s00, int32_t& s01, int32_t& s10, int32_t& s11) {
+      int o, ox, oy;
+      if (INTERIOR) {
+        o = (yc - sy0) * LW + (xc - sx0) + n * (dy * LW + dx);
+        ox = 1;
+        oy = LW;
+      } else {
+        const int X = clampi(xc + n * dx, 0, W - 1), Y = clampi(yc + n * dy, 0, H - 1);
+        o = (Y - sy0) * LW + (X - sx0);
+        ox = X + 1 <= W - 1 ? 1 : 0;
+        oy = Y + 1 <= H - 1 ? LW : 0;
+      }
+      s00 = T[o];
+      s01 = T[o + ox];
+      s10 = T[o + oy];
+      s11 = T[o + oy + ox];
+    };
+    int32_t c00, c01, c10, c11;
+    corners(0, 0, c00, c01, c10, c11);
+    // neighbours from the last bit to the first (a rolled loop keeps the
+    // four pixels' corner reads from being hoisted into registers at once)
+#pragma unroll 1
+    for (int i = 7; i >= 0; --i) {
+      const int t = i < 4 ? i : i + 1;
+      int32_t s00, s01, s10, s11;
+      corners(t % 3 - 1, t / 3 - 1, s00, s01, s10, s11);
+      const int32_t D00 = s00 - c00, D01 = s01 - c01, D10 = s10 - c10, D11 = s11 - c11;
+      const int32_t E = (D11 - D10) - (D01 - D00);
+      // at b = b0: d(0, b) and the step along a
+      int32_t d0 = Q * ((Q - b0) * D00 + b0 * D10);
+      int32_t st = (Q - b0) * (D01 - D00) + b0 * (D11 - D10);
+#pragma unroll
+      for (int bb = 0; bb < PB / Q; ++bb) {
+        int32_t d = d0;
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+          acc[k][bb * Q + a] = __builtin_amdgcn_alignbit(acc[k][bb * Q + a], (uint32_t)d, 31);
+          d += st;
+        }
+        d0 += Q * (D10 - D00);
+        st += E;
+      }
+    }
   }
-  __syncthreads();
+}
+
+// The tile's words for every phase block: the bits of each channel, then
+// the row-major and the transposed stores.  One instance per kind of tile, so
+// that the two never share a register allocation.
+template <int Q, bool INTERIOR, int TP, int PB>
+__device__ __forceinline__ void census_tile_impl(int16_t (*tileS)[kCensusLW * kCensusLW],
+                                                 uint32_t (*tbuf)[kCensusTile][kCensusTile + 1], int W, int H, int C,
+                                                 int n, int x0, int y0, int sx0, int sy0, int LW, uint32_t* rm,
+                                                 uint32_t* tr) {
+  constexpr int QQ = Q * Q;
+  const size_t N = (size_t)W * H;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   const int x = x0 + tx, xc = min(x, W - 1);
   for (int pb = 0; pb < QQ; pb += PB) {
     const int b0 = pb / Q;
@@ -255,46 +299,7 @@ __global__ __launch_bounds__(256) void k_census(const int16_t* __restrict__ Sall
 #pragma unroll
       for (int ph = 0; ph < PB; ++ph) acc[k][ph] = 0;
     for (int c = C - 1; c >= 0; --c) {
-      const int16_t* T = tileS[c];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int yc = min(y0 + ty + 8 * k, H - 1);
-        // the four samples at tap (dx, dy) of this pixel, clamped as the
-        // images are: (X, Y), (X + 1, Y), (X, Y + 1), (X + 1, Y + 1)
-        auto corners = [&](int dx, int dy, int32_t& s00, int32_t& s01, int32_t& s10, int32_t& s11) {
-          const int X = clampi(xc + n * dx, 0, W - 1), Y = clampi(yc + n * dy, 0, H - 1);
-          const int o = (Y - sy0) * LW + (X - sx0);
-          const int ox = X + 1 <= W - 1 ? 1 : 0, oy = Y + 1 <= H - 1 ? LW : 0;
-          s00 = T[o];
-          s01 = T[o + ox];
-          s10 = T[o + oy];
-          s11 = T[o + oy + ox];
-        };
-        int32_t c00, c01, c10, c11;
-        corners(0, 0, c00, c01, c10, c11);
-#pragma unroll
-        for (int i = 7; i >= 0; --i) {
-          const int t = i < 4 ? i : i + 1;
-          int32_t s00, s01, s10, s11;
-          corners(t % 3 - 1, t / 3 - 1, s00, s01, s10, s11);
-          const int32_t D00 = s00 - c00, D01 = s01 - c01, D10 = s10 - c10, D11 = s11 - c11;
-          const int32_t E = (D11 - D10) - (D01 - D00);
-          // at b = b0: d(0, b) and the step along a
-          int32_t d0 = Q * ((Q - b0) * D00 + b0 * D10);
-          int32_t st = (Q - b0) * (D01 - D00) + b0 * (D11 - D10);
-#pragma unroll
-          for (int bb = 0; bb < PB / Q; ++bb) {
-            int32_t d = d0;
-#pragma unroll
-            for (int a = 0; a < Q; ++a) {
-              acc[k][bb * Q + a] = __builtin_amdgcn_alignbit(acc[k][bb * Q + a], (uint32_t)d, 31);
-              d += st;
-            }
-            d0 += Q * (D10 - D00);
-            st += E;
-          }
-        }
-      }
+      census_channel<Q, PB, INTERIOR>(tileS[c], LW, n, W, H, sx0, sy0, xc, y0 + ty, b0, acc);
     }
     // row-major words
 #pragma unroll
@@ -327,6 +332,45 @@ __global__ __launch_bounds__(256) void k_census(const int16_t* __restrict__ Sall
       }
     }
   }
+}
+
+template <int Q, bool INTERIOR>
+__device__ __forceinline__ void census_tile(int16_t (*tileS)[kCensusLW * kCensusLW],
+                                            uint32_t (*tbuf)[kCensusTile][kCensusTile + 1], int W, int H, int C,
+                                            int n, int x0, int y0, int sx0, int sy0, int LW, uint32_t* rm,
+                                            uint32_t* tr) {
+  constexpr int QQ = Q * Q, PB = QQ < kCensusPB ? QQ : kCensusPB, TP = PB < kCensusTP ? PB : kCensusTP;
+  census_tile_impl<Q, INTERIOR, TP, PB>(tileS, tbuf, W, H, C, n, x0, y0, sx0, sy0, LW, rm, tr);
+}
+
+template <int Q>
+__global__ __launch_bounds__(256) void k_census(const int16_t* __restrict__ Sall, int W, int H, int C,
+                                                uint32_t* __restrict__ outRM, uint32_t* __restrict__ outT) {
+  constexpr int QQ = Q * Q, PB = QQ < kCensusPB ? QQ : kCensusPB, TP = PB < kCensusTP ? PB : kCensusTP;
+  static_assert(QQ % PB == 0 && PB % TP == 0 && PB % Q == 0, "phase blocks");
+  __shared__ int16_t tileS[3][kCensusLW * kCensusLW];
+  __shared__ uint32_t tbuf[TP][kCensusTile][kCensusTile + 1];
+  const int lev = blockIdx.z, n = 1 << lev;
+  const size_t N = (size_t)W * H;
+  const int16_t* S = Sall + (size_t)lev * C * N;
+  uint32_t* rm = outRM + (size_t)lev * QQ * N;
+  uint32_t* tr = outT + (size_t)lev * QQ * N;
+  const int x0 = blockIdx.x * kCensusTile, y0 = blockIdx.y * kCensusTile;
+  const int sx0 = max(x0 - n, 0), sx1 = min(x0 + kCensusTile + n, W - 1);
+  const int sy0 = max(y0 - n, 0), sy1 = min(y0 + kCensusTile + n, H - 1);
+  const int LW = sx1 - sx0 + 1, LH = sy1 - sy0 + 1;
+  const bool interior = x0 >= n && x0 + kCensusTile + n <= W - 1 && y0 >= n && y0 + kCensusTile + n <= H - 1;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  // stage the window of every channel: rows over the 8 row groups, columns
+  // over the 32 lanes
+  for (int r = ty; r < C * LH; r += 8) {
+    const int c = r / LH, yy = r - c * LH;
+    const int16_t* src = S + (size_t)c * N + (size_t)(sy0 + yy) * W + sx0;
+    for (int xx = tx; xx < LW; xx += 32) tileS[c][yy * LW + xx] = src[xx];
+  }
+  __syncthreads();
+  if (interior) census_tile<Q, true>(tileS, tbuf, W, H, C, n, x0, y0, sx0, sy0, LW, rm, tr);
+  else census_tile<Q, false>(tileS, tbuf, W, H, C, n, x0, y0, sx0, sy0, LW, rm, tr);
 }
 
 // ---------------------------------------------------------------- WHT
