@@ -374,62 +374,129 @@ __global__ __launch_bounds__(256) void k_census(const int16_t* __restrict__ Sall
 }
 
 // ---------------------------------------------------------------- WHT
-// 1-D Walsh functions in sequency order on [-rho, rho]; odd extents split
-// rho | rho+1, the second split puts the smaller part first.
-__device__ __forceinline__ int walsh_sign(int s, int t, int rho) {
-  if (s == 0) return 1;
-  if (s == 1) return t < 0 ? 1 : -1;
-  if (t < 0) return (t + rho < rho / 2) ? 1 : -1;
-  return (t < (rho + 1) / 2) ? -1 : 1;
+// The three 1-D Walsh functions on [-rho, rho] in sequency order are
+// piecewise constant on four runs: A = [-rho, -rho + rho/2), B = [.., -1],
+// Cs = [0, (rho+1)/2), D = [(rho+1)/2, rho] (an odd extent splits rho |
+// rho + 1, the second split puts the smaller part first), so with the run
+// sums  w0 = A + B + Cs + D,  w1 = A + B - Cs - D,  w2 = A - B - Cs + D.
+// The 2-D basis (u on dy, v on dx) is taken in the order (0,0) (0,1) (1,0)
+// (1,1) (0,2) (2,0) (1,2) (2,1) (2,2), per channel; samples are clamped to
+// the image.
+//
+// One launch for every radius (grid z).  A workgroup owns a 64 x 16 tile:
+// its Lab8 window (grown by rho, clamped) goes to LDS, the three horizontal
+// run combinations of every window row and tile column to LDS as int16
+// (|w| <= (2 rho + 1) 255), and each thread combines vertical runs of those
+// into the 9 C values of its pixels, written as one 128-byte row per pixel.
+constexpr int kWhtTW = 64, kWhtTH = 16;
+
+struct WhtRadii {
+  int32_t rho[FF_MAX_RADII];
+};
+
+__device__ __forceinline__ void walsh_runs(int rho, int& a1, int& m, int& c1) {
+  a1 = rho / 2;          // run A: [0, a1)
+  m = rho;               // runs A + B: [0, rho); Cs starts at rho
+  c1 = (rho + 1) / 2;    // run Cs: [rho, rho + c1); D: [rho + c1, 2 rho]
 }
 
-// horizontal 1-D transforms, three per channel
-__global__ void k_wht_h(const uint8_t* __restrict__ J, int W, int H, int rho, int32_t* __restrict__ h) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y;
-  const int c = blockIdx.z;
-  if (x >= W) return;
+size_t wht_lds_bytes(int C, int rho) {
+  const int R = kWhtTH + 2 * rho, CW = kWhtTW + 2 * rho;
+  return align_up((size_t)C * R * CW, 16) + (size_t)C * 3 * R * kWhtTW * 2;
+}
+
+__global__ __launch_bounds__(256) void k_wht(const uint8_t* __restrict__ J, int W, int H, int C, WhtRadii rr,
+                                             int stride, int32_t* __restrict__ Vbase) {
+  extern __shared__ __align__(16) unsigned char wht_lds[];
+  const int ri = blockIdx.z, rho = rr.rho[ri];
   const size_t N = (size_t)W * H;
-  const uint8_t* row = J + c * N + (size_t)y * W;
-  int32_t s0 = 0, s1 = 0, s2 = 0;
-  for (int t = -rho; t <= rho; ++t) {
-    const int v = row[clampi(x + t, 0, W - 1)];
-    s0 += v;
-    s1 += walsh_sign(1, t, rho) * v;
-    s2 += walsh_sign(2, t, rho) * v;
+  int32_t* V = Vbase + (size_t)ri * N * stride;
+  const int x0 = blockIdx.x * kWhtTW, y0 = blockIdx.y * kWhtTH;
+  const int R = kWhtTH + 2 * rho, CW = kWhtTW + 2 * rho;
+  uint8_t* jt = wht_lds;                                                       // [C][R][CW]
+  int16_t* hb = reinterpret_cast<int16_t*>(wht_lds + (((size_t)C * R * CW + 15) & ~(size_t)15));   // [C][3][R][64]
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  for (int r = grp; r < C * R; r += 4) {
+    const int c = r / R, yy = r - c * R;
+    const uint8_t* src = J + (size_t)c * N + (size_t)clampi(y0 - rho + yy, 0, H - 1) * W;
+    for (int xx = lane; xx < CW; xx += 64) jt[r * CW + xx] = src[clampi(x0 - rho + xx, 0, W - 1)];
   }
-  const size_t o = (size_t)y * W + x;
-  h[(c * 3 + 0) * N + o] = s0;
-  h[(c * 3 + 1) * N + o] = s1;
-  h[(c * 3 + 2) * N + o] = s2;
-}
-
-// vertical combination into the 9 bases (u on dy, v on dx) in the order
-// (0,0) (0,1) (1,0) (1,1) (0,2) (2,0) (1,2) (2,1) (2,2)
-__global__ void k_wht_v(const int32_t* __restrict__ h, int W, int H, int C, int rho, int stride,
-                        int32_t* __restrict__ V) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y;
-  if (x >= W) return;
-  const size_t N = (size_t)W * H;
-  const int bu[9] = {0, 0, 1, 1, 0, 2, 1, 2, 2};
-  const int bv[9] = {0, 1, 0, 1, 2, 0, 2, 1, 2};
-  int32_t* out = V + ((size_t)y * W + x) * stride;
-  for (int c = 0; c < C; ++c) {
-    int32_t acc[9];
+  __syncthreads();
+  int a1, m, c1;
+  walsh_runs(rho, a1, m, c1);
+  // horizontal runs of every window row at tile column `lane`
+  for (int r = grp; r < C * R; r += 4) {
+    const uint8_t* row = jt + r * CW + lane;
+    int32_t A = 0, B = 0, Cs = 0, D = 0;
+    int k = 0;
+    for (; k < a1; ++k) A += row[k];
+    for (; k < m; ++k) B += row[k];
+    for (; k < m + c1; ++k) Cs += row[k];
+    for (; k <= 2 * rho; ++k) D += row[k];
+    const int c = r / R, yy = r - c * R;
+    int16_t* h = hb + ((size_t)c * 3 * R + yy) * kWhtTW + lane;
+    h[0] = (int16_t)(A + B + Cs + D);
+    h[R * kWhtTW] = (int16_t)(A + B - Cs - D);
+    h[2 * R * kWhtTW] = (int16_t)(A - B - Cs + D);
+  }
+  __syncthreads();
+  // vertical runs: thread (lane, grp) owns column lane, rows 4 grp .. 4 grp + 3
+  const int x = x0 + lane;
+  for (int i = 0; i < 4; ++i) {
+    const int py = 4 * grp + i, y = y0 + py;
+    int32_t out[32];
 #pragma unroll
-    for (int j = 0; j < 9; ++j) acc[j] = 0;
-    for (int t = -rho; t <= rho; ++t) {
-      const size_t o = (size_t)clampi(y + t, 0, H - 1) * W + x;
-      const int32_t hv[3] = {h[(c * 3 + 0) * N + o], h[(c * 3 + 1) * N + o], h[(c * 3 + 2) * N + o]};
-      const int su[3] = {1, walsh_sign(1, t, rho), walsh_sign(2, t, rho)};
+    for (int j = 0; j < 32; ++j) out[j] = 0;
 #pragma unroll
-      for (int j = 0; j < 9; ++j) acc[j] += su[bu[j]] * hv[bv[j]];
+    for (int c = 0; c < 3; ++c) {
+      if (c < C) {
+        int32_t w[3][3];   // w[u][v]: vertical function u over horizontal plane v
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          const int16_t* col = hb + ((size_t)(c * 3 + v) * R + py) * kWhtTW + lane;
+          int32_t A = 0, B = 0, Cs = 0, D = 0;
+          int k = 0;
+          for (; k < a1; ++k) A += col[k * kWhtTW];
+          for (; k < m; ++k) B += col[k * kWhtTW];
+          for (; k < m + c1; ++k) Cs += col[k * kWhtTW];
+          for (; k <= 2 * rho; ++k) D += col[k * kWhtTW];
+          w[0][v] = A + B + Cs + D;
+          w[1][v] = A + B - Cs - D;
+          w[2][v] = A - B - Cs + D;
+        }
+        out[9 * c + 0] = w[0][0];
+        out[9 * c + 1] = w[0][1];
+        out[9 * c + 2] = w[1][0];
+        out[9 * c + 3] = w[1][1];
+        out[9 * c + 4] = w[0][2];
+        out[9 * c + 5] = w[2][0];
+        out[9 * c + 6] = w[1][2];
+        out[9 * c + 7] = w[2][1];
+        out[9 * c + 8] = w[2][2];
+      }
     }
+    if (x < W && y < H) {
+      typedef int32_t v4_t __attribute__((ext_vector_type(4)));
+      v4_t* dst = reinterpret_cast<v4_t*>(V + ((size_t)y * W + x) * stride);
 #pragma unroll
-    for (int j = 0; j < 9; ++j) out[c * 9 + j] = acc[j];
+      for (int q = 0; q < 8; ++q)
+        if (4 * q < stride) dst[q] = v4_t{out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]};
+    }
   }
-  for (int j = 9 * C; j < stride; ++j) out[j] = 0;
+}
+
+static void enqueue_wht(const ff_desc* d, const uint8_t* lab, char* base, hipStream_t stream) {
+  if (d->n_radii <= 0) return;
+  WhtRadii rr{};
+  int rmax = 0;
+  for (int i = 0; i < d->n_radii; ++i) {
+    rr.rho[i] = d->radii[i];
+    rmax = max(rmax, d->radii[i]);
+  }
+  const size_t lds = wht_lds_bytes(d->channels, rmax);
+  const dim3 grid((d->width + kWhtTW - 1) / kWhtTW, (d->height + kWhtTH - 1) / kWhtTH, d->n_radii);
+  k_wht<<<grid, 256, lds, stream>>>(lab, d->width, d->height, d->channels, rr, d->wht_stride,
+                                    reinterpret_cast<int32_t*>(base + d->off_wht));
 }
 
 // ---------------------------------------------------------------- SIFT colour levels
@@ -616,11 +683,7 @@ ff_status ff_compute_descriptors(const ff_desc* d, const ff_image* img, const ui
   }
   prof_mark(FF_PROF_SMOOTH, stream, false);
   prof_mark(FF_PROF_WHT, stream, true);
-  for (int i = 0; i < d->n_radii; ++i) {
-    int32_t* V = reinterpret_cast<int32_t*>(base + d->off_wht + (size_t)i * N * d->wht_stride * 4);
-    k_wht_h<<<dim3(gx, H, C), tb, 0, stream>>>(lab, W, H, d->radii[i], scratch);
-    k_wht_v<<<dim3(gx, H), tb, 0, stream>>>(scratch, W, H, C, d->radii[i], d->wht_stride, V);
-  }
+  enqueue_wht(d, lab, base, stream);
   prof_mark(FF_PROF_WHT, stream, false);
   prof_mark(FF_PROF_CENSUS, stream, true);
   {
@@ -650,21 +713,14 @@ ff_status ff_compute_lab_wht(const ff_desc* d, const ff_image* img, const uint8_
   ff_status st = ensure_init();
   if (st != FF_OK) return st;
   const int W = d->width, H = d->height, C = d->channels;
-  const size_t N = (size_t)W * H;
   char* base = static_cast<char*>(blob);
   uint8_t* lab = reinterpret_cast<uint8_t*>(base + d->off_lab);
-  int32_t* scratch = reinterpret_cast<int32_t*>(base + d->off_census);
-  const dim3 tb(256);
   const unsigned gx = (unsigned)((W + 255) / 256);
   prof_mark(FF_PROF_LAB, stream, true);
-  k_lab8<<<dim3(gx, H), tb, 0, stream>>>(pixels, W, H, C, img->row_stride, lab);
+  k_lab8<<<dim3(gx, H), dim3(256), 0, stream>>>(pixels, W, H, C, img->row_stride, lab);
   prof_mark(FF_PROF_LAB, stream, false);
   prof_mark(FF_PROF_WHT, stream, true);
-  for (int i = 0; i < d->n_radii; ++i) {
-    int32_t* V = reinterpret_cast<int32_t*>(base + d->off_wht + (size_t)i * N * d->wht_stride * 4);
-    k_wht_h<<<dim3(gx, H, C), tb, 0, stream>>>(lab, W, H, d->radii[i], scratch);
-    k_wht_v<<<dim3(gx, H), tb, 0, stream>>>(scratch, W, H, C, d->radii[i], d->wht_stride, V);
-  }
+  enqueue_wht(d, lab, base, stream);
   prof_mark(FF_PROF_WHT, stream, false);
   return launch_status();
 }

@@ -62,7 +62,10 @@ CASES = [("square", lambda: pairs.square_pair(0), 3, (8, 6)),
          ("1x1", lambda: _ragged_pair(9, 1, 1), 3, (8, 6)),
          ("1x7", lambda: _ragged_pair(10, 1, 7), 2, (8, 6)),
          ("9x1", lambda: _ragged_pair(11, 9, 1), 2, (8, 6)),
-         ("2x2", lambda: _ragged_pair(12, 2, 2), 3, (3,))]
+         ("2x2", lambda: _ragged_pair(12, 2, 2), 3, (3,)),
+         # the largest and the smallest WHT radius, odd radii, four radii
+         ("radii15_1", lambda: _ragged_pair(13, 70, 40), 2, (15, 1)),
+         ("gray_four_radii", lambda: _ragged_pair(14, 83, 37, C=1), 1, (2, 9, 12, 5))]
 
 
 @pytest.mark.parametrize("name,make,k,radii", CASES, ids=[c[0] for c in CASES])
