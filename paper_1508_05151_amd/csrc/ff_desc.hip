@@ -390,60 +390,104 @@ __global__ __launch_bounds__(256) void k_census(const int16_t* __restrict__ Sall
 // into the 9 C values of its pixels, written as one 128-byte row per pixel.
 constexpr int kWhtTW = 64, kWhtTH = 16;
 
-struct WhtRadii {
-  int32_t rho[FF_MAX_RADII];
-};
-
-__device__ __forceinline__ void walsh_runs(int rho, int& a1, int& m, int& c1) {
-  a1 = rho / 2;          // run A: [0, a1)
-  m = rho;               // runs A + B: [0, rho); Cs starts at rho
-  c1 = (rho + 1) / 2;    // run Cs: [rho, rho + c1); D: [rho + c1, 2 rho]
-}
+__host__ __device__ constexpr int wht_rows(int rho) { return kWhtTH + 2 * rho; }
+__host__ __device__ constexpr int wht_cols(int rho) { return kWhtTW + 2 * rho; }
 
 size_t wht_lds_bytes(int C, int rho) {
-  const int R = kWhtTH + 2 * rho, CW = kWhtTW + 2 * rho;
-  return align_up((size_t)C * R * CW, 16) + (size_t)C * 3 * R * kWhtTW * 2;
+  return align_up((size_t)C * wht_rows(rho) * wht_cols(rho), 16) + (size_t)C * 3 * wht_rows(rho) * kWhtTW * 2;
 }
 
-__global__ __launch_bounds__(256) void k_wht(const uint8_t* __restrict__ J, int W, int H, int C, WhtRadii rr,
-                                             int stride, int32_t* __restrict__ Vbase) {
+// the run sums of 2 RHO + 1 samples p[0], p[st], ..., combined into w0..w2
+template <int RHO, typename T>
+__device__ __forceinline__ void walsh_three(const T* p, int st, int32_t& w0, int32_t& w1, int32_t& w2) {
+  constexpr int a1 = RHO / 2, m = RHO, c1 = (RHO + 1) / 2;
+  int32_t A = 0, B = 0, Cs = 0, D = 0;
+#pragma unroll
+  for (int k = 0; k <= 2 * RHO; ++k) {
+    const int32_t v = p[k * st];
+    if (k < a1) A += v;
+    else if (k < m) B += v;
+    else if (k < m + c1) Cs += v;
+    else D += v;
+  }
+  w0 = A + B + Cs + D;
+  w1 = A + B - Cs - D;
+  w2 = A - B - Cs + D;
+}
+
+template <int RHO>
+__global__ __launch_bounds__(256) void k_wht(const uint8_t* __restrict__ J, int W, int H, int C, int stride,
+                                             int32_t* __restrict__ V) {
+  constexpr int R = wht_rows(RHO), CW = wht_cols(RHO);
+  constexpr int a1 = RHO / 2, m = RHO, c1 = (RHO + 1) / 2;
   extern __shared__ __align__(16) unsigned char wht_lds[];
-  const int ri = blockIdx.z, rho = rr.rho[ri];
   const size_t N = (size_t)W * H;
-  int32_t* V = Vbase + (size_t)ri * N * stride;
   const int x0 = blockIdx.x * kWhtTW, y0 = blockIdx.y * kWhtTH;
-  const int R = kWhtTH + 2 * rho, CW = kWhtTW + 2 * rho;
-  uint8_t* jt = wht_lds;                                                       // [C][R][CW]
+  uint8_t* jt = wht_lds;                                                                  // [C][R][CW]
   int16_t* hb = reinterpret_cast<int16_t*>(wht_lds + (((size_t)C * R * CW + 15) & ~(size_t)15));   // [C][3][R][64]
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
   for (int r = grp; r < C * R; r += 4) {
     const int c = r / R, yy = r - c * R;
-    const uint8_t* src = J + (size_t)c * N + (size_t)clampi(y0 - rho + yy, 0, H - 1) * W;
-    for (int xx = lane; xx < CW; xx += 64) jt[r * CW + xx] = src[clampi(x0 - rho + xx, 0, W - 1)];
+    const uint8_t* src = J + (size_t)c * N + (size_t)clampi(y0 - RHO + yy, 0, H - 1) * W;
+    for (int xx = lane; xx < CW; xx += 64) jt[r * CW + xx] = src[clampi(x0 - RHO + xx, 0, W - 1)];
   }
   __syncthreads();
-  int a1, m, c1;
-  walsh_runs(rho, a1, m, c1);
   // horizontal runs of every window row at tile column `lane`
   for (int r = grp; r < C * R; r += 4) {
-    const uint8_t* row = jt + r * CW + lane;
-    int32_t A = 0, B = 0, Cs = 0, D = 0;
-    int k = 0;
-    for (; k < a1; ++k) A += row[k];
-    for (; k < m; ++k) B += row[k];
-    for (; k < m + c1; ++k) Cs += row[k];
-    for (; k <= 2 * rho; ++k) D += row[k];
+    int32_t w0, w1, w2;
+    walsh_three<RHO>(jt + r * CW + lane, 1, w0, w1, w2);
     const int c = r / R, yy = r - c * R;
     int16_t* h = hb + ((size_t)c * 3 * R + yy) * kWhtTW + lane;
-    h[0] = (int16_t)(A + B + Cs + D);
-    h[R * kWhtTW] = (int16_t)(A + B - Cs - D);
-    h[2 * R * kWhtTW] = (int16_t)(A - B - Cs + D);
+    h[0] = (int16_t)w0;
+    h[R * kWhtTW] = (int16_t)w1;
+    h[2 * R * kWhtTW] = (int16_t)w2;
   }
   __syncthreads();
-  // vertical runs: thread (lane, grp) owns column lane, rows 4 grp .. 4 grp + 3
-  const int x = x0 + lane;
+  // vertical runs: thread (lane, grp) owns column lane, rows 4 grp .. 4 grp +
+  // 3; the runs of the first row are summed, then slid one row at a time
+  const int x = x0 + lane, py0 = 4 * grp;
+  int32_t run[3][3][4];   // [channel][plane][A, B, Cs, D]
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      if (c < C) {
+        const int16_t* col = hb + ((size_t)(c * 3 + v) * R + py0) * kWhtTW + lane;
+        int32_t A = 0, B = 0, Cs = 0, D = 0;
+#pragma unroll
+        for (int k = 0; k <= 2 * RHO; ++k) {
+          const int32_t h = col[k * kWhtTW];
+          if (k < a1) A += h;
+          else if (k < m) B += h;
+          else if (k < m + c1) Cs += h;
+          else D += h;
+        }
+        run[c][v][0] = A;
+        run[c][v][1] = B;
+        run[c][v][2] = Cs;
+        run[c][v][3] = D;
+      }
+    }
+#pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int py = 4 * grp + i, y = y0 + py;
+    if (i > 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          if (c < C) {
+            // the runs move down one row: each loses its first row and gains
+            // the one after its last
+            const int16_t* col = hb + ((size_t)(c * 3 + v) * R + py0 + i - 1) * kWhtTW + lane;
+            const int32_t h0 = col[0], ha = col[a1 * kWhtTW], hm = col[m * kWhtTW];
+            const int32_t hc = col[(m + c1) * kWhtTW], he = col[(2 * RHO + 1) * kWhtTW];
+            run[c][v][0] += ha - h0;
+            run[c][v][1] += hm - ha;
+            run[c][v][2] += hc - hm;
+            run[c][v][3] += he - hc;
+          }
+        }
+    }
     int32_t out[32];
 #pragma unroll
     for (int j = 0; j < 32; ++j) out[j] = 0;
@@ -453,13 +497,7 @@ __global__ __launch_bounds__(256) void k_wht(const uint8_t* __restrict__ J, int 
         int32_t w[3][3];   // w[u][v]: vertical function u over horizontal plane v
 #pragma unroll
         for (int v = 0; v < 3; ++v) {
-          const int16_t* col = hb + ((size_t)(c * 3 + v) * R + py) * kWhtTW + lane;
-          int32_t A = 0, B = 0, Cs = 0, D = 0;
-          int k = 0;
-          for (; k < a1; ++k) A += col[k * kWhtTW];
-          for (; k < m; ++k) B += col[k * kWhtTW];
-          for (; k < m + c1; ++k) Cs += col[k * kWhtTW];
-          for (; k <= 2 * rho; ++k) D += col[k * kWhtTW];
+          const int32_t A = run[c][v][0], B = run[c][v][1], Cs = run[c][v][2], D = run[c][v][3];
           w[0][v] = A + B + Cs + D;
           w[1][v] = A + B - Cs - D;
           w[2][v] = A - B - Cs + D;
@@ -475,6 +513,7 @@ __global__ __launch_bounds__(256) void k_wht(const uint8_t* __restrict__ J, int 
         out[9 * c + 8] = w[2][2];
       }
     }
+    const int y = y0 + py0 + i;
     if (x < W && y < H) {
       typedef int32_t v4_t __attribute__((ext_vector_type(4)));
       v4_t* dst = reinterpret_cast<v4_t*>(V + ((size_t)y * W + x) * stride);
@@ -485,18 +524,35 @@ __global__ __launch_bounds__(256) void k_wht(const uint8_t* __restrict__ J, int 
   }
 }
 
+template <int RHO>
+static void launch_wht(const ff_desc* d, const uint8_t* lab, int32_t* V, hipStream_t stream) {
+  const dim3 grid((d->width + kWhtTW - 1) / kWhtTW, (d->height + kWhtTH - 1) / kWhtTH);
+  k_wht<RHO><<<grid, 256, wht_lds_bytes(d->channels, RHO), stream>>>(lab, d->width, d->height, d->channels,
+                                                                      d->wht_stride, V);
+}
+
 static void enqueue_wht(const ff_desc* d, const uint8_t* lab, char* base, hipStream_t stream) {
-  if (d->n_radii <= 0) return;
-  WhtRadii rr{};
-  int rmax = 0;
+  static_assert(kMaxRadius == 15, "one instance per radius");
   for (int i = 0; i < d->n_radii; ++i) {
-    rr.rho[i] = d->radii[i];
-    rmax = max(rmax, d->radii[i]);
+    int32_t* V = reinterpret_cast<int32_t*>(base + d->off_wht) + (size_t)i * d->width * d->height * d->wht_stride;
+    switch (d->radii[i]) {
+      case 1: launch_wht<1>(d, lab, V, stream); break;
+      case 2: launch_wht<2>(d, lab, V, stream); break;
+      case 3: launch_wht<3>(d, lab, V, stream); break;
+      case 4: launch_wht<4>(d, lab, V, stream); break;
+      case 5: launch_wht<5>(d, lab, V, stream); break;
+      case 6: launch_wht<6>(d, lab, V, stream); break;
+      case 7: launch_wht<7>(d, lab, V, stream); break;
+      case 8: launch_wht<8>(d, lab, V, stream); break;
+      case 9: launch_wht<9>(d, lab, V, stream); break;
+      case 10: launch_wht<10>(d, lab, V, stream); break;
+      case 11: launch_wht<11>(d, lab, V, stream); break;
+      case 12: launch_wht<12>(d, lab, V, stream); break;
+      case 13: launch_wht<13>(d, lab, V, stream); break;
+      case 14: launch_wht<14>(d, lab, V, stream); break;
+      default: launch_wht<15>(d, lab, V, stream); break;
+    }
   }
-  const size_t lds = wht_lds_bytes(d->channels, rmax);
-  const dim3 grid((d->width + kWhtTW - 1) / kWhtTW, (d->height + kWhtTH - 1) / kWhtTH, d->n_radii);
-  k_wht<<<grid, 256, lds, stream>>>(lab, d->width, d->height, d->channels, rr, d->wht_stride,
-                                    reinterpret_cast<int32_t*>(base + d->off_wht));
 }
 
 // ---------------------------------------------------------------- SIFT colour levels
