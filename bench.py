@@ -473,7 +473,7 @@ def main():
                     "occluded_fraction": round(float(pair.occluded.mean()), 4)},
     }
     if not args.no_secondary:
-        line["kernels"] = kernel_table(ff, run, torch, W, H, C)
+        line["kernels"] = kernel_table(ff, run, torch, W, H, C, img=img1)
         if args.pipeline and len(each) >= 3 * per_field:
             line["level1_sweep"] = level1_sweep(each, per_field, args.steps, W, H, args.band_rows)
         line["secondary"] = secondary(ff, torch, dev, pair, skewed, args.steps)
@@ -490,13 +490,21 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def kernel_table(ff, run, torch, W, H, C):
+def kernel_table(ff, run, torch, W, H, C, img=None):
     """Every kernel class of the step against its own bound: algorithmic
-    bytes per launch over the measured launch time, against the HBM peak."""
+    bytes per launch over the measured launch time, against the HBM peak.
+    In the step the two images' descriptors share the GPU; the descriptor
+    classes are also timed for one image alone (`alone_*`)."""
     ab = algorithmic_bytes(W, H, C)
     classes = ["lab", "smooth", "census", "wht", "descriptors", "tree", "seed", "level_entry", "random_search",
                "filter"]
     t = class_times(ff, run, torch, classes)
+    alone = {}
+    if img is not None:
+        d = ff.ff_desc_init(W, H, C, K, Q, (R, R2))
+        blob = torch.empty(d.bytes, dtype=torch.uint8, device=img.device)
+        alone = class_times(ff, lambda: ff.ff_compute_descriptors(d, img, blob), torch,
+                            ["lab", "smooth", "census", "wht", "descriptors"], reps=10)
     table = {}
     for c in classes:
         ms, per = t[c]
@@ -506,6 +514,10 @@ def kernel_table(ff, run, torch, W, H, C):
         elif c in ab:
             gbs = ab[c] / (ms / 1000.0) / 1e9
             row.update(bound="hbm", algorithmic_bytes=ab[c], GBps=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
+            if c in alone:
+                gba = ab[c] / (alone[c][0] / 1000.0) / 1e9
+                row.update(alone_ms=round(alone[c][0], 4), alone_GBps=round(gba, 1),
+                           alone_frac=round(gba / HBM_PEAK_GBS, 4))
         else:
             row.update(bound="alu/latency")
         table[c] = row

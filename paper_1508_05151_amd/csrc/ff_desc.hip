@@ -216,10 +216,8 @@ __global__ void k_lanczos_v(const int32_t* __restrict__ T, int W, int H, int n, 
 // 32 words is one 128-byte line), and transposed (plane[x][y]) through an
 // LDS buffer, so that a column of 32 words is one line as well.
 constexpr int kCensusTile = 32;
-constexpr int kCensusMaxN = 16;              // largest level stride (k <= 4)
 constexpr int kCensusPB = 16;                // phases held in registers at once
 constexpr int kCensusTP = 4;                 // phases per LDS transposition round
-constexpr int kCensusLW = kCensusTile + 2 * kCensusMaxN + 2;
 
 // One channel's comparison bits for the thread's four pixels and the PB
 // phases from row b0 on.  INTERIOR: the tile grown by n + 1 lies inside the
@@ -283,7 +281,7 @@ __device__ __forceinline__ void census_channel(const int16_t* __restrict__ T, in
 // the row-major and the transposed stores.  One instance per kind of tile, so
 // that the two never share a register allocation.
 template <int Q, bool INTERIOR, int TP, int PB>
-__device__ __forceinline__ void census_tile_impl(int16_t (*tileS)[kCensusLW * kCensusLW],
+__device__ __forceinline__ void census_tile_impl(const int16_t* tileS, int plane,
                                                  uint32_t (*tbuf)[kCensusTile][kCensusTile + 1], int W, int H, int C,
                                                  int n, int x0, int y0, int sx0, int sy0, int LW, uint32_t* rm,
                                                  uint32_t* tr) {
@@ -299,7 +297,7 @@ __device__ __forceinline__ void census_tile_impl(int16_t (*tileS)[kCensusLW * kC
 #pragma unroll
       for (int ph = 0; ph < PB; ++ph) acc[k][ph] = 0;
     for (int c = C - 1; c >= 0; --c) {
-      census_channel<Q, PB, INTERIOR>(tileS[c], LW, n, W, H, sx0, sy0, xc, y0 + ty, b0, acc);
+      census_channel<Q, PB, INTERIOR>(tileS + c * plane, LW, n, W, H, sx0, sy0, xc, y0 + ty, b0, acc);
     }
     // row-major words
 #pragma unroll
@@ -335,20 +333,22 @@ __device__ __forceinline__ void census_tile_impl(int16_t (*tileS)[kCensusLW * kC
 }
 
 template <int Q, bool INTERIOR>
-__device__ __forceinline__ void census_tile(int16_t (*tileS)[kCensusLW * kCensusLW],
+__device__ __forceinline__ void census_tile(const int16_t* tileS, int plane,
                                             uint32_t (*tbuf)[kCensusTile][kCensusTile + 1], int W, int H, int C,
                                             int n, int x0, int y0, int sx0, int sy0, int LW, uint32_t* rm,
                                             uint32_t* tr) {
   constexpr int QQ = Q * Q, PB = QQ < kCensusPB ? QQ : kCensusPB, TP = PB < kCensusTP ? PB : kCensusTP;
-  census_tile_impl<Q, INTERIOR, TP, PB>(tileS, tbuf, W, H, C, n, x0, y0, sx0, sy0, LW, rm, tr);
+  census_tile_impl<Q, INTERIOR, TP, PB>(tileS, plane, tbuf, W, H, C, n, x0, y0, sx0, sy0, LW, rm, tr);
 }
 
 template <int Q>
-__global__ __launch_bounds__(256) void k_census(const int16_t* __restrict__ Sall, int W, int H, int C,
+__global__ __launch_bounds__(256) void k_census(const int16_t* __restrict__ Sall, int W, int H, int C, int plane,
                                                 uint32_t* __restrict__ outRM, uint32_t* __restrict__ outT) {
   constexpr int QQ = Q * Q, PB = QQ < kCensusPB ? QQ : kCensusPB, TP = PB < kCensusTP ? PB : kCensusTP;
   static_assert(QQ % PB == 0 && PB % TP == 0 && PB % Q == 0, "phase blocks");
-  __shared__ int16_t tileS[3][kCensusLW * kCensusLW];
+  // the staged windows, C of them, LWmax^2 int16 each (sized by the
+  // launch for the descriptor's coarsest level)
+  extern __shared__ __align__(16) int16_t census_lds[];
   __shared__ uint32_t tbuf[TP][kCensusTile][kCensusTile + 1];
   const int lev = blockIdx.z, n = 1 << lev;
   const size_t N = (size_t)W * H;
@@ -366,11 +366,11 @@ __global__ __launch_bounds__(256) void k_census(const int16_t* __restrict__ Sall
   for (int r = ty; r < C * LH; r += 8) {
     const int c = r / LH, yy = r - c * LH;
     const int16_t* src = S + (size_t)c * N + (size_t)(sy0 + yy) * W + sx0;
-    for (int xx = tx; xx < LW; xx += 32) tileS[c][yy * LW + xx] = src[xx];
+    for (int xx = tx; xx < LW; xx += 32) census_lds[c * plane + yy * LW + xx] = src[xx];
   }
   __syncthreads();
-  if (interior) census_tile<Q, true>(tileS, tbuf, W, H, C, n, x0, y0, sx0, sy0, LW, rm, tr);
-  else census_tile<Q, false>(tileS, tbuf, W, H, C, n, x0, y0, sx0, sy0, LW, rm, tr);
+  if (interior) census_tile<Q, true>(census_lds, plane, tbuf, W, H, C, n, x0, y0, sx0, sy0, LW, rm, tr);
+  else census_tile<Q, false>(census_lds, plane, tbuf, W, H, C, n, x0, y0, sx0, sy0, LW, rm, tr);
 }
 
 // ---------------------------------------------------------------- WHT
@@ -746,11 +746,13 @@ ff_status ff_compute_descriptors(const ff_desc* d, const ff_image* img, const ui
     uint32_t* rm = reinterpret_cast<uint32_t*>(base + d->off_census);
     uint32_t* tr = reinterpret_cast<uint32_t*>(base + d->off_census_t);
     const dim3 cg((W + kCensusTile - 1) / kCensusTile, (H + kCensusTile - 1) / kCensusTile, d->k + 1);
+    const int lw = kCensusTile + 2 * (1 << d->k) + 2, plane = lw * lw;
+    const size_t lds = (size_t)C * plane * sizeof(int16_t);
     switch (d->subpel) {
-      case 1: k_census<1><<<cg, tb, 0, stream>>>(smooth, W, H, C, rm, tr); break;
-      case 2: k_census<2><<<cg, tb, 0, stream>>>(smooth, W, H, C, rm, tr); break;
-      case 4: k_census<4><<<cg, tb, 0, stream>>>(smooth, W, H, C, rm, tr); break;
-      default: k_census<8><<<cg, tb, 0, stream>>>(smooth, W, H, C, rm, tr); break;
+      case 1: k_census<1><<<cg, tb, lds, stream>>>(smooth, W, H, C, plane, rm, tr); break;
+      case 2: k_census<2><<<cg, tb, lds, stream>>>(smooth, W, H, C, plane, rm, tr); break;
+      case 4: k_census<4><<<cg, tb, lds, stream>>>(smooth, W, H, C, plane, rm, tr); break;
+      default: k_census<8><<<cg, tb, lds, stream>>>(smooth, W, H, C, plane, rm, tr); break;
     }
   }
   prof_mark(FF_PROF_CENSUS, stream, false);
