@@ -383,12 +383,17 @@ __global__ __launch_bounds__(256) void k_census(const int16_t* __restrict__ Sall
 // (1,1) (0,2) (2,0) (1,2) (2,1) (2,2), per channel; samples are clamped to
 // the image.
 //
-// One launch for every radius (grid z).  A workgroup owns a 64 x 16 tile:
+// One launch per radius.  A workgroup owns a 32 x 16 tile:
 // its Lab8 window (grown by rho, clamped) goes to LDS, the three horizontal
 // run combinations of every window row and tile column to LDS as int16
 // (|w| <= (2 rho + 1) 255), and each thread combines vertical runs of those
 // into the 9 C values of its pixels, written as one 128-byte row per pixel.
-constexpr int kWhtTW = 64, kWhtTH = 16;
+#ifndef WHT_TW
+#define WHT_TW 32
+#endif
+constexpr int kWhtTW = WHT_TW, kWhtTH = 16;
+constexpr int kWhtG = 256 / kWhtTW;            // thread groups (one per tile column set)
+constexpr int kWhtRPT = kWhtTH / kWhtG;        // output rows per thread
 
 __host__ __device__ constexpr int wht_rows(int rho) { return kWhtTH + 2 * rho; }
 __host__ __device__ constexpr int wht_cols(int rho) { return kWhtTW + 2 * rho; }
@@ -425,15 +430,15 @@ __global__ __launch_bounds__(256) void k_wht(const uint8_t* __restrict__ J, int 
   const int x0 = blockIdx.x * kWhtTW, y0 = blockIdx.y * kWhtTH;
   uint8_t* jt = wht_lds;                                                                  // [C][R][CW]
   int16_t* hb = reinterpret_cast<int16_t*>(wht_lds + (((size_t)C * R * CW + 15) & ~(size_t)15));   // [C][3][R][64]
-  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  for (int r = grp; r < C * R; r += 4) {
+  const int lane = threadIdx.x % kWhtTW, grp = threadIdx.x / kWhtTW;
+  for (int r = grp; r < C * R; r += kWhtG) {
     const int c = r / R, yy = r - c * R;
     const uint8_t* src = J + (size_t)c * N + (size_t)clampi(y0 - RHO + yy, 0, H - 1) * W;
-    for (int xx = lane; xx < CW; xx += 64) jt[r * CW + xx] = src[clampi(x0 - RHO + xx, 0, W - 1)];
+    for (int xx = lane; xx < CW; xx += kWhtTW) jt[r * CW + xx] = src[clampi(x0 - RHO + xx, 0, W - 1)];
   }
   __syncthreads();
   // horizontal runs of every window row at tile column `lane`
-  for (int r = grp; r < C * R; r += 4) {
+  for (int r = grp; r < C * R; r += kWhtG) {
     int32_t w0, w1, w2;
     walsh_three<RHO>(jt + r * CW + lane, 1, w0, w1, w2);
     const int c = r / R, yy = r - c * R;
@@ -443,9 +448,10 @@ __global__ __launch_bounds__(256) void k_wht(const uint8_t* __restrict__ J, int 
     h[2 * R * kWhtTW] = (int16_t)w2;
   }
   __syncthreads();
-  // vertical runs: thread (lane, grp) owns column lane, rows 4 grp .. 4 grp +
-  // 3; the runs of the first row are summed, then slid one row at a time
-  const int x = x0 + lane, py0 = 4 * grp;
+  // vertical runs: thread (lane, grp) owns column lane and kWhtRPT rows from
+  // kWhtRPT grp; the runs of the first row are summed, then slid one row at a
+  // time
+  const int x = x0 + lane, py0 = kWhtRPT * grp;
   int32_t run[3][3][4];   // [channel][plane][A, B, Cs, D]
 #pragma unroll
   for (int c = 0; c < 3; ++c)
@@ -469,7 +475,7 @@ __global__ __launch_bounds__(256) void k_wht(const uint8_t* __restrict__ J, int 
       }
     }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < kWhtRPT; ++i) {
     if (i > 0) {
 #pragma unroll
       for (int c = 0; c < 3; ++c)
