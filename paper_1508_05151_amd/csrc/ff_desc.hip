@@ -145,54 +145,112 @@ __global__ void k_lab8(const uint8_t* __restrict__ img, int W, int H, int C, int
 }
 
 // ---------------------------------------------------------------- I^n
-__global__ void k_scale16(const uint8_t* __restrict__ lab, int16_t* __restrict__ out, size_t n) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = (int16_t)(16 * lab[i]);
+// Every level in three launches: (1) level 0 (Lab8 with 4 fractional bits)
+// and the n x n block sums of the replicate-padded planes of every coarser
+// level, (2) every level's horizontal Lanczos pass (coarse rows to
+// full-resolution columns, rounded back to block-sum units), (3) every
+// level's vertical pass (divided by 2^14 n^2, 4 fractional bits kept).  One
+// thread per output element over the levels laid end to end; each level has
+// its own block-sum and pass buffers in the scratch region.
+constexpr int kMaxLevels = 5;   // k <= 4
+
+struct SmoothPlan {
+  int W, H, C, k;
+  int Wc[kMaxLevels], Hc[kMaxLevels];
+  int64_t end1[kMaxLevels];   // stage 1: level 0's C N samples, then each level's C Hc Wc block sums
+  int64_t end2[kMaxLevels];   // stage 2: each level's C Hc W horizontal outputs (end2[0] = 0)
+  int64_t offA[kMaxLevels], offT[kMaxLevels];   // int32 offsets of a level's buffers in the scratch
+};
+
+SmoothPlan smooth_plan(int W, int H, int C, int k) {
+  SmoothPlan p{};
+  p.W = W;
+  p.H = H;
+  p.C = C;
+  p.k = k;
+  const int64_t N = (int64_t)W * H;
+  p.end1[0] = C * N;
+  p.end2[0] = 0;
+  int64_t off = 0;
+  for (int l = 1; l <= k; ++l) {
+    const int n = 1 << l;
+    p.Wc[l] = (W + n - 1) / n;
+    p.Hc[l] = (H + n - 1) / n;
+    p.end1[l] = p.end1[l - 1] + (int64_t)C * p.Hc[l] * p.Wc[l];
+    p.end2[l] = p.end2[l - 1] + (int64_t)C * p.Hc[l] * W;
+    p.offA[l] = off;
+    off += (int64_t)C * p.Hc[l] * p.Wc[l];
+    p.offT[l] = off;
+    off += (int64_t)C * p.Hc[l] * W;
+  }
+  return p;
 }
 
-// n x n block sums of the replicate-padded plane
-__global__ void k_blocksum(const uint8_t* __restrict__ J, int W, int H, int n, int Wc, int Hc, int32_t* __restrict__ A) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y;
-  const int c = blockIdx.z;
-  if (j >= Wc) return;
+// int32 words of scratch the smoothing needs
+size_t smooth_scratch_words(int W, int H, int C, int k) {
+  const SmoothPlan p = smooth_plan(W, H, C, k);
+  return k == 0 ? 0 : (size_t)(p.offT[k] + (int64_t)C * p.Hc[k] * W);
+}
+
+__global__ void k_smooth_blocks(const uint8_t* __restrict__ J, SmoothPlan p, int16_t* __restrict__ S,
+                                int32_t* __restrict__ scratch) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.end1[p.k]) return;
+  if (i < p.end1[0]) {
+    S[i] = (int16_t)(16 * J[i]);
+    return;
+  }
+  int l = 1;
+  while (l < p.k && i >= p.end1[l]) ++l;
+  const int64_t e = i - p.end1[l - 1];
+  const int Wc = p.Wc[l], Hc = p.Hc[l], n = 1 << l, W = p.W, H = p.H;
+  const int j = (int)(e % Wc);
+  const int64_t r = e / Wc;
+  const int ii = (int)(r % Hc), c = (int)(r / Hc);
   const uint8_t* P = J + (size_t)c * W * H;
   int32_t s = 0;
   for (int u = 0; u < n; ++u) {
-    const uint8_t* row = P + (size_t)min(i * n + u, H - 1) * W;
+    const uint8_t* row = P + (size_t)min(ii * n + u, H - 1) * W;
     for (int v = 0; v < n; ++v) s += row[min(j * n + v, W - 1)];
   }
-  A[((size_t)c * Hc + i) * Wc + j] = s;
+  scratch[p.offA[l] + e] = s;
 }
 
-// horizontal Lanczos pass: coarse rows -> full-resolution columns, rounded
-// back to block-sum units
-__global__ void k_lanczos_h(const int32_t* __restrict__ A, int W, int n, int li, int Wc, int Hc, int32_t* __restrict__ T) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y;
-  const int c = blockIdx.z;
-  if (x >= W) return;
-  const int32_t* row = A + ((size_t)c * Hc + i) * Wc;
+__global__ void k_smooth_h(SmoothPlan p, int32_t* __restrict__ scratch) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.end2[p.k]) return;
+  int l = 1;
+  while (l < p.k && i >= p.end2[l]) ++l;
+  const int64_t e = i - p.end2[l - 1];
+  const int Wc = p.Wc[l], Hc = p.Hc[l], n = 1 << l, W = p.W;
+  const int x = (int)(e % W);
+  const int64_t rc = e / W;   // c Hc + i
+  (void)Hc;
+  const int32_t* row = scratch + p.offA[l] + rc * Wc;
   const int ph = x % n, base = x / n;
   int32_t s = 0;
 #pragma unroll
-  for (int k = 0; k < 7; ++k) s += c_lanczos[li][ph][k] * row[clampi(base + k - 3, 0, Wc - 1)];
-  T[((size_t)c * Hc + i) * W + x] = (s + 8192) >> 14;
+  for (int k = 0; k < 7; ++k) s += c_lanczos[l - 1][ph][k] * row[clampi(base + k - 3, 0, Wc - 1)];
+  scratch[p.offT[l] + e] = (s + 8192) >> 14;
 }
 
-// vertical pass: divide by 2^14 n^2 and keep 4 fractional bits
-__global__ void k_lanczos_v(const int32_t* __restrict__ T, int W, int H, int n, int li, int Hc, int shift,
-                            int16_t* __restrict__ S) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y;
-  const int c = blockIdx.z;
-  if (x >= W) return;
-  const int32_t* P = T + (size_t)c * Hc * W;
+__global__ void k_smooth_v(SmoothPlan p, const int32_t* __restrict__ scratch, int16_t* __restrict__ S) {
+  const int64_t N = (int64_t)p.W * p.H, CN = p.C * N;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.k * CN) return;
+  const int l = 1 + (int)(i / CN);
+  const int64_t e = i - (l - 1) * CN;
+  const int Hc = p.Hc[l], n = 1 << l, W = p.W, H = p.H;
+  const int x = (int)(e % W);
+  const int64_t r = e / W;
+  const int y = (int)(r % H), c = (int)(r / H);
+  const int32_t* P = scratch + p.offT[l] + (int64_t)c * Hc * W;
   const int ph = y % n, base = y / n;
   int32_t s = 0;
 #pragma unroll
-  for (int k = 0; k < 7; ++k) s += c_lanczos[li][ph][k] * P[(size_t)clampi(base + k - 3, 0, Hc - 1) * W + x];
-  S[((size_t)c * H + y) * W + x] = (int16_t)((s + (1 << (shift - 1))) >> shift);
+  for (int k = 0; k < 7; ++k) s += c_lanczos[l - 1][ph][k] * P[(size_t)clampi(base + k - 3, 0, Hc - 1) * W + x];
+  const int shift = 14 + 2 * l - 4;
+  S[l * CN + e] = (int16_t)((s + (1 << (shift - 1))) >> shift);
 }
 
 // ---------------------------------------------------------------- census
@@ -686,11 +744,9 @@ ff_status ff_desc_init(ff_desc* d, const ff_image* img, int32_t k, int32_t subpe
   d->off_census = off;
   d->plane_bytes = N * 4;
   size_t census = (size_t)(k + 1) * subpel * subpel * N * 4;
-  // the census region doubles as scratch before the planes are written
-  const int Wc2 = (W + 1) / 2, Hc2 = (H + 1) / 2;
-  size_t scratch = (size_t)C * 3 * N * 4;
-  const size_t sm = (size_t)C * ((size_t)Hc2 * Wc2 + (size_t)Hc2 * W) * 4;
-  if (sm > scratch) scratch = sm;
+  // the census region doubles as the smoothing's scratch (every level's
+  // block sums and horizontal pass) before the planes are written
+  const size_t scratch = smooth_scratch_words(W, H, C, k) * 4;
   if (scratch > census) census = scratch;
   off = align_up(off + census, 256);
   d->off_census_t = off;
@@ -732,16 +788,14 @@ ff_status ff_compute_descriptors(const ff_desc* d, const ff_image* img, const ui
   k_lab8<<<dim3(gx, H), tb, 0, stream>>>(pixels, W, H, C, img->row_stride, lab);
   prof_mark(FF_PROF_LAB, stream, false);
   prof_mark(FF_PROF_SMOOTH, stream, true);
-  k_scale16<<<(unsigned)((C * N + 255) / 256), tb, 0, stream>>>(lab, smooth, C * N);
-  for (int lev = 1; lev <= d->k; ++lev) {
-    const int n = 1 << lev;
-    const int Wc = (W + n - 1) / n, Hc = (H + n - 1) / n;
-    int32_t* A = scratch;
-    int32_t* T = scratch + (size_t)C * Hc * Wc;
-    k_blocksum<<<dim3((unsigned)((Wc + 255) / 256), Hc, C), tb, 0, stream>>>(lab, W, H, n, Wc, Hc, A);
-    k_lanczos_h<<<dim3(gx, Hc, C), tb, 0, stream>>>(A, W, n, lev - 1, Wc, Hc, T);
-    const int shift = 14 + 2 * lev - 4;
-    k_lanczos_v<<<dim3(gx, H, C), tb, 0, stream>>>(T, W, H, n, lev - 1, Hc, shift, smooth + (size_t)lev * C * N);
+  {
+    const SmoothPlan sp = smooth_plan(W, H, C, d->k);
+    const auto blocks = [](int64_t items) { return (unsigned)((items + 255) / 256); };
+    k_smooth_blocks<<<blocks(sp.end1[d->k]), tb, 0, stream>>>(lab, sp, smooth, scratch);
+    if (d->k > 0) {
+      k_smooth_h<<<blocks(sp.end2[d->k]), tb, 0, stream>>>(sp, scratch);
+      k_smooth_v<<<blocks((int64_t)d->k * C * (int64_t)N), tb, 0, stream>>>(sp, scratch, smooth);
+    }
   }
   prof_mark(FF_PROF_SMOOTH, stream, false);
   prof_mark(FF_PROF_WHT, stream, true);
