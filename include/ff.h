@@ -91,7 +91,11 @@ typedef struct {
   int32_t leaf;       /* kd-tree leaf size l [8], 1..64 */
   int32_t n_prop;     /* propagation sweeps per level [4] */
   int32_t n_rs;       /* random searches per level, after sweeps 1..n_rs [3] */
-  int32_t use_kdtree; /* 1: kd-tree seeds (Eq. 1 / Eq. 4); 0: proposal only */
+  int32_t use_kdtree; /* 1: kd-tree seeds (Eq. 1 / Eq. 4), the tree built in the
+                         call; 2: kd-tree seeds from the tree that
+                         ff_match_field_tree left in the same workspace for
+                         the same field and arguments (one-field calls only);
+                         0: proposal only */
   int32_t max_steps;  /* < 0: whole search; else stop after this many steps
                          (1 seed step, 7 at the coarsest level, 8 per finer
                          level) and write the current grid -- for inspection */
@@ -153,6 +157,19 @@ size_t ff_match_workspace_bytes(const ff_desc* src, const ff_desc* dst, int32_t 
 ff_status ff_match_field(const ff_desc* src, const void* src_blob, const ff_desc* dst, const void* dst_blob,
                          int32_t radius, const ff_match_params* p, const int32_t* proposal, int32_t* flow,
                          int32_t* cost, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * The kd-tree of ff_match_field alone (section 3.1, over dst's WHT(radius)
+ * vectors), built into `workspace`, so that it can start as soon as the WHT
+ * vectors exist (ff_compute_lab_wht) while the census planes are still being
+ * computed.  A following ff_match_field with the same arguments, the same
+ * workspace and p->use_kdtree = 2 seeds from it instead of building it; its
+ * results equal a call with use_kdtree = 1.  p->use_kdtree must be nonzero.
+ * The blobs need only their WHT regions at this point.
+ */
+ff_status ff_match_field_tree(const ff_desc* src, const void* src_blob, const ff_desc* dst, const void* dst_blob,
+                              int32_t radius, const ff_match_params* p, void* workspace, size_t workspace_bytes,
+                              hipStream_t stream);
 
 /*
  * Batched matching: many fields (of pairs of any sizes) in one call, every
@@ -381,6 +398,13 @@ ff_status ff_sift_levels(const int16_t* codes, int32_t width, int32_t height, in
  * left as they are. */
 ff_status ff_compute_lab_wht(const ff_desc* d, const ff_image* img, const uint8_t* pixels, void* blob,
                              size_t blob_bytes, hipStream_t stream);
+
+/* The rest of ff_compute_descriptors (sections 3.2, 3.3): the smoothed levels
+ * I^n and the census planes of every level and phase, both layouts, from the
+ * Lab8 planes that ff_compute_lab_wht wrote into the same blob (queued before
+ * it on the same stream, or waited for).  ff_compute_lab_wht followed by
+ * ff_compute_census fills the blob exactly as ff_compute_descriptors does. */
+ff_status ff_compute_census(const ff_desc* d, void* blob, size_t blob_bytes, hipStream_t stream);
 
 /*
  * Flow Fields with the SIFT-flow data term (sections 3.1-3.3), a batch of

@@ -699,6 +699,67 @@ void enqueue_sift_levels(const int16_t* codes, int W, int H, int S, int P, int k
   }
 }
 
+// argument checks shared by the entry points that take an image
+static ff_status check_image(const ff_desc* d, const ff_image* img, const uint8_t* pixels, void* blob,
+                             size_t blob_bytes) {
+  if (!d || !img || !pixels || !blob) return FF_ERR_ARG;
+  if (img->width != d->width || img->height != d->height || img->channels != d->channels ||
+      img->row_stride < img->width * img->channels)
+    return FF_ERR_ARG;
+  if (blob_bytes < d->bytes) return FF_ERR_WORKSPACE;
+  return ensure_init();
+}
+
+// Lab8 planes and the WHT vectors of every radius
+static void enqueue_lab_wht(const ff_desc* d, const ff_image* img, const uint8_t* pixels, char* base,
+                            hipStream_t stream) {
+  uint8_t* lab = reinterpret_cast<uint8_t*>(base + d->off_lab);
+  prof_mark(FF_PROF_LAB, stream, true);
+  k_lab8<<<dim3((unsigned)((d->width + 255) / 256), d->height), dim3(256), 0, stream>>>(
+      pixels, d->width, d->height, d->channels, img->row_stride, lab);
+  prof_mark(FF_PROF_LAB, stream, false);
+  prof_mark(FF_PROF_WHT, stream, true);
+  enqueue_wht(d, lab, base, stream);
+  prof_mark(FF_PROF_WHT, stream, false);
+}
+
+// the smoothed levels I^n and the census planes of every level and phase,
+// from the blob's Lab8 planes
+static void enqueue_levels_census(const ff_desc* d, char* base, hipStream_t stream) {
+  const int W = d->width, H = d->height, C = d->channels;
+  const size_t N = (size_t)W * H;
+  const uint8_t* lab = reinterpret_cast<const uint8_t*>(base + d->off_lab);
+  int16_t* smooth = reinterpret_cast<int16_t*>(base + d->off_smooth);
+  int32_t* scratch = reinterpret_cast<int32_t*>(base + d->off_census);
+  const dim3 tb(256);
+  prof_mark(FF_PROF_SMOOTH, stream, true);
+  {
+    const SmoothPlan sp = smooth_plan(W, H, C, d->k);
+    const auto blocks = [](int64_t items) { return (unsigned)((items + 255) / 256); };
+    k_smooth_blocks<<<blocks(sp.end1[d->k]), tb, 0, stream>>>(lab, sp, smooth, scratch);
+    if (d->k > 0) {
+      k_smooth_h<<<blocks(sp.end2[d->k]), tb, 0, stream>>>(sp, scratch);
+      k_smooth_v<<<blocks((int64_t)d->k * C * (int64_t)N), tb, 0, stream>>>(sp, scratch, smooth);
+    }
+  }
+  prof_mark(FF_PROF_SMOOTH, stream, false);
+  prof_mark(FF_PROF_CENSUS, stream, true);
+  {
+    uint32_t* rm = reinterpret_cast<uint32_t*>(base + d->off_census);
+    uint32_t* tr = reinterpret_cast<uint32_t*>(base + d->off_census_t);
+    const dim3 cg((W + kCensusTile - 1) / kCensusTile, (H + kCensusTile - 1) / kCensusTile, d->k + 1);
+    const int lw = kCensusTile + 2 * (1 << d->k) + 2, plane = lw * lw;
+    const size_t lds = (size_t)C * plane * sizeof(int16_t);
+    switch (d->subpel) {
+      case 1: k_census<1><<<cg, tb, lds, stream>>>(smooth, W, H, C, plane, rm, tr); break;
+      case 2: k_census<2><<<cg, tb, lds, stream>>>(smooth, W, H, C, plane, rm, tr); break;
+      case 4: k_census<4><<<cg, tb, lds, stream>>>(smooth, W, H, C, plane, rm, tr); break;
+      default: k_census<8><<<cg, tb, lds, stream>>>(smooth, W, H, C, plane, rm, tr); break;
+    }
+  }
+  prof_mark(FF_PROF_CENSUS, stream, false);
+}
+
 }  // namespace ff
 
 using namespace ff;
@@ -767,79 +828,29 @@ ff_status ff_desc_init(ff_desc* d, const ff_image* img, int32_t k, int32_t subpe
 
 ff_status ff_compute_descriptors(const ff_desc* d, const ff_image* img, const uint8_t* pixels, void* blob,
                                  size_t blob_bytes, hipStream_t stream) {
-  if (!d || !img || !pixels || !blob) return FF_ERR_ARG;
-  if (img->width != d->width || img->height != d->height || img->channels != d->channels ||
-      img->row_stride < img->width * img->channels)
-    return FF_ERR_ARG;
-  if (blob_bytes < d->bytes) return FF_ERR_WORKSPACE;
-  ff_status st = ensure_init();
+  ff_status st = check_image(d, img, pixels, blob, blob_bytes);
   if (st != FF_OK) return st;
-  const int W = d->width, H = d->height, C = d->channels;
-  const size_t N = (size_t)W * H;
-  char* base = static_cast<char*>(blob);
-  uint8_t* lab = reinterpret_cast<uint8_t*>(base + d->off_lab);
-  int16_t* smooth = reinterpret_cast<int16_t*>(base + d->off_smooth);
-  int32_t* scratch = reinterpret_cast<int32_t*>(base + d->off_census);
-  const dim3 tb(256);
-  const unsigned gx = (unsigned)((W + 255) / 256);
-
   prof_mark(FF_PROF_DESCRIPTORS, stream, true);
-  prof_mark(FF_PROF_LAB, stream, true);
-  k_lab8<<<dim3(gx, H), tb, 0, stream>>>(pixels, W, H, C, img->row_stride, lab);
-  prof_mark(FF_PROF_LAB, stream, false);
-  prof_mark(FF_PROF_SMOOTH, stream, true);
-  {
-    const SmoothPlan sp = smooth_plan(W, H, C, d->k);
-    const auto blocks = [](int64_t items) { return (unsigned)((items + 255) / 256); };
-    k_smooth_blocks<<<blocks(sp.end1[d->k]), tb, 0, stream>>>(lab, sp, smooth, scratch);
-    if (d->k > 0) {
-      k_smooth_h<<<blocks(sp.end2[d->k]), tb, 0, stream>>>(sp, scratch);
-      k_smooth_v<<<blocks((int64_t)d->k * C * (int64_t)N), tb, 0, stream>>>(sp, scratch, smooth);
-    }
-  }
-  prof_mark(FF_PROF_SMOOTH, stream, false);
-  prof_mark(FF_PROF_WHT, stream, true);
-  enqueue_wht(d, lab, base, stream);
-  prof_mark(FF_PROF_WHT, stream, false);
-  prof_mark(FF_PROF_CENSUS, stream, true);
-  {
-    uint32_t* rm = reinterpret_cast<uint32_t*>(base + d->off_census);
-    uint32_t* tr = reinterpret_cast<uint32_t*>(base + d->off_census_t);
-    const dim3 cg((W + kCensusTile - 1) / kCensusTile, (H + kCensusTile - 1) / kCensusTile, d->k + 1);
-    const int lw = kCensusTile + 2 * (1 << d->k) + 2, plane = lw * lw;
-    const size_t lds = (size_t)C * plane * sizeof(int16_t);
-    switch (d->subpel) {
-      case 1: k_census<1><<<cg, tb, lds, stream>>>(smooth, W, H, C, plane, rm, tr); break;
-      case 2: k_census<2><<<cg, tb, lds, stream>>>(smooth, W, H, C, plane, rm, tr); break;
-      case 4: k_census<4><<<cg, tb, lds, stream>>>(smooth, W, H, C, plane, rm, tr); break;
-      default: k_census<8><<<cg, tb, lds, stream>>>(smooth, W, H, C, plane, rm, tr); break;
-    }
-  }
-  prof_mark(FF_PROF_CENSUS, stream, false);
+  enqueue_lab_wht(d, img, pixels, static_cast<char*>(blob), stream);
+  enqueue_levels_census(d, static_cast<char*>(blob), stream);
   prof_mark(FF_PROF_DESCRIPTORS, stream, false);
   return launch_status();
 }
 
-
-ff_status ff_compute_lab_wht(const ff_desc* d, const ff_image* img, const uint8_t* pixels, void* blob,
-                             size_t blob_bytes, hipStream_t stream) {
-  if (!d || !img || !pixels || !blob) return FF_ERR_ARG;
-  if (img->width != d->width || img->height != d->height || img->channels != d->channels ||
-      img->row_stride < img->width * img->channels)
-    return FF_ERR_ARG;
+ff_status ff_compute_census(const ff_desc* d, void* blob, size_t blob_bytes, hipStream_t stream) {
+  if (!d || !blob) return FF_ERR_ARG;
   if (blob_bytes < d->bytes) return FF_ERR_WORKSPACE;
   ff_status st = ensure_init();
   if (st != FF_OK) return st;
-  const int W = d->width, H = d->height, C = d->channels;
-  char* base = static_cast<char*>(blob);
-  uint8_t* lab = reinterpret_cast<uint8_t*>(base + d->off_lab);
-  const unsigned gx = (unsigned)((W + 255) / 256);
-  prof_mark(FF_PROF_LAB, stream, true);
-  k_lab8<<<dim3(gx, H), dim3(256), 0, stream>>>(pixels, W, H, C, img->row_stride, lab);
-  prof_mark(FF_PROF_LAB, stream, false);
-  prof_mark(FF_PROF_WHT, stream, true);
-  enqueue_wht(d, lab, base, stream);
-  prof_mark(FF_PROF_WHT, stream, false);
+  enqueue_levels_census(d, static_cast<char*>(blob), stream);
+  return launch_status();
+}
+
+ff_status ff_compute_lab_wht(const ff_desc* d, const ff_image* img, const uint8_t* pixels, void* blob,
+                             size_t blob_bytes, hipStream_t stream) {
+  ff_status st = check_image(d, img, pixels, blob, blob_bytes);
+  if (st != FF_OK) return st;
+  enqueue_lab_wht(d, img, pixels, static_cast<char*>(blob), stream);
   return launch_status();
 }
 

@@ -1095,6 +1095,7 @@ static ff_status check_params(const ff_desc* src, const ff_desc* dst, int radius
   if (p->band_rows != 0 && p->band_rows != 8 && p->band_rows != 16 && p->band_rows != 32) return FF_ERR_ARG;
   if (p->pipeline != 0 && p->pipeline != 1) return FF_ERR_ARG;
   if (p->watchdog_us < 0) return FF_ERR_ARG;
+  if (p->use_kdtree < 0 || p->use_kdtree > 2) return FF_ERR_ARG;
   if (p->use_kdtree) {
     if (p->leaf < 2 || p->leaf > kMaxLeaf) return FF_ERR_ARG;
     bool hs = false, hd = false;
@@ -1221,8 +1222,10 @@ static void write_table(const JobArray<FieldRec>& recs, int nrec, FieldRec* dev,
 
 // The whole search for a batch of fields.  Every stage is one launch over
 // all fields (propagation: one launch per patch radius).
+// tree_only: the call's set-up and the kd-tree build, nothing after (the
+// tree stays in the workspace for a later call with use_kdtree = 2)
 static ff_status run_batch(const ff_field_job* jobs, int n, const ff_match_params* p, char* ws, const BatchLayout& B,
-                           hipStream_t stream) {
+                           hipStream_t stream, bool tree_only = false) {
   int32_t* status = reinterpret_cast<int32_t*>(ws);
   int32_t* tickets = reinterpret_cast<int32_t*>(ws + B.off_tickets);
   FieldRec* table = reinterpret_cast<FieldRec*>(ws + B.off_table);
@@ -1245,12 +1248,13 @@ static ff_status run_batch(const ff_field_job* jobs, int n, const ff_match_param
   fill_i32(tickets, (size_t)B.launches, 0, stream);
   write_table(recs, n, table, stream);
   k_clear_xch<<<dim3(64, n), 256, 0, stream>>>(table, kMinBandRows);
-  if (p->use_kdtree) {
+  if (p->use_kdtree == 1 || tree_only) {
     prof_mark(FF_PROF_TREE, stream, true);
     ff_status st = enqueue_tree_build(table, n, maxN, maxTop, p->leaf, stream);
     prof_mark(FF_PROF_TREE, stream, false);
     if (st != FF_OK) return st;
   }
+  if (tree_only) return launch_status();
   auto pts = [&](int lev) { return ((maxW + (1 << lev) - 1) >> lev) * ((maxH + (1 << lev) - 1) >> lev); };
   // random search: one workgroup per 256 / kLanesPt consecutive points of a grid row
   auto rs_blocks = [&](int lev) {
@@ -1421,6 +1425,8 @@ size_t ff_match_batch_workspace_bytes(const ff_field_job* jobs, int32_t n_jobs, 
 ff_status ff_match_batch(const ff_field_job* jobs, int32_t n_jobs, const ff_match_params* p, void* workspace,
                          size_t workspace_bytes, hipStream_t stream) {
   if (!jobs || !p || !workspace || n_jobs < 1 || n_jobs > 4096) return FF_ERR_ARG;
+  // a tree left in the workspace by ff_match_field_tree belongs to one field
+  if (p->use_kdtree == 2 && n_jobs != 1) return FF_ERR_ARG;
   for (int i = 0; i < n_jobs; ++i) {
     if (!jobs[i].src || !jobs[i].dst) return FF_ERR_ARG;
     ff_status st = check_job(jobs[i], p);
@@ -1464,6 +1470,21 @@ ff_status ff_match_field(const ff_desc* src, const void* src_blob, const ff_desc
   if (!p) return FF_ERR_ARG;
   const ff_field_job j = single_job(src, src_blob, dst, dst_blob, radius, p, proposal, flow, cost);
   return ff_match_batch(&j, 1, p, workspace, workspace_bytes, stream);
+}
+
+ff_status ff_match_field_tree(const ff_desc* src, const void* src_blob, const ff_desc* dst, const void* dst_blob,
+                              int32_t radius, const ff_match_params* p, void* workspace, size_t workspace_bytes,
+                              hipStream_t stream) {
+  if (!p || !workspace || !p->use_kdtree) return FF_ERR_ARG;
+  ff_status st = check_params(src, dst, radius, p);
+  if (st != FF_OK) return st;
+  const ff_field_job j = single_job(src, src_blob, dst, dst_blob, radius, p, nullptr, nullptr, nullptr);
+  if (!src_blob || !dst_blob) return FF_ERR_ARG;
+  const BatchLayout B = batch_layout(&j, 1, p);
+  if (workspace_bytes < B.bytes) return FF_ERR_WORKSPACE;
+  st = ensure_init();
+  if (st != FF_OK) return st;
+  return run_batch(&j, 1, p, static_cast<char*>(workspace), B, stream, true);
 }
 
 ff_status ff_match_field_noalloc(const ff_desc* src, const void* src_blob, const ff_desc* dst, const void* dst_blob,

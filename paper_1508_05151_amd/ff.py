@@ -139,6 +139,11 @@ def lib():
         L.ff_sift_levels.restype = i32
         L.ff_compute_lab_wht.argtypes = [C.POINTER(ff_desc), C.POINTER(ff_image), P, P, C.c_size_t, P]
         L.ff_compute_lab_wht.restype = i32
+        L.ff_compute_census.argtypes = [C.POINTER(ff_desc), P, C.c_size_t, P]
+        L.ff_compute_census.restype = i32
+        L.ff_match_field_tree.argtypes = [C.POINTER(ff_desc), P, C.POINTER(ff_desc), P, i32,
+                                          C.POINTER(ff_match_params), P, C.c_size_t, P]
+        L.ff_match_field_tree.restype = i32
         L.ff_match_sift_workspace_bytes.argtypes = [C.POINTER(ff_sift_job), i32, C.POINTER(ff_match_params)]
         L.ff_match_sift_workspace_bytes.restype = C.c_size_t
         L.ff_match_sift.argtypes = [C.POINTER(ff_sift_job), i32, C.POINTER(ff_match_params), P, C.c_size_t, P]
@@ -233,6 +238,14 @@ def ff_match_field(src: ff_desc, src_blob, dst: ff_desc, dst_blob, radius: int, 
     _check(lib().ff_match_field(C.byref(src), _ptr(src_blob), C.byref(dst), _ptr(dst_blob), radius, C.byref(p),
                                 _ptr(proposal), _ptr(flow), _ptr(cost), _ptr(workspace), workspace.numel(),
                                 _stream(stream)), "ff_match_field")
+
+
+def ff_match_field_tree(src: ff_desc, src_blob, dst: ff_desc, dst_blob, radius: int, p: ff_match_params, workspace,
+                        stream=None):
+    """The kd-tree of a later ff_match_field call (same arguments and
+    workspace, p.use_kdtree = 2 there) built ahead of it."""
+    _check(lib().ff_match_field_tree(C.byref(src), _ptr(src_blob), C.byref(dst), _ptr(dst_blob), radius, C.byref(p),
+                                     _ptr(workspace), workspace.numel(), _stream(stream)), "ff_match_field_tree")
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -437,6 +450,11 @@ def ff_compute_lab_wht(d: ff_desc, pixels: torch.Tensor, blob: torch.Tensor, str
                                     _stream(stream)), "ff_compute_lab_wht")
 
 
+def ff_compute_census(d: ff_desc, blob: torch.Tensor, stream=None):
+    """Smoothed levels and census planes from the blob's Lab8 planes."""
+    _check(lib().ff_compute_census(C.byref(d), _ptr(blob), blob.numel(), _stream(stream)), "ff_compute_census")
+
+
 def make_sift_job(src: ff_desc, src_blob, dst: ff_desc, dst_blob, src_levels, dst_levels, S, levels_k, radius,
                   flow, cost, field_id=0, pair_id=0, seed=0) -> ff_sift_job:
     _check_i32(flow, src.width * src.height, "flow")
@@ -591,12 +609,15 @@ class PairMatcher:
     one of HIP's four hardware queues with a field and serialise behind it."""
 
     def __init__(self, width, height, channels=3, r=8, r2=6, k=3, subpel=4, eps=5, n_bwd=2, device="cuda",
-                 region_s=None, sparse_e=None, **params):
+                 region_s=None, sparse_e=None, early_trees=True, **params):
         """region_s: None, or s of section 3.4's region filter, which then
         runs after the consistency check (outputs keep_region,
         filtered_region, region_label); sparse_e: None, or e of section
         3.5's sparsification of the region-filtered field (outputs pick,
-        sparse; needs region_s)."""
+        sparse; needs region_s); early_trees: build each field's kd-tree from
+        its target's WHT vectors while the census planes are computed
+        (ff_compute_lab_wht, ff_match_field_tree, ff_compute_census) instead
+        of after whole descriptors; the results are the same."""
         if sparse_e is not None and region_s is None:
             raise ValueError("sparse_e needs region_s (sparsification follows the region filter)")
         self.W, self.H, self.C = width, height, channels
@@ -631,23 +652,54 @@ class PairMatcher:
         # a process four hardware queues by default, and a fifth stream would
         # share one with a field and serialise behind it
         self.streams = [torch.cuda.Stream(device=device) for _ in range(3)]
+        # build each field's kd-tree as soon as its target's WHT vectors exist
+        # (ff_match_field_tree), ahead of the census planes
+        self.early_trees = early_trees
 
     def run(self, img1: torch.Tensor, img2: torch.Tensor, seed: int = 0, pair_id: int = 0, proposal=None):
         """proposal: None, a seed-grid tensor for F, or (forward, backward)
         where the backward proposal serves B1 and B2."""
         main = torch.cuda.current_stream()
-        # the two images' descriptors run concurrently (each is a chain of
-        # small kernels that leaves most of the chip idle); the second image's
-        # go to the last field stream, which waits for both anyway
-        ds = self.streams[len(self.fields) - 1]
-        ds.wait_stream(main)
-        ff_compute_descriptors(self.desc, img2, self.blob2, ds)
-        img2.record_stream(ds)
-        ff_compute_descriptors(self.desc, img1, self.blob1, main)
-        main.wait_stream(ds)
+        fs = self.streams
+        tree_first = self.early_trees and any(self.params[fid].use_kdtree for _, _, fid in self.fields)
+        if tree_first:
+            # the kd-trees start on the WHT vectors (section 3.1) while the
+            # census planes are computed: the second image's Lab8 and WHT on
+            # F's stream (F's tree is over them), the first image's on the
+            # caller's stream, whose census and smoothed levels follow
+            fs[0].wait_stream(main)
+            ff_compute_lab_wht(self.desc, img2, self.blob2, fs[0])
+            img2.record_stream(fs[0])
+            e2 = torch.cuda.Event()
+            e2.record(fs[0])
+            ff_compute_lab_wht(self.desc, img1, self.blob1, main)
+            e1 = torch.cuda.Event()
+            e1.record(main)
+            for (name, rad, fid), ws, s in zip(self.fields, self.ws, fs):
+                p = self.params[fid]
+                if not p.use_kdtree:
+                    continue
+                if name != "F":
+                    s.wait_event(e1)
+                src, sb, dst, db = ((self.desc, self.blob1, self.desc, self.blob2) if name == "F"
+                                    else (self.desc, self.blob2, self.desc, self.blob1))
+                ff_match_field_tree(src, sb, dst, db, rad, p, ws, s)
+            ff_compute_census(self.desc, self.blob1, main)
+            main.wait_event(e2)
+            ff_compute_census(self.desc, self.blob2, main)
+        else:
+            # the two images' descriptors run concurrently (each is a chain of
+            # small kernels that leaves most of the chip idle); the second
+            # image's go to the last field stream, which waits for both anyway
+            ds = fs[len(self.fields) - 1]
+            ds.wait_stream(main)
+            ff_compute_descriptors(self.desc, img2, self.blob2, ds)
+            img2.record_stream(ds)
+            ff_compute_descriptors(self.desc, img1, self.blob1, main)
+            main.wait_stream(ds)
         ev = torch.cuda.Event()
         ev.record(main)
-        for (name, rad, fid), ws, s in zip(self.fields, self.ws, self.streams):
+        for (name, rad, fid), ws, s in zip(self.fields, self.ws, fs):
             s.wait_event(ev)
             p = self.params[fid]
             p.seed = seed
@@ -658,7 +710,14 @@ class PairMatcher:
                 prop = proposal[0] if name == "F" else proposal[1]
             else:
                 prop = proposal if name == "F" else None
-            ff_match_field(src, sb, dst, db, rad, p, prop, self.flow[name], self.cost[name], ws, s)
+            built = tree_first and p.use_kdtree
+            if built:
+                p.use_kdtree = 2   # the tree built above, in this workspace
+            try:
+                ff_match_field(src, sb, dst, db, rad, p, prop, self.flow[name], self.cost[name], ws, s)
+            finally:
+                if built:
+                    p.use_kdtree = 1
         for s in self.streams[:len(self.fields)]:
             e = torch.cuda.Event()
             e.record(s)

@@ -113,6 +113,36 @@ def test_batch_entry_points_validate(ff):
     assert L.ff_match_batch(jobs, 0, C.byref(p), None, 0, None) == -1
 
 
+def test_tree_ahead_entry_points_validate(ff):
+    """use_kdtree is 0, 1 or 2; 2 (the tree left in the workspace by
+    ff_match_field_tree) serves one-field calls only; the tree-only call needs
+    kd-tree seeding, both blobs and a large enough workspace; the census-only
+    call needs a blob of the descriptor's size.  All refused before any
+    launch."""
+    L = ff.lib()
+    d = ff.ff_desc_init(64, 48, 3, 3, 4, (8,))
+    for v in (-1, 3):
+        q = ff.ff_default_params(use_kdtree=v)
+        assert L.ff_match_workspace_bytes(C.byref(d), C.byref(d), 8, C.byref(q)) == 0
+    q2 = ff.ff_default_params(use_kdtree=2)
+    assert L.ff_match_workspace_bytes(C.byref(d), C.byref(d), 8, C.byref(q2)) > 0
+    jobs = (ff.ff_field_job * 2)()
+    for j in jobs:
+        j.src = C.pointer(d)
+        j.dst = C.pointer(d)
+        j.radius = 8
+    fake = C.c_void_p(0x1000)
+    assert L.ff_match_batch(jobs, 2, C.byref(q2), fake, 1 << 30, None) == -1
+    p = ff.ff_default_params()
+    q0 = ff.ff_default_params(use_kdtree=0)
+    assert L.ff_match_field_tree(C.byref(d), fake, C.byref(d), fake, 8, C.byref(q0), fake, 1 << 30, None) == -1
+    assert L.ff_match_field_tree(C.byref(d), None, C.byref(d), fake, 8, C.byref(p), fake, 1 << 30, None) == -1
+    assert L.ff_match_field_tree(C.byref(d), fake, C.byref(d), fake, 6, C.byref(p), fake, 1 << 30, None) == -1
+    assert L.ff_match_field_tree(C.byref(d), fake, C.byref(d), fake, 8, C.byref(p), fake, 16, None) == -3
+    assert L.ff_compute_census(C.byref(d), None, d.bytes, None) == -1
+    assert L.ff_compute_census(C.byref(d), fake, d.bytes - 1, None) == -3
+
+
 def test_desc_init_refuses_layouts_beyond_the_sweeps_32bit_offsets(ff):
     """The sweep addresses the row-major and transposed census planes of a
     level from one base with 32-bit byte offsets; its largest word index is

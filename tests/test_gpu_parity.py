@@ -172,6 +172,56 @@ def test_whole_pair_bit_exact(ff, name, make, k, radii):
         assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
 
 
+def test_tree_ahead_and_split_descriptors_equal_the_whole_calls(ff):
+    """ff_compute_lab_wht followed by ff_compute_census fills every region of
+    a blob as ff_compute_descriptors does; a field seeded from the tree that
+    ff_match_field_tree built ahead (use_kdtree = 2) equals one that builds
+    it in the call; the pair with trees ahead equals the pair after whole
+    descriptors."""
+    p = _ragged_pair(21, 161, 97, nlayers=3)
+    H, W = p.img1.shape[:2]
+    N = W * H
+    i1, i2 = _dev(p.img1), _dev(p.img2)
+    d = ff.ff_desc_init(W, H, 3, 3, Q, (8, 6))
+    whole = torch.zeros(d.bytes, dtype=torch.uint8, device="cuda")
+    split = torch.zeros(d.bytes, dtype=torch.uint8, device="cuda")
+    ff.ff_compute_descriptors(d, i1, whole)
+    ff.ff_compute_lab_wht(d, i1, split)
+    ff.ff_compute_census(d, split)
+    torch.cuda.synchronize()
+    regions = [(d.off_lab, 3 * N), (d.off_smooth, 4 * 3 * N * 2), (d.off_census, 4 * Q * Q * N * 4),
+               (d.off_census_t, 4 * Q * Q * N * 4), (d.off_wht, 2 * N * 32 * 4)]
+    for off, nb in regions:
+        assert torch.equal(whole[off:off + nb], split[off:off + nb]), off
+    # one field, tree built ahead vs in the call
+    d2 = ff.ff_desc_init(W, H, 3, 3, Q, (8, 6))
+    b2 = torch.empty(d2.bytes, dtype=torch.uint8, device="cuda")
+    ff.ff_compute_descriptors(d2, i2, b2)
+    outs = []
+    for mode in (1, 2):
+        prm = ff.ff_default_params(seed=5, field_id=0)
+        ws = torch.empty(ff.ff_match_workspace_bytes(d, d2, 8, prm), dtype=torch.uint8, device="cuda")
+        flow = torch.empty((H, W), dtype=torch.int32, device="cuda")
+        cost = torch.empty_like(flow)
+        if mode == 2:
+            ff.ff_match_field_tree(d, whole, d2, b2, 8, prm, ws)
+            prm.use_kdtree = 2
+        ff.ff_match_field(d, whole, d2, b2, 8, prm, None, flow, cost, ws)
+        torch.cuda.synchronize()
+        outs.append((flow.cpu(), cost.cpu()))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    # the whole pair both ways
+    res = []
+    for early in (False, True):
+        m = ff.PairMatcher(W, H, 3, r=8, r2=6, k=3, subpel=Q, eps=5, early_trees=early)
+        o = m.run(i1, i2, seed=77, pair_id=1)
+        torch.cuda.synchronize()
+        assert m.status() == [0] * len(m.fields)
+        res.append({k: v.cpu().clone() for k, v in o.items() if v is not None})
+    for key in res[0]:
+        assert torch.equal(res[0][key], res[1][key]), key
+
+
 def test_proposal_paths(ff):
     p = pairs.square_pair(2)
     k, r = 3, 8
