@@ -8,7 +8,8 @@
 // matters (leaves are finally sorted by pixel index), so the order inside a
 // node is free.
 //  * Top levels (nodes larger than kTreeLds points): level-synchronous passes
-//    over all nodes of a level at once --
+//    over all nodes of a level at once (down to kNodeMax points per node;
+//    below that, one workgroup per node does a level in one launch) --
 //      minmax    per-node per-dimension min/max (order-free atomics), a pass
 //                of its own for the root only,
 //      hist x4   MSD radix select of the rank floor(cnt/2) element of the
@@ -446,6 +447,193 @@ __global__ __launch_bounds__(kTpb) void k_tree_partition(const FieldRec* __restr
   }
 }
 
+// ---------------------------------------------------------------- one workgroup per node
+// Levels whose nodes hold at most kNodeMax points: one 1024-thread workgroup
+// per node does the whole level in one launch -- the node's ids and split
+// keys stay in registers (EPT per thread), the four radix-select passes bin
+// them into an LDS histogram, the partition is a workgroup scan (no global
+// atomics, so the children's order is fixed too), and the children's
+// min/max are reduced over the partitioned ids listed in LDS.  The pivot,
+// and so the tree, is the one the global passes select.
+constexpr int kNodeTpb = 1024;
+constexpr int kNodeMax = 16 * kNodeTpb;   // measured: 32 K (level 4 at 1024x436) slower, 8 K no better
+
+// exclusive prefix of v over the workgroup (kNodeTpb threads) and the total;
+// two barriers; `wt` holds kNodeTpb / 64 ints of LDS
+__device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t* wt, int32_t& total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int32_t incl = wave_incl_scan(v);
+  if (lane == 63) wt[wv] = incl;
+  __syncthreads();
+  int32_t off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kNodeTpb / 64; ++w) {
+    const int32_t x = wt[w];
+    if (w < wv) off += x;
+    tot += x;
+  }
+  __syncthreads();
+  total = tot;
+  return off + incl - v;
+}
+
+template <int EPT>
+__global__ __launch_bounds__(kNodeTpb) void k_tree_node(const FieldRec* __restrict__ table, int d) {
+  extern __shared__ __align__(16) int32_t node_lds[];   // [kSelBins] histogram, then the side-ordered ids
+  __shared__ int32_t s_wt[kNodeTpb / 64];
+  __shared__ int32_t s_bin, s_before;
+  __shared__ int32_t cmin[2][32], cmax[2][32];
+  const TreeView t = tree_view(table[blockIdx.y]);
+  if (d >= t.top) return;
+  const int j = blockIdx.x;
+  if (j >= (1 << d)) return;
+  int start, cnt;
+  node_range(d, j, t.N, start, cnt);
+  const int32_t* perm = (d & 1) ? t.perm2 : t.perm;
+  int32_t* out = (d & 1) ? t.perm : t.perm2;
+  const int node = (1 << d) - 1 + j;
+  int dim;
+  int32_t mn;
+  node_split_dim(t.mm, node, t.D, dim, mn);
+  int32_t* hist = node_lds;
+  int32_t* sids = node_lds + kSelBins;
+  // ids and split keys of the node, all loads issued first
+  int ids[EPT];
+  uint32_t kv[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kNodeTpb;
+    ids[i] = e < cnt ? perm[start + e] : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kNodeTpb;
+    kv[i] = e < cnt ? (uint32_t)(t.V[(size_t)ids[i] * t.stride + dim] - mn) : 0u;
+  }
+  // MSD radix select of rank cnt / 2 of the 44-bit key (key << 22 | pixel)
+  uint64_t prefix = 0;
+  int rank = cnt >> 1;
+  for (int pass = 0; pass < kSelPasses; ++pass) {
+    const int shift = 33 - 11 * pass;
+    for (int i = threadIdx.x; i < kSelBins; i += kNodeTpb) hist[i] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + i * kNodeTpb;
+      const uint64_t ck = ((uint64_t)kv[i] << 22) | (uint64_t)ids[i];
+      if (e < cnt && (ck >> (shift + 11)) == prefix) atomicAdd(&hist[(ck >> shift) & (kSelBins - 1)], 1);
+    }
+    __syncthreads();
+    // thread t owns bins 2t and 2t + 1
+    static_assert(kSelBins == 2 * kNodeTpb, "two bins per thread");
+    const int32_t b0 = hist[2 * threadIdx.x], b1 = hist[2 * threadIdx.x + 1];
+    int32_t tot;
+    const int32_t excl = block_excl_scan(b0 + b1, s_wt, tot);
+    if (rank >= excl && rank < excl + b0 + b1) {
+      const bool first = rank < excl + b0;
+      s_bin = 2 * threadIdx.x + (first ? 0 : 1);
+      s_before = first ? excl : excl + b0;
+    }
+    __syncthreads();
+    prefix = (prefix << 11) | (uint64_t)s_bin;
+    rank -= s_before;
+    __syncthreads();
+  }
+  const uint64_t pivot = prefix;
+  if (threadIdx.x == 0) {
+    t.dim[node] = dim;
+    t.split[node] = (int32_t)(pivot >> 22) + mn;
+  }
+  // partition: the left points (key below the pivot) first, in a fixed order
+  uint32_t leftmask = 0;
+  int nl = 0, nv = 0;
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kNodeTpb;
+    if (e < cnt) {
+      const uint64_t ck = ((uint64_t)kv[i] << 22) | (uint64_t)ids[i];
+      if (ck < pivot) { leftmask |= 1u << i; ++nl; }
+      ++nv;
+    }
+  }
+  int32_t totL, totR;
+  int pl = block_excl_scan(nl, s_wt, totL);
+  int pr = block_excl_scan(nv - nl, s_wt, totR);
+  const int h = cnt >> 1;
+  const bool kids = d + 1 < t.top;
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kNodeTpb;
+    if (e < cnt) {
+      if ((leftmask >> i) & 1) {
+        if (pl < h) {
+          out[start + pl] = ids[i];
+          if (kids) sids[pl] = ids[i];
+        }
+        ++pl;
+      } else {
+        if (pr < cnt - h) {
+          out[start + h + pr] = ids[i];
+          if (kids) sids[h + pr] = ids[i];
+        }
+        ++pr;
+      }
+    }
+  }
+  if (!kids) return;
+  // the children's per-dimension min/max over the listed ids (left: [0, h),
+  // right: [h, cnt)); rows read whole by groups of 8 lanes
+  if (threadIdx.x < 64) {
+    cmin[threadIdx.x >> 5][threadIdx.x & 31] = INT32_MAX;
+    cmax[threadIdx.x >> 5][threadIdx.x & 31] = INT32_MIN;
+  }
+  __syncthreads();
+  const int g = threadIdx.x / kLpr, q = threadIdx.x % kLpr;
+  const bool on = 4 * q < t.D;
+  int mnL[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX}, mxL[4] = {INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN};
+  int mnR[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX}, mxR[4] = {INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN};
+  if (on) {
+#pragma unroll 8
+    for (int e = g; e < cnt; e += kNodeTpb / kLpr) {
+      const v4i_t v = row_quad(t.V, t.stride, sids[e], q);
+      const int vv[4] = {v.x, v.y, v.z, v.w};
+      const bool left = e < h;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        mnL[i] = left ? min(mnL[i], vv[i]) : mnL[i];
+        mxL[i] = left ? max(mxL[i], vv[i]) : mxL[i];
+        mnR[i] = left ? mnR[i] : min(mnR[i], vv[i]);
+        mxR[i] = left ? mxR[i] : max(mxR[i], vv[i]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    for (int o = kLpr; o < 64; o <<= 1) {
+      mnL[i] = min(mnL[i], __shfl_xor(mnL[i], o));
+      mxL[i] = max(mxL[i], __shfl_xor(mxL[i], o));
+      mnR[i] = min(mnR[i], __shfl_xor(mnR[i], o));
+      mxR[i] = max(mxR[i], __shfl_xor(mxR[i], o));
+    }
+  if ((threadIdx.x & 63) < kLpr && on) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (4 * q + i < t.D) {
+        atomicMin(&cmin[0][4 * q + i], mnL[i]);
+        atomicMax(&cmax[0][4 * q + i], mxL[i]);
+        atomicMin(&cmin[1][4 * q + i], mnR[i]);
+        atomicMax(&cmax[1][4 * q + i], mxR[i]);
+      }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < 2 * t.D) {
+    const int side = threadIdx.x >= t.D ? 1 : 0, k = threadIdx.x - side * t.D;
+    const size_t child = (size_t)2 * node + 1 + side;
+    t.mm[(child * 32 + k) * 2] = cmin[side][k];
+    t.mm[(child * 32 + k) * 2 + 1] = cmax[side][k];
+  }
+}
+
 // ---------------------------------------------------------------- subtrees in LDS
 constexpr int kSubTpb = 512;
 
@@ -695,6 +883,14 @@ ff_status enqueue_tree_build(const FieldRec* table, int nf, int maxN, int maxTop
     // below the root the previous level's partition has reduced each
     // node's minimum and maximum
     if (d == 0) k_tree_minmax<<<grid, kTpb, 0, stream>>>(table, d);
+    if (maxcnt <= kNodeMax) {
+      const size_t lds = (size_t)(kSelBins + maxcnt) * 4;
+      const dim3 ng(1 << d, nf);
+      if (maxcnt <= 4 * kNodeTpb) k_tree_node<4><<<ng, kNodeTpb, lds, stream>>>(table, d);
+      else if (maxcnt <= 8 * kNodeTpb) k_tree_node<8><<<ng, kNodeTpb, lds, stream>>>(table, d);
+      else k_tree_node<16><<<ng, kNodeTpb, lds, stream>>>(table, d);
+      continue;
+    }
     for (int p = 0; p < kSelPasses; ++p) k_tree_hist<<<grid, kTpb, 0, stream>>>(table, d, p);
     k_tree_partition<<<grid, kTpb, 0, stream>>>(table, d);
   }
