@@ -509,7 +509,15 @@ def kernel_table(ff, run, torch, W, H, C, img=None):
     for c in classes:
         ms, per = t[c]
         row = {"avg_launch_ms": round(ms, 4), "launches_per_step": round(per, 2)}
-        if per == 0:
+        if per == 0 and c == "descriptors":
+            row["note"] = ("in the step the descriptors are two calls per image, Lab8 + WHT and then levels + "
+                           "census, with the kd-trees started between them: see the lab, smooth, census and wht "
+                           "rows; the whole call is timed alone")
+            if c in alone:
+                gba = ab[c] / (alone[c][0] / 1000.0) / 1e9
+                row.update(bound="hbm", algorithmic_bytes=ab[c], alone_ms=round(alone[c][0], 4),
+                           alone_GBps=round(gba, 1), alone_frac=round(gba / HBM_PEAK_GBS, 4))
+        elif per == 0:
             row["note"] = "no launch of its own: runs inside the pipelined sweep launches"
         elif c in ab:
             gbs = ab[c] / (ms / 1000.0) / 1e9
