@@ -446,10 +446,7 @@ __global__ __launch_bounds__(256) void k_census(const int16_t* __restrict__ Sall
 // run combinations of every window row and tile column to LDS as int16
 // (|w| <= (2 rho + 1) 255), and each thread combines vertical runs of those
 // into the 9 C values of its pixels, written as one 128-byte row per pixel.
-#ifndef WHT_TW
-#define WHT_TW 32
-#endif
-constexpr int kWhtTW = WHT_TW, kWhtTH = 16;
+constexpr int kWhtTW = 32, kWhtTH = 16;         // 64-wide tiles measured 19 % slower (half the workgroups)
 constexpr int kWhtG = 256 / kWhtTW;            // thread groups (one per tile column set)
 constexpr int kWhtRPT = kWhtTH / kWhtG;        // output rows per thread
 
