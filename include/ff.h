@@ -94,7 +94,9 @@ typedef struct {
   int32_t use_kdtree; /* 1: kd-tree seeds (Eq. 1 / Eq. 4), the tree built in the
                          call; 2: kd-tree seeds from the tree that
                          ff_match_field_tree left in the same workspace for
-                         the same field and arguments (one-field calls only);
+                         the same field and arguments (ff_match_field, or
+                         ff_match_batch with one job; refused by
+                         ff_match_field_noalloc and ff_match_sift);
                          0: proposal only */
   int32_t max_steps;  /* < 0: whole search; else stop after this many steps
                          (1 seed step, 7 at the coarsest level, 8 per finer

@@ -1490,7 +1490,8 @@ ff_status ff_match_field_tree(const ff_desc* src, const void* src_blob, const ff
 ff_status ff_match_field_noalloc(const ff_desc* src, const void* src_blob, const ff_desc* dst, const void* dst_blob,
                                  int32_t radius, const ff_match_params* p, const int32_t* proposal, int32_t* flow,
                                  int32_t* cost, int32_t* status, hipStream_t stream) {
-  if (!p) return FF_ERR_ARG;
+  // the library's scratch never holds a tree built ahead by ff_match_field_tree
+  if (!p || p->use_kdtree == 2) return FF_ERR_ARG;
   ff_status st = check_params(src, dst, radius, p);
   if (st != FF_OK) return st;
   const ff_field_job j = single_job(src, src_blob, dst, dst_blob, radius, p, proposal, flow, cost);

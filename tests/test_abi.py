@@ -219,3 +219,8 @@ def test_noalloc_entry_refuses_before_any_launch(ff):
     assert L.ff_match_field_noalloc(C.byref(ok), None, C.byref(ok), None, 6, C.byref(p), None, None, None, None,
                                     None) == -1
     assert L.ff_match_field_noalloc(None, None, None, None, 8, None, None, None, None, None, None) == -1
+    # its scratch never holds a tree built ahead
+    q2 = ff.ff_default_params(use_kdtree=2)
+    fake = C.c_void_p(0x1000)
+    assert L.ff_match_field_noalloc(C.byref(ok), fake, C.byref(ok), fake, 8, C.byref(q2), None, fake, fake, None,
+                                    None) == -1
