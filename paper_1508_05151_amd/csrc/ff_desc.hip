@@ -457,24 +457,6 @@ size_t wht_lds_bytes(int C, int rho) {
   return align_up((size_t)C * wht_rows(rho) * wht_cols(rho), 16) + (size_t)C * 3 * wht_rows(rho) * kWhtTW * 2;
 }
 
-// the run sums of 2 RHO + 1 samples p[0], p[st], ..., combined into w0..w2
-template <int RHO, typename T>
-__device__ __forceinline__ void walsh_three(const T* p, int st, int32_t& w0, int32_t& w1, int32_t& w2) {
-  constexpr int a1 = RHO / 2, m = RHO, c1 = (RHO + 1) / 2;
-  int32_t A = 0, B = 0, Cs = 0, D = 0;
-#pragma unroll
-  for (int k = 0; k <= 2 * RHO; ++k) {
-    const int32_t v = p[k * st];
-    if (k < a1) A += v;
-    else if (k < m) B += v;
-    else if (k < m + c1) Cs += v;
-    else D += v;
-  }
-  w0 = A + B + Cs + D;
-  w1 = A + B - Cs - D;
-  w2 = A - B - Cs + D;
-}
-
 template <int RHO>
 __global__ __launch_bounds__(256) void k_wht(const uint8_t* __restrict__ J, int W, int H, int C, int stride,
                                              int32_t* __restrict__ V) {
@@ -492,15 +474,38 @@ __global__ __launch_bounds__(256) void k_wht(const uint8_t* __restrict__ J, int 
     for (int xx = lane; xx < CW; xx += kWhtTW) jt[r * CW + xx] = src[clampi(x0 - RHO + xx, 0, W - 1)];
   }
   __syncthreads();
-  // horizontal runs of every window row at tile column `lane`
-  for (int r = grp; r < C * R; r += kWhtG) {
-    int32_t w0, w1, w2;
-    walsh_three<RHO>(jt + r * CW + lane, 1, w0, w1, w2);
+  // horizontal runs of every window row: a task is kWhtHS consecutive tile
+  // columns of one row, summed at its first column and slid one column at a
+  // time (each run loses its first sample and gains the one after its last)
+  constexpr int kWhtHS = 4, kSegs = kWhtTW / kWhtHS;
+  for (int task = threadIdx.x; task < C * R * kSegs; task += 256) {
+    const int r = task / kSegs, x0s = (task - r * kSegs) * kWhtHS;
+    const uint8_t* row = jt + r * CW + x0s;
+    int32_t A = 0, B = 0, Cs = 0, D = 0;
+#pragma unroll
+    for (int k = 0; k <= 2 * RHO; ++k) {
+      const int32_t v = row[k];
+      if (k < a1) A += v;
+      else if (k < m) B += v;
+      else if (k < m + c1) Cs += v;
+      else D += v;
+    }
     const int c = r / R, yy = r - c * R;
-    int16_t* h = hb + ((size_t)c * 3 * R + yy) * kWhtTW + lane;
-    h[0] = (int16_t)w0;
-    h[R * kWhtTW] = (int16_t)w1;
-    h[2 * R * kWhtTW] = (int16_t)w2;
+    int16_t* h = hb + ((size_t)c * 3 * R + yy) * kWhtTW + x0s;
+#pragma unroll
+    for (int j = 0; j < kWhtHS; ++j) {
+      if (j > 0) {
+        const int32_t v0 = row[j - 1], va = row[j - 1 + a1], vm = row[j - 1 + m];
+        const int32_t vc = row[j - 1 + m + c1], ve = row[j + 2 * RHO];
+        A += va - v0;
+        B += vm - va;
+        Cs += vc - vm;
+        D += ve - vc;
+      }
+      h[j] = (int16_t)(A + B + Cs + D);
+      h[R * kWhtTW + j] = (int16_t)(A + B - Cs - D);
+      h[2 * R * kWhtTW + j] = (int16_t)(A - B - Cs + D);
+    }
   }
   __syncthreads();
   // vertical runs: thread (lane, grp) owns column lane and kWhtRPT rows from
