@@ -315,11 +315,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-reps", type=int, default=3, help="CPU baseline: oracle runs (side by side)")
-    ap.add_argument("--mode", default="pair", choices=("pair", "batch", "outliers", "ablation", "sift"),
+    ap.add_argument("--mode", default="pair", choices=("pair", "batch", "outliers", "ablation", "sift", "frontier"),
                     help="pair: one 1024x436 pair (headline, with every secondary block); batch: 64 mixed-size "
                          "pairs in one batched call alone; outliers: removed outliers vs removed inliers of the "
                          "filters over epsilon; ablation: the measures of Table 1 over k, l, R and the fast "
-                         "variant; sift: the SIFT-flow data term path alone (KITTI setting)")
+                         "variant; sift: the SIFT-flow data term path alone (KITTI setting); frontier: "
+                         "throughput against inlier rate over the kd-tree leaf size, with and without the "
+                         "learned proposal")
     ap.add_argument("--pairs", type=int, default=64, help="batch block: number of mixed-size pairs")
     ap.add_argument("--gen-workers", type=int, default=16,
                     help="processes drawing the synthetic pairs (0 = in-process; use 0 under a profiler)")
@@ -365,7 +367,7 @@ def main():
     if args.mode == "batch" or (args.mode == "pair" and not args.no_batch):
         batch_pairs = (pairs.mixed_pairs_parallel(args.pairs, workers=args.gen_workers) if args.gen_workers > 0
                        else pairs.mixed_pairs(args.pairs))
-    if args.mode == "pair" and not args.no_learned:
+    if args.mode == "frontier" or (args.mode == "pair" and not args.no_learned):
         eval_pairs = pairs.layered_pairs(LEARNED_SEED0, args.learned_pairs, workers=args.gen_workers)
     pair = pairs.layered_pair(HEADLINE_SEED)
     skewed = pairs.layered_pair(HEADLINE_SEED, motion="skewed") if args.mode == "pair" else None
@@ -392,6 +394,8 @@ def main():
         return bench_outliers(args, ff, outlier_pairs, torch, dev)
     if args.mode == "ablation":
         return bench_ablation(args, ff, outlier_pairs, torch, dev)
+    if args.mode == "frontier":
+        return bench_frontier(args, ff, pair, eval_pairs, torch, dev)
     if args.mode == "sift":
         res = bench_sift(ff, torch, dev, sift_workloads, args.steps)
         d = res["driving_1242x375_gray"]
@@ -633,6 +637,65 @@ def bench_learned(ff, pair, img1, img2, eval_pairs, torch, dev, plain_value, pla
                        for m in ("plain", "plain+learned", "learned")},
                     "network_alone_at_seed_points": round(ev["network_only_seed_points"], 4)}
     return res
+
+
+FRONTIER = (("plain", 8), ("plain", 4), ("plain", 16), ("plain", 32), ("plain", 64), ("plain+learned", 4),
+            ("plain+learned", 8), ("plain+learned", 16), ("plain+learned", 32), ("plain+learned", 64),
+            ("learned", 8))
+
+
+def bench_frontier(args, ff, pair, eval_pairs, torch, dev, steps=10):
+    """The learned proposal as a trade: for each kd-tree leaf size l (a
+    larger leaf: a shallower tree, more seed candidates per point) with and
+    without the network's candidate, and the network alone (no tree), the
+    whole step's throughput on the benchmark pair (network forward inside the
+    timed region where used) and the EPE < 3 px rate of F over the benchmark
+    pair and the held-out pairs (seeds 4000..), each matched on its own."""
+    from paper_1508_05151_amd import proposal
+    from synth import pairs
+    net = proposal.load(WEIGHTS)
+    H, W = pair.img1.shape[:2]
+    held = [pair] + list(eval_pairs)
+    imgs = [(torch.from_numpy(p.img1).to(dev), torch.from_numpy(p.img2).to(dev)) for p in held]
+    rows = []
+    for mode, leaf in FRONTIER:
+        m = ff.PairMatcher(W, H, 3, r=R, r2=R2, k=K, subpel=Q, eps=EPS, leaf=leaf,
+                           use_kdtree=0 if mode == "learned" else 1)
+
+        def once(i1, i2, seed):
+            prop = None
+            if mode != "plain":
+                pf, pb = proposal.proposals_both_ways(net, i1.unsqueeze(0), i2.unsqueeze(0))
+                prop = (pf[0], pb[0])
+            return m.run(i1, i2, seed=seed, proposal=prop)
+
+        i1, i2 = imgs[0]
+        once(i1, i2, HEADLINE_SEED)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            once(i1, i2, HEADLINE_SEED)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / steps
+        rates = []
+        for p, (a, b) in zip(held, imgs):
+            out = once(a, b, p.seed)
+            rates.append(pairs.inlier_rate(out["F"].cpu().numpy(), p, Q))
+        assert m.status() == [0, 0, 0], m.status()
+        rows.append({"mode": mode, "leaf": leaf, "ms_per_pair": round(ms, 4),
+                     "Mpixel_per_s": round(W * H / ms / 1e3, 3), "inlier_F_benchmark_pair": round(rates[0], 4),
+                     "inlier_F_mean": round(float(sum(rates) / len(rates)), 4)})
+        del m
+    base = rows[0]
+    line = {"metric": "learned-proposal frontier: whole-step Mpixel/s against the EPE < 3 px rate of F",
+            "unit": "Mpixel/s", "n_gpus": 1, "steps": steps, "dtype": "int32 (network bf16)", "data": "synthetic",
+            "config": {"workload": f"the benchmark pair (seed {HEADLINE_SEED}) timed; the rate over it and "
+                                   f"{len(eval_pairs)} held-out layered 1024x436 pairs (seeds {LEARNED_SEED0}..)",
+                       "k": K, "r": R, "r2": R2, "subpel": Q, "eps": EPS},
+            "rows": rows,
+            "dominating_plain_l8": [r for r in rows[1:] if r["Mpixel_per_s"] > base["Mpixel_per_s"]
+                                    and r["inlier_F_mean"] >= base["inlier_F_mean"]]}
+    print(json.dumps(line), flush=True)
 
 
 NET_LAYERS = ((6, 32, 2, 1), (32, 32, 2, 1), (32, 32, 2, 1), (32, 32, 1, 4), (32, 32, 1, 8), (32, 2, 1, 1))

@@ -273,7 +273,8 @@ def test_subpel_variants_bit_exact(ff, subpel):
 
 @pytest.mark.parametrize("R,n_prop,n_rs,k,leaf", [(2, 4, 3, 3, 8), (1, 2, 1, 3, 8), (3, 6, 6, 2, 4),
                                                   (1, 4, 0, 3, 16), (1, 1, 1, 0, 8), (1, 8, 5, 2, 8),
-                                                  (1, 4, 3, 0, 8), (1, 4, 3, 1, 8), (1, 4, 3, 3, 4)])
+                                                  (1, 4, 3, 0, 8), (1, 4, 3, 1, 8), (1, 4, 3, 3, 4),
+                                                  (1, 4, 3, 3, 32), (1, 4, 3, 3, 64)])
 def test_search_parameter_variants_bit_exact(ff, R, n_prop, n_rs, k, leaf):
     """Random-search radius multiplier, number of propagation sweeps and
     random searches per level, hierarchy depth (k = 0: no hierarchy) and
