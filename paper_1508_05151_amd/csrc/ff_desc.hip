@@ -458,8 +458,8 @@ size_t wht_lds_bytes(int C, int rho) {
 }
 
 template <int RHO>
-__global__ __launch_bounds__(256) void k_wht(const uint8_t* __restrict__ J, int W, int H, int C, int stride,
-                                             int32_t* __restrict__ V) {
+__device__ __forceinline__ void wht_tile(const uint8_t* __restrict__ J, int W, int H, int C, int stride,
+                                         int32_t* __restrict__ V) {
   constexpr int R = wht_rows(RHO), CW = wht_cols(RHO);
   constexpr int a1 = RHO / 2, m = RHO, c1 = (RHO + 1) / 2;
   extern __shared__ __align__(16) unsigned char wht_lds[];
@@ -591,14 +591,44 @@ __global__ __launch_bounds__(256) void k_wht(const uint8_t* __restrict__ J, int 
 }
 
 template <int RHO>
+__global__ __launch_bounds__(256) void k_wht(const uint8_t* __restrict__ J, int W, int H, int C, int stride,
+                                             int32_t* __restrict__ V) {
+  wht_tile<RHO>(J, W, H, C, stride, V);
+}
+
+// Both radii of a descriptor in one launch (grid z = radius): each radius
+// alone leaves most of the chip idle (its tiles are short chains of loads,
+// two barriers and stores), side by side they overlap.
+template <int RA, int RB>
+__global__ __launch_bounds__(256) void k_wht2(const uint8_t* __restrict__ J, int W, int H, int C, int stride,
+                                              int32_t* __restrict__ VA, int32_t* __restrict__ VB) {
+  if (blockIdx.z == 0) wht_tile<RA>(J, W, H, C, stride, VA);
+  else wht_tile<RB>(J, W, H, C, stride, VB);
+}
+
+template <int RHO>
 static void launch_wht(const ff_desc* d, const uint8_t* lab, int32_t* V, hipStream_t stream) {
   const dim3 grid((d->width + kWhtTW - 1) / kWhtTW, (d->height + kWhtTH - 1) / kWhtTH);
   k_wht<RHO><<<grid, 256, wht_lds_bytes(d->channels, RHO), stream>>>(lab, d->width, d->height, d->channels,
                                                                       d->wht_stride, V);
 }
 
+template <int RA, int RB>
+static void launch_wht2(const ff_desc* d, const uint8_t* lab, int32_t* VA, int32_t* VB, hipStream_t stream) {
+  const dim3 grid((d->width + kWhtTW - 1) / kWhtTW, (d->height + kWhtTH - 1) / kWhtTH, 2);
+  const size_t lds = std::max(wht_lds_bytes(d->channels, RA), wht_lds_bytes(d->channels, RB));
+  k_wht2<RA, RB><<<grid, 256, lds, stream>>>(lab, d->width, d->height, d->channels, d->wht_stride, VA, VB);
+}
+
 static void enqueue_wht(const ff_desc* d, const uint8_t* lab, char* base, hipStream_t stream) {
   static_assert(kMaxRadius == 15, "one instance per radius");
+  if (d->n_radii == 2) {
+    // the radius pairs of the paper's two settings (r, r2) = (8, 6) and (3, 2)
+    int32_t* V0 = reinterpret_cast<int32_t*>(base + d->off_wht);
+    int32_t* V1 = V0 + (size_t)d->width * d->height * d->wht_stride;
+    if (d->radii[0] == 8 && d->radii[1] == 6) return launch_wht2<8, 6>(d, lab, V0, V1, stream);
+    if (d->radii[0] == 3 && d->radii[1] == 2) return launch_wht2<3, 2>(d, lab, V0, V1, stream);
+  }
   for (int i = 0; i < d->n_radii; ++i) {
     int32_t* V = reinterpret_cast<int32_t*>(base + d->off_wht) + (size_t)i * d->width * d->height * d->wht_stride;
     switch (d->radii[i]) {
