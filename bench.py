@@ -39,7 +39,7 @@ INT_PEAK_TOPS = CUS * LANES_PER_CU * CLOCK_GHZ / 1000.0   # 32-bit integer VALU 
 # counter runs scaled by a plain-copy calibration; the counter runs are
 # summarised in profiles/hotpath_1024x436_hbm_counters.md.  Valid for the
 # k_propagate the summary names only.
-PROPAGATE_HBM_BYTES_PER_LAUNCH = 72.65e6
+PROPAGATE_HBM_BYTES_PER_LAUNCH = 74.38e6
 
 K, R, R2, Q, EPS, LEAF = 3, 8, 6, 4, 5, 8
 SPARSE_S, SPARSE_E = 50, 4            # section 4: s and e for Sintel
