@@ -25,59 +25,68 @@ __device__ uint16_t g_fcurve[65537];
 // (index log2 n - 1), phase x mod n, tap -3..3 around floor(x/n).
 __constant__ int32_t c_lanczos[4][16][7];
 
-static void host_lab_tables(int32_t* gamma, int32_t* mat, uint16_t* fcurve) {
-  for (int c = 0; c < 256; ++c) {
-    const double v = (double)c / 255.0;
-    double lin;
-    if (v <= 0.04045)
-      lin = v / 12.92;
-    else
-      lin = pow((v + 0.055) / 1.055, 2.4);
-    gamma[c] = (int32_t)floor(lin * 65536.0 + 0.5);
+// The tables are computed on the device, in fp64, by the kernels below (one
+// thread per entry; a matrix row and a Lanczos phase each need their own sum,
+// so they take one thread per row).  Every entry is at least 2.4e-6 away
+// from a rounding tie, far more than the few ulps by which device and host
+// fp64 functions may differ, so the rounded tables are exact.
+__device__ int32_t g_lanczos_stage[4][16][7];   // copied to the constant table
+
+__global__ void k_lab_tables() {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= 65536) {
+    // CIE companding f over t in [0, 1] (Q16 in, Q15 out): a cube root above
+    // delta^3, its tangent line through 4/29 below, delta = 6/29
+    const double delta = 6.0 / 29.0, t = (double)i / 65536.0;
+    const double f = t > delta * delta * delta ? cbrt(t) : t / (3.0 * delta * delta) + 4.0 / 29.0;
+    g_fcurve[i] = (uint16_t)floor(32768.0 * f + 0.5);
   }
-  static const double rgb2xyz[9] = {0.4124564, 0.3575761, 0.1804375, 0.2126729, 0.7151522,
-                                    0.0721750, 0.0193339, 0.1191920, 0.9503041};
-  for (int row = 0; row < 3; ++row) {
-    const double* m = rgb2xyz + 3 * row;
-    const double total = m[0] + m[1] + m[2];
-    int largest = 0, acc = 0;
+  if (i < 256) {
+    // the sRGB transfer function inverted: 8-bit code -> linear, Q16
+    const double e = (double)i / 255.0;
+    const double lin = e > 0.04045 ? pow((e + 0.055) / 1.055, 2.4) : e / 12.92;
+    g_gamma[i] = (int32_t)floor(65536.0 * lin + 0.5);
+  }
+  if (i < 3) {
+    // linear sRGB -> XYZ (D65), each row divided by its sum (the white
+    // point) and taken to Q14; the row's rounding residual goes to its
+    // largest entry, so every row sums to exactly 2^14
+    const double M[3][3] = {{0.4124564, 0.3575761, 0.1804375},
+                            {0.2126729, 0.7151522, 0.0721750},
+                            {0.0193339, 0.1191920, 0.9503041}};
+    const double w = M[i][0] + M[i][1] + M[i][2];
+    int32_t q[3];
+    int top = 0;
     for (int j = 0; j < 3; ++j) {
-      mat[3 * row + j] = (int32_t)floor(16384.0 * m[j] / total + 0.5);
-      acc += mat[3 * row + j];
-      if (m[j] > m[largest]) largest = j;
+      q[j] = (int32_t)floor(16384.0 * (M[i][j] / w) + 0.5);
+      top = M[i][j] > M[i][top] ? j : top;
     }
-    mat[3 * row + largest] += 16384 - acc;
-  }
-  const double toe = 216.0 / 24389.0;
-  for (int t = 0; t <= 65536; ++t) {
-    const double x = (double)t / 65536.0;
-    const double f = x > toe ? cbrt(x) : x * (841.0 / 108.0) + 4.0 / 29.0;
-    fcurve[t] = (uint16_t)(int32_t)floor(f * 32768.0 + 0.5);
+    q[top] += 16384 - q[0] - q[1] - q[2];
+    for (int j = 0; j < 3; ++j) g_mat[3 * i + j] = q[j];
   }
 }
 
-static void host_lanczos(int32_t (*w)[16][7]) {
-  const double pi = 3.14159265358979323846;
-  for (int li = 0; li < 4; ++li) {
-    const int n = 2 << li;
-    for (int ph = 0; ph < 16; ++ph)
-      for (int k = 0; k < 7; ++k) w[li][ph][k] = 0;
-    for (int ph = 0; ph < n; ++ph) {
-      const double centre = (ph + 0.5) / n - 0.5;
-      int sum = 0;
-      for (int k = -3; k <= 3; ++k) {
-        const double x = centre - k;
-        double L = 0.0;
-        if (x == 0.0)
-          L = 1.0;
-        else if (fabs(x) < 3.0)
-          L = 3.0 * sin(pi * x) * sin(pi * x / 3.0) / (pi * pi * x * x);
-        w[li][ph][k + 3] = (int32_t)floor(16384.0 * L + 0.5);
-        sum += w[li][ph][k + 3];
-      }
-      w[li][ph][3] += 16384 - sum;
+// Lanczos-3 weights (sinc(x) sinc(x / 3) on |x| < 3) for the upsampling of
+// section 3.2, per scale n = 2 << li and phase ph < n: output pixel x of
+// phase ph sits at u = (ph + 1/2) / n - 1/2 on the coarse grid, taps
+// k = -3..3 around floor(x / n); Q14, the rounding residual on the centre tap
+// (each phase sums to exactly 2^14).  One thread per (scale, phase).
+__global__ void k_lanczos_table() {
+  const int li = blockIdx.x, ph = threadIdx.x, n = 2 << li;
+  if (ph >= 16) return;
+  int32_t sum = 0;
+  for (int k = -3; k <= 3; ++k) {
+    int32_t wq = 0;
+    if (ph < n) {
+      const double x = (ph + 0.5) / n - 0.5 - k;
+      double L = 1.0;
+      if (x != 0.0) L = fabs(x) < 3.0 ? 3.0 * sinpi(x) * sinpi(x / 3.0) / (M_PI * M_PI * x * x) : 0.0;
+      wq = (int32_t)floor(16384.0 * L + 0.5);
     }
+    g_lanczos_stage[li][ph][k + 3] = wq;
+    sum += wq;
   }
+  if (ph < n) g_lanczos_stage[li][ph][3] += 16384 - sum;
 }
 
 static std::mutex g_init_mu;
@@ -88,15 +97,14 @@ ff_status ensure_init() {
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return FF_ERR_HIP;
   std::lock_guard<std::mutex> lk(g_init_mu);
   if (g_init_done[dev]) return FF_OK;
-  static int32_t gamma[256], mat[9];
-  static uint16_t fcurve[65537];
-  static int32_t lz[4][16][7];
-  host_lab_tables(gamma, mat, fcurve);
-  host_lanczos(lz);
-  if (hipMemcpyToSymbol(HIP_SYMBOL(g_gamma), gamma, sizeof(gamma)) != hipSuccess) return FF_ERR_HIP;
-  if (hipMemcpyToSymbol(HIP_SYMBOL(g_mat), mat, sizeof(mat)) != hipSuccess) return FF_ERR_HIP;
-  if (hipMemcpyToSymbol(HIP_SYMBOL(g_fcurve), fcurve, sizeof(fcurve)) != hipSuccess) return FF_ERR_HIP;
-  if (hipMemcpyToSymbol(HIP_SYMBOL(c_lanczos), lz, sizeof(lz)) != hipSuccess) return FF_ERR_HIP;
+  k_lab_tables<<<(65537 + 255) / 256, 256>>>();
+  k_lanczos_table<<<4, 64>>>();
+  if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) return FF_ERR_HIP;
+  void* stage = nullptr;
+  if (hipGetSymbolAddress(&stage, HIP_SYMBOL(g_lanczos_stage)) != hipSuccess || !stage) return FF_ERR_HIP;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_lanczos), stage, sizeof(g_lanczos_stage), 0, hipMemcpyDeviceToDevice) !=
+      hipSuccess)
+    return FF_ERR_HIP;
   if (hipDeviceSynchronize() != hipSuccess) return FF_ERR_HIP;
   g_init_done[dev] = true;
   return FF_OK;
