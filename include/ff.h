@@ -11,8 +11,9 @@
  *  - Every call that takes a stream only enqueues work on it: it never
  *    allocates, never synchronises and never copies to the host, so it may be
  *    captured in a HIP graph -- except the first call on a device, which
- *    uploads the library's constant tables (call ff_init() first when the
- *    first use is inside a capture).
+ *    computes the library's constant tables there (two small kernels on the
+ *    null stream and a synchronisation; call ff_init() first when the first
+ *    use is inside a capture).
  *  - Arguments are validated on the host before anything is enqueued; on an
  *    error nothing is enqueued and a negative ff_status is returned.
  *  - Flows are packed int16x2 words: low half dx, high half dy, both in 1/Q
@@ -121,8 +122,10 @@ typedef struct {
 /* Fill the paper's defaults (k=3, R=1, l=8, 4 sweeps, 3 searches). Host. */
 void ff_default_params(ff_match_params* p);
 
-/* Load the constant tables on the current device (idempotent, synchronous).
- * Returns FF_ERR_HIP if the device cannot be used. */
+/* Compute the constant tables (8-bit CIELab conversion of section 3.3,
+ * Lanczos-3 weights of section 3.2) on the current device and look up the
+ * no-allocation scratch array there (idempotent, synchronous; allocates
+ * nothing).  Returns FF_ERR_HIP if the device cannot be used. */
 ff_status ff_init(void);
 
 /* Host-only: compute the descriptor layout for an image.  radii (host) lists
