@@ -480,6 +480,7 @@ def main():
         line["kernels"] = kernel_table(ff, run, torch, W, H, C, img=img1)
         if args.pipeline and len(each) >= 3 * per_field:
             line["level1_sweep"] = level1_sweep(each, per_field, args.steps, W, H, args.band_rows)
+            line["level1_sweep"]["latency_floor"] = latency_floor(ff, torch, dev, line["level1_sweep"])
         line["secondary"] = secondary(ff, torch, dev, pair, skewed, args.steps)
     if batch_pairs is not None:
         line["batch"] = bench_batch(args, ff, batch_pairs, torch, dev, steps=5)
@@ -549,6 +550,36 @@ def level1_sweep(each, per_field, steps, W, H, bh):
     return {"median_ms": round(ms, 4), "wavefront_steps": wave_steps,
             "ns_per_step": round(ms * 1e6 / wave_steps, 1),
             "cycles_per_step_at_2.4GHz": round(ms * 1e-3 * CLOCK_GHZ * 1e9 / wave_steps, 0)}
+
+
+def load_round_trip_ns(ff, torch, dev, n_ints, hops=20000, reps=5):
+    """One dependent global load's round trip (ns), median of `reps` timed
+    walks of a cycle over the first word of every 128-byte line of an
+    n_ints buffer (warmed by two passes over it first)."""
+    nxt = torch.from_numpy(ff.load_cycle(n_ints)).to(dev)
+    out = torch.zeros(2, dtype=torch.int64, device=dev)
+    lines = n_ints // 32
+    res = []
+    for _ in range(reps):
+        ff.ff_probe_load_latency(nxt, 2 * lines, hops, out)
+        torch.cuda.synchronize()
+        res.append(out[0].item() * 10.0 / hops)
+    return statistics.median(res)
+
+
+def latency_floor(ff, torch, dev, sweep):
+    """The sweep's latency floor: a step's result decides the next step's
+    target addresses, so every wavefront step costs at least one dependent
+    round trip to the cache that holds the census words (L2 for a cycle of
+    1 MB, L1 for one of 16 KB, both measured here on one thread)."""
+    l1 = load_round_trip_ns(ff, torch, dev, 4096)
+    l2 = load_round_trip_ns(ff, torch, dev, 1 << 18)
+    floor_ms = sweep["wavefront_steps"] * l2 * 1e-6
+    return {"l1_round_trip_ns": round(l1, 1), "l2_round_trip_ns": round(l2, 1),
+            "l2_round_trip_cycles_at_2.4GHz": round(l2 * CLOCK_GHZ, 0),
+            "floor_ms_one_l2_round_trip_per_step": round(floor_ms, 4),
+            "floor_over_measured": round(floor_ms / sweep["median_ms"], 4),
+            "note": "the level-1 sweep's wavefront steps x one dependent L2 round trip, against its measured time"}
 
 
 def secondary(ff, torch, dev, pair, skewed, steps):

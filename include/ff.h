@@ -518,6 +518,26 @@ ff_status ff_profile_end(double* total_ms, int32_t* launches);
  * array, in the order the launches were issued) to each_ms. */
 ff_status ff_profile_end_each(double* total_ms, int32_t* launches, double* each_ms, int32_t max_each);
 
+/*
+ * Dependent-load latency probe (measurement only; not used on the search
+ * path).  A propagation sweep is a chain of wavefront steps, each step's
+ * result deciding the next step's target addresses (Eq. 2 in raster order,
+ * section 3.2), so one dependent memory round trip per step is a floor on
+ * its time.  This call measures that round trip: one wavefront follows next[]
+ * from index 0 for `warm` hops (bringing the cycle into the caches), then
+ * for `hops` more, timed with the 100 MHz real-time counter.  Every hop is
+ * one global load whose address is the previous load's value masked to
+ * [0, n), so it costs one round trip to where the cycle's lines live: the
+ * vector L1 for a cycle of a few KB, the L2 for one of a few MB.
+ * next: device, n int32 (n a power of two), filled by the caller with a
+ * cycle through index 0.  out: device, 2 int64: the timed walk's ticks
+ * (10 ns each) and the final index.  Errors (nothing enqueued): FF_ERR_ARG
+ * for null pointers, n outside [2, 2^28] or not a power of two, hops outside
+ * [1, 2^24], warm outside [0, 2^28].
+ */
+ff_status ff_probe_load_latency(const int32_t* next, int32_t n, int32_t warm, int32_t hops, int64_t* out,
+                                hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1558,3 +1558,46 @@ ff_status ff_build_kdtree(const ff_desc* d, const void* blob, int32_t radius, in
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- load-latency probe
+// One wavefront follows a cycle of indices through global memory (every
+// lane the same one): every hop is one load whose address is the previous
+// load's value, so a hop costs one dependent round trip to wherever the
+// cycle's lines live.  The sweep's step
+// is such a chain (a step's result decides the next step's target
+// addresses), so this round trip times the number of wavefront steps is the
+// floor a sweep cannot go below.
+namespace ff {
+__global__ void k_chase(const int32_t* __restrict__ next, int32_t mask, int32_t warm, int32_t hops,
+                        int64_t* __restrict__ out) {
+  const __attribute__((address_space(1))) int32_t* p = gp(next);
+  // a lane-varying start (0 in every lane of the one wavefront launched)
+  // keeps the walk in vector registers, so every hop is a vector-memory load
+  // through the vector L1 and the L2, the path of the sweep's target loads,
+  // not a scalar-cache load
+  int32_t i = (int32_t)(threadIdx.x >> 6);
+  for (int h = 0; h < warm; ++h) i = p[i] & mask;
+  // the clock is read once the warm walk's last load has returned, and again
+  // once the timed walk's has (the asm consumes the index in a register)
+  asm volatile("" ::"v"(i));
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  for (int h = 0; h < hops; ++h) i = p[i] & mask;
+  asm volatile("" ::"v"(i));
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
+  if (threadIdx.x == 0) {
+    out[0] = (int64_t)(t1 - t0);
+    out[1] = i;
+  }
+}
+}  // namespace ff
+
+extern "C" ff_status ff_probe_load_latency(const int32_t* next, int32_t n, int32_t warm, int32_t hops, int64_t* out,
+                                           hipStream_t stream) {
+  if (!next || !out || n < 2 || n > (1 << 28) || (n & (n - 1)) != 0) return FF_ERR_ARG;
+  if (hops < 1 || hops > (1 << 24) || warm < 0 || warm > (1 << 28)) return FF_ERR_ARG;
+  k_chase<<<1, 64, 0, stream>>>(next, n - 1, warm, hops, out);
+  return launch_status();
+}

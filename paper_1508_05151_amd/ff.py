@@ -99,6 +99,8 @@ def lib():
         L.ff_profile_end.restype = i32
         L.ff_profile_end_each.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int32), P, i32]
         L.ff_profile_end_each.restype = i32
+        L.ff_probe_load_latency.argtypes = [P, i32, i32, i32, P, P]
+        L.ff_probe_load_latency.restype = i32
         L.ff_consistency_filter.argtypes = [P, i32, i32, P, i32, i32, i32, i32, i32, P, P, P]
         L.ff_consistency_filter.restype = i32
         L.ff_region_filter_workspace_bytes.argtypes = [i32, i32]
@@ -375,6 +377,32 @@ def ff_profile_end(each: int = 0):
     _check(lib().ff_profile_end_each(C.byref(tot), C.byref(n), C.cast(buf, C.c_void_p) if each else None, each),
            "ff_profile_end")
     return tot.value, n.value, [buf[i] for i in range(min(each, n.value))]
+
+
+def ff_probe_load_latency(nxt, warm: int, hops: int, out, stream=None):
+    """One thread walks the cycle nxt (contiguous int32 device tensor, a
+    power-of-two length) for `warm` hops, then times `hops` more; out (int64
+    device tensor of 2) receives the timed walk's 10 ns ticks and the final
+    index."""
+    if not isinstance(nxt, torch.Tensor) or nxt.dtype != torch.int32 or not nxt.is_contiguous() or not nxt.is_cuda:
+        raise FFError(-1, "ff_probe_load_latency: expected a contiguous int32 device tensor")
+    if not isinstance(out, torch.Tensor) or out.dtype != torch.int64 or out.numel() != 2 or not out.is_cuda:
+        raise FFError(-1, "ff_probe_load_latency: out must be 2 int64 on the device")
+    _check(lib().ff_probe_load_latency(_ptr(nxt), nxt.numel(), warm, hops, _ptr(out), _stream(stream)),
+           "ff_probe_load_latency")
+
+
+def load_cycle(n_ints: int, line_ints: int = 32, seed: int = 0):
+    """A cycle through index 0 that visits the first word of every
+    `line_ints`-word line of an n_ints buffer once, in a seeded random order
+    (host NumPy array), for ff_probe_load_latency."""
+    import numpy as np
+    lines = n_ints // line_ints
+    order = np.random.default_rng(seed).permutation(lines)
+    order = np.concatenate([[0], order[order != 0]])
+    nxt = np.zeros(n_ints, dtype=np.int32)
+    nxt[order * line_ints] = np.roll(order, -1) * line_ints
+    return nxt
 
 
 def ff_read_status(workspace) -> int:

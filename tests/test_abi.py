@@ -224,3 +224,30 @@ def test_noalloc_entry_refuses_before_any_launch(ff):
     fake = C.c_void_p(0x1000)
     assert L.ff_match_field_noalloc(C.byref(ok), fake, C.byref(ok), fake, 8, C.byref(q2), None, fake, fake, None,
                                     None) == -1
+
+
+def test_load_latency_probe_validation(ff):
+    """The load-latency probe refuses bad sizes and null pointers on the host,
+    before anything is enqueued (fake device pointers are never touched)."""
+    lib = C.CDLL(ff.LIB_PATH)
+    lib.ff_probe_load_latency.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
+    lib.ff_probe_load_latency.restype = C.c_int32
+    fake = C.c_void_p(0x10000)
+    for nxt, n, warm, hops, out in [(None, 1024, 0, 10, fake), (fake, 1024, 0, 10, None), (fake, 1000, 0, 10, fake),
+                                    (fake, 1, 0, 10, fake), (fake, 1 << 29, 0, 10, fake), (fake, 1024, -1, 10, fake),
+                                    (fake, 1024, 0, 0, fake), (fake, 1024, 0, (1 << 24) + 1, fake)]:
+        assert lib.ff_probe_load_latency(nxt, n, warm, hops, out, None) == -1, (n, warm, hops)
+
+
+def test_load_cycle_visits_every_line_once(ff):
+    """The probe's cycle starts at index 0, visits the first word of every
+    128-byte line exactly once and returns to 0."""
+    import numpy as np
+    n = 1 << 14
+    nxt = ff.load_cycle(n, seed=3)
+    i, seen = 0, []
+    for _ in range(n // 32):
+        seen.append(i)
+        i = int(nxt[i])
+    assert i == 0 and sorted(seen) == list(range(0, n, 32))
+    assert np.all(nxt[np.arange(n) % 32 != 0] == 0)
