@@ -533,7 +533,8 @@ ff_status ff_profile_end_each(double* total_ms, int32_t* launches, double* each_
  * cycle through index 0.  out: device, 2 int64: the timed walk's ticks
  * (10 ns each) and the final index.  Errors (nothing enqueued): FF_ERR_ARG
  * for null pointers, n outside [2, 2^28] or not a power of two, hops outside
- * [1, 2^24], warm outside [0, 2^28].
+ * [1, 2^22], warm outside [0, 2^22] (a walk stays within a few seconds even
+ * if every hop goes to HBM).
  */
 ff_status ff_probe_load_latency(const int32_t* next, int32_t n, int32_t warm, int32_t hops, int64_t* out,
                                 hipStream_t stream);

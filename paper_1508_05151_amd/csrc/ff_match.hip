@@ -1597,7 +1597,8 @@ __global__ void k_chase(const int32_t* __restrict__ next, int32_t mask, int32_t 
 extern "C" ff_status ff_probe_load_latency(const int32_t* next, int32_t n, int32_t warm, int32_t hops, int64_t* out,
                                            hipStream_t stream) {
   if (!next || !out || n < 2 || n > (1 << 28) || (n & (n - 1)) != 0) return FF_ERR_ARG;
-  if (hops < 1 || hops > (1 << 24) || warm < 0 || warm > (1 << 28)) return FF_ERR_ARG;
+  // at most 2^22 hops per walk: a few seconds even if every hop went to HBM
+  if (hops < 1 || hops > (1 << 22) || warm < 0 || warm > (1 << 22)) return FF_ERR_ARG;
   k_chase<<<1, 64, 0, stream>>>(next, n - 1, warm, hops, out);
   return launch_status();
 }

@@ -235,7 +235,8 @@ def test_load_latency_probe_validation(ff):
     fake = C.c_void_p(0x10000)
     for nxt, n, warm, hops, out in [(None, 1024, 0, 10, fake), (fake, 1024, 0, 10, None), (fake, 1000, 0, 10, fake),
                                     (fake, 1, 0, 10, fake), (fake, 1 << 29, 0, 10, fake), (fake, 1024, -1, 10, fake),
-                                    (fake, 1024, 0, 0, fake), (fake, 1024, 0, (1 << 24) + 1, fake)]:
+                                    (fake, 1024, 0, 0, fake), (fake, 1024, 0, (1 << 22) + 1, fake),
+                                    (fake, 1024, (1 << 22) + 1, 10, fake)]:
         assert lib.ff_probe_load_latency(nxt, n, warm, hops, out, None) == -1, (n, warm, hops)
 
 
