@@ -584,8 +584,9 @@ def latency_floor(ff, torch, dev, sweep):
 
 def secondary(ff, torch, dev, pair, skewed, steps):
     """The paper's fast variant (r = 6, one backward field, section 4.2),
-    the skewed-motion recipe, and the path through the region filter and
-    the sparsification (sections 3.4, 3.5)."""
+    the benchmark step replayed from a HIP graph, the skewed-motion recipe,
+    and the path through the region filter and the sparsification (sections
+    3.4, 3.5)."""
     from synth import pairs
     H, W, C = pair.img1.shape
     res = {}
@@ -604,6 +605,26 @@ def secondary(ff, torch, dev, pair, skewed, steps):
                            "Mpixel_per_s": round(W * H / ms / 1e3, 3), "ms_per_pair": round(ms, 4),
                            "F_inlier_rate_epe_lt_3px": round(pairs.inlier_rate(out["F"].cpu().numpy(), pair, Q), 4)}
     del fast
+    # the same step captured in one HIP graph (the three field streams forked
+    # from and joined to the capturing stream) and replayed: no launch gaps
+    # between a field's dependent kernels; outputs checked against eager
+    mg = ff.PairMatcher(W, H, C, r=R, r2=R2, k=K, subpel=Q, eps=EPS)
+    out = mg.run(i1, i2, seed=pair.seed)
+    torch.cuda.synchronize()
+    eager = {k: out[k].clone() for k in ("F", "B1", "B2", "filtered")}
+    gs = torch.cuda.Stream()
+    gs.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=gs):
+        gout = mg.run(i1, i2, seed=pair.seed)
+    g.replay()
+    ms, _, _ = time_steps(g.replay, torch, steps)
+    assert all(s == 0 for s in mg.status()), mg.status()
+    same = all(torch.equal(gout[k], eager[k]) for k in eager)
+    res["graph_replay"] = {"workload": "the benchmark step captured in one HIP graph and replayed",
+                           "Mpixel_per_s": round(W * H / ms / 1e3, 3), "ms_per_pair": round(ms, 4),
+                           "equals_eager": same}
+    del g, mg
     m = ff.PairMatcher(W, H, C, r=R, r2=R2, k=K, subpel=Q, eps=EPS)
     s1, s2 = torch.from_numpy(skewed.img1).to(dev), torch.from_numpy(skewed.img2).to(dev)
     ms, out = measure(m, s1, s2, skewed)
